@@ -1,0 +1,211 @@
+/*
+ * cbt.h -- C ABI of the MI355X (gfx950) adaptive bisection update.
+ *
+ * Implements the per-frame update of "Concurrent Binary Trees for Large-Scale
+ * Game Components" (Benyoub & Dupuy, 2024): root bisectors are the halfedges
+ * of a polygon mesh (Section 2.2), every frame each live bisector is refined,
+ * decimated or kept (Section 2.3, Alg. 3-6, Table 1), and the bisectors live
+ * in a fixed pool of 2^D blocks managed by a concurrent binary tree -- a
+ * bitfield with a sum-reduction tree -- used as a memory pool (Section 3.2,
+ * Alg. 7-9) through the nine-step pipeline of Section 3.3.
+ *
+ * Conventions shared by every call
+ *  - Status: every function returns cbt_status; 0 is CBT_OK, errors are
+ *    negative.  No C++ exception crosses this boundary.  cbt_last_error()
+ *    gives a message for the last failure on a handle.
+ *  - Memory: the caller owns every array passed in.  Host arrays may be
+ *    released when the call returns.  The device workspace given to cbt_init
+ *    is owned by the caller (for instance a torch tensor), must hold
+ *    cbt_workspace_bytes(H, D) bytes, be 256-byte aligned, and outlive the
+ *    handle; the library allocates no device memory of its own.
+ *  - Streams: the hipStream_t given to cbt_init is borrowed; every device
+ *    operation of the handle is enqueued on it.  cbt_update and
+ *    cbt_update_with_decisions do not synchronise unless statistics are
+ *    requested; the query calls synchronise the stream.
+ *  - Threads: a handle is not thread-safe; use one handle per thread or lock.
+ *  - Heap IDs: root halfedge h is bisector 2^k + h with k = ceil(log2 H);
+ *    the children of bisector x are 2x and 2x+1 (Section 2.3 "Notation",
+ *    Section 3.3 "Initialization").  A bisector of depth d therefore has
+ *    2^(k+d) <= x < 2^(k+d+1); 64-bit IDs allow d <= 63 - k.
+ *  - Neighbour pointers are pool slots (-1 = border): twin across the edge
+ *    (v0,v1), next across (v1,v2), prev across (v2,v0) of the vertex triple.
+ */
+#ifndef CBT_H
+#define CBT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cbt_status;
+#define CBT_OK 0
+#define CBT_E_ARG (-1)      /* null or out-of-range argument                 */
+#define CBT_E_MESH (-2)     /* mesh fails validation (see cbt_init)           */
+#define CBT_E_DEPTH (-3)    /* D < max(5, ceil(log2 H)) or D > 30             */
+#define CBT_E_CAPACITY (-4) /* output arrays too small                        */
+#define CBT_E_DEVICE (-5)   /* HIP error or device-side check; handle failed  */
+#define CBT_E_BUDGET (-6)   /* workspace smaller than cbt_workspace_bytes     */
+#define CBT_E_STATE (-7)    /* handle failed earlier                          */
+
+typedef struct cbt_instance* cbt_handle;
+
+/* Halfedge mesh (Section 2.1).  Host arrays of length H: Twin (-1 on a
+ * border), Next, Prev and Vert (origin vertex) of every halfedge; pos holds
+ * V vertices as x,y,z floats.  Requirements checked by cbt_init: H >= 3,
+ * Next and Prev inverse permutations, every face cycle of length >= 3, Twin
+ * an involution without fixed points whose halfedges run in opposite
+ * directions and do not belong to the same corner (twin(h) is neither
+ * next(h) nor prev(h)), vertex indices in [0, V). */
+typedef struct {
+    int32_t H;
+    const int32_t* twin;
+    const int32_t* next;
+    const int32_t* prev;
+    const int32_t* vert;
+    int32_t V;
+    const float* pos;
+} cbt_mesh;
+
+/* Pinhole camera: position, forward direction, up direction (need not be
+ * orthogonal to forward), vertical field of view in radians, viewport in
+ * pixels and near-plane distance along the forward axis. */
+typedef struct {
+    float pos[3];
+    float fwd[3];
+    float up[3];
+    float fovy;
+    int32_t width;
+    int32_t height;
+    float znear;
+} cbt_camera;
+
+/* World position applied to the flat-domain vertices before the LOD test
+ * (Section 4.1: planets project vertices on a sphere and displace them;
+ * terrains displace by an elevation map). */
+enum {
+    CBT_MODE_FLAT = 0,        /* p = v                                            */
+    CBT_MODE_SPHERE = 1,      /* p = n (1 + amplitude T_cube(n)), n = v / |v|      */
+    CBT_MODE_HEIGHTFIELD = 2  /* p = v + (0, 0, amplitude T_grid(v.x, v.y))        */
+};
+
+/* LOD parameters.  A live bisector is split when the projected length of
+ * its base edge (v0,v1) exceeds split_px pixels and merged when it is below
+ * merge_px; one whose vertices all lie outside one frustum plane is merged,
+ * one whose base edge reaches behind the near plane is split (the paper's
+ * screen-space size target of Section 3.3 kernel 4 and Section 4.1).
+ * table is a DEVICE pointer (float32), caller-owned, that must stay valid
+ * while updates run: 6 * table_res^2 texels for CBT_MODE_SPHERE (faces
+ * +x,-x,+y,-y,+z,-z; texel (i,j) of a face at row j, column i) or
+ * table_res^2 for CBT_MODE_HEIGHTFIELD (texel (i,j) at x = i/(res-1),
+ * y = j/(res-1)); sampled bilinearly.  NULL for CBT_MODE_FLAT. */
+typedef struct {
+    int32_t mode;
+    float split_px;
+    float merge_px;
+    const float* table;
+    int32_t table_res;
+    float amplitude;
+} cbt_lod_params;
+
+/* Per-frame counters (filled when a non-NULL pointer is passed). */
+typedef struct {
+    int64_t live_before;      /* L, the CBT root before the frame            */
+    int64_t free_before;      /* F = 2^D - L                                  */
+    int64_t split_requests;   /* bisectors whose decision is SPLIT            */
+    int64_t split_accepted;   /* split initiators within the memory budget    */
+    int64_t merge_requests;   /* bisectors whose decision is MERGE            */
+    int64_t merge_configs;    /* unanimous merge configurations               */
+    int64_t merge_accepted;   /* configurations within the memory budget      */
+    int64_t merges_executed;  /* configurations merged                        */
+    int64_t split_consumed;   /* bisectors consumed by splits                 */
+    int64_t allocations;      /* new blocks                                   */
+    int64_t frees;            /* released blocks                              */
+    int64_t live_after;
+    int64_t max_depth;        /* 0 unless requested through cbt_query         */
+} cbt_frame_stats;
+
+/* Live bisectors in ascending slot order (two-call pattern: with capacity
+ * smaller than the live count, only count is written and CBT_E_CAPACITY is
+ * returned).  Every array pointer is a HOST pointer and may be NULL. */
+typedef struct {
+    int64_t capacity;     /* in: entries available in the per-bisector arrays */
+    int64_t count;        /* out: number of live bisectors                    */
+    int32_t* slot;        /* out: pool slot                                   */
+    uint64_t* heap_id;    /* out: heap ID                                     */
+    int32_t* twin;        /* out: neighbour slots, -1 on a border             */
+    int32_t* next;
+    int32_t* prev;
+    float* vertices;      /* out: 9 floats per bisector, flat-domain (Alg. 2)  */
+    uint32_t* tree;       /* out: full CBT heap of 2^(D+1) counters, node 0 = 0 */
+} cbt_bisectors;
+
+/* Device workspace needed for a mesh of H halfedges and a pool of 2^D
+ * blocks (0 when the arguments are invalid). */
+size_t cbt_workspace_bytes(int32_t H, int32_t D);
+
+/* Section 3.3 "Initialization": H root bisectors in the first H blocks,
+ * their neighbours copied from the halfedge operators, the first H bits
+ * set, then the sum reduction.  Validates the mesh (CBT_E_MESH), requires
+ * max(5, ceil(log2 H)) <= D <= 30 (CBT_E_DEPTH) and a large enough
+ * workspace (CBT_E_BUDGET).  Synchronises the stream before returning. */
+cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace,
+                    size_t workspace_bytes, void* hip_stream, cbt_handle* out);
+
+/* One frame of the Section 3.3 pipeline: every live bisector decides by the
+ * LOD test, splits propagate along compatibility chains (Alg. 3), merges
+ * need all members of a configuration (Alg. 4), blocks are reserved against
+ * the free count and allocated through the free bits of the CBT, neighbour
+ * pointers are rewritten (Alg. 5, Alg. 6, Table 1), the bitfield and the
+ * sum-reduction tree are updated.  Asynchronous on the handle's stream
+ * unless stats is non-NULL (then it synchronises and also reports device
+ * checks as CBT_E_DEVICE). */
+cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod,
+                      cbt_frame_stats* stats);
+
+/* Test hook: the same frame with the LOD test replaced by one decision per
+ * pool slot (0 keep, 1 split, 2 merge), read from a DEVICE array of 2^D
+ * bytes.  Roots still never merge and no split passes the index width. */
+cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisions,
+                                     cbt_frame_stats* stats);
+
+/* Copies the live bisectors (and optionally vertices and the CBT heap) to
+ * host arrays; synchronises the stream. */
+cbt_status cbt_query(cbt_handle h, cbt_bisectors* out);
+
+/* Decision codes of the last frame per slot (host array of 2^D bytes):
+ * 0 keep, 1 split, 2 merge for slots live when the frame started, 255 for
+ * the others.  Valid until the next update or query. */
+cbt_status cbt_query_decisions(cbt_handle h, uint8_t* per_slot);
+
+/* Snapshot / restore of the pool state as host arrays of 2^D entries
+ * (heap ID 0 marks a free block).  Restore rebuilds the bitfield and the
+ * sum-reduction tree from the IDs; the caller guarantees the arrays
+ * describe a conforming triangulation of this mesh (for instance a snapshot
+ * of the same instance).  Both synchronise the stream. */
+cbt_status cbt_snapshot(cbt_handle h, uint64_t* heap_id, int32_t* twin, int32_t* next,
+                        int32_t* prev);
+cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twin,
+                       const int32_t* next, const int32_t* prev);
+
+/* LOD constants the device uses for a camera, evaluated once per frame in
+ * double precision and rounded to float: cam[3] right[3] up[3] fwd[3] f^2
+ * split_px^2 merge_px^2 tan_x tan_y znear (18 floats). */
+cbt_status cbt_frame_constants(cbt_handle h, const cbt_camera* camera,
+                               const cbt_lod_params* lod, float* out18);
+
+/* Number of live bisectors (synchronises). */
+cbt_status cbt_live_count(cbt_handle h, int64_t* out);
+
+/* Releases the handle (not the workspace).  Synchronises the stream. */
+cbt_status cbt_destroy(cbt_handle h);
+
+const char* cbt_status_string(cbt_status s);
+const char* cbt_last_error(cbt_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBT_H */

@@ -1,0 +1,497 @@
+// Host side of the C ABI declared in include/cbt.h: argument and mesh
+// validation, root bisectors (Section 2.2, Alg. 1), workspace carving, frame
+// constants, and the query / snapshot paths.  All device work is done by the
+// kernels of cbt_kernels.hip on the caller's stream.
+
+#include "cbt.h"
+#include "cbt_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using cbtk::Counters;
+using cbtk::LodK;
+using cbtk::Pool;
+
+struct cbt_instance {
+    Pool P;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    int failed;
+    int last_frame_valid;   // the live list still describes the last frame
+    uint32_t last_L;
+    Counters* hctr;         // pinned host mirror of the device counters
+    char err[512];
+};
+
+static thread_local char g_err[512] = "";
+
+static cbt_status fail(cbt_handle h, cbt_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::memcpy(g_err, buf, sizeof buf);
+    if (h) std::memcpy(h->err, buf, sizeof buf);
+    return st;
+}
+
+static cbt_status hip_fail(cbt_handle h, hipError_t e, const char* what)
+{
+    if (h) h->failed = 1;
+    return fail(h, CBT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, expr, what)                        \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(h, e_, what); \
+    } while (0)
+
+static int ceil_log2(int64_t n)
+{
+    int k = 0;
+    while ((int64_t(1) << k) < n) ++k;
+    return k;
+}
+
+// Section 2.1 halfedge requirements (see cbt_mesh in cbt.h).
+static cbt_status validate_mesh(const cbt_mesh* m)
+{
+    if (!m || !m->twin || !m->next || !m->prev || !m->vert || !m->pos)
+        return fail(nullptr, CBT_E_ARG, "mesh arrays must not be NULL");
+    const int32_t H = m->H;
+    if (H < 3) return fail(nullptr, CBT_E_MESH, "mesh has %d halfedges, needs >= 3", H);
+    if (m->V < 1) return fail(nullptr, CBT_E_MESH, "mesh has no vertices");
+    for (int32_t h = 0; h < H; ++h) {
+        const int32_t n = m->next[h], p = m->prev[h], t = m->twin[h], v = m->vert[h];
+        if (n < 0 || n >= H || p < 0 || p >= H) return fail(nullptr, CBT_E_MESH, "halfedge %d: next/prev out of range", h);
+        if (m->prev[n] != h || m->next[p] != h) return fail(nullptr, CBT_E_MESH, "halfedge %d: next/prev not inverse", h);
+        if (v < 0 || v >= m->V) return fail(nullptr, CBT_E_MESH, "halfedge %d: vertex out of range", h);
+        if (t < -1 || t >= H || t == h) return fail(nullptr, CBT_E_MESH, "halfedge %d: twin out of range", h);
+        if (t >= 0) {
+            if (m->twin[t] != h) return fail(nullptr, CBT_E_MESH, "halfedge %d: twin not an involution", h);
+            if (m->vert[t] != m->vert[n] || m->vert[m->next[t]] != v)
+                return fail(nullptr, CBT_E_MESH, "halfedge %d: twin not opposite", h);
+            if (t == n || t == p) return fail(nullptr, CBT_E_MESH, "halfedge %d: twin in its own corner", h);
+        }
+    }
+    // face cycles of length >= 3 (visit each cycle once)
+    std::vector<uint8_t> seen(H, 0);
+    for (int32_t h = 0; h < H; ++h) {
+        if (seen[h]) continue;
+        int32_t len = 0, g = h;
+        do {
+            seen[g] = 1;
+            g = m->next[g];
+            if (++len > H) return fail(nullptr, CBT_E_MESH, "face of halfedge %d does not close", h);
+        } while (g != h);
+        if (len < 3) return fail(nullptr, CBT_E_MESH, "face of halfedge %d has %d sides", h, len);
+    }
+    return CBT_OK;
+}
+
+// Alg. 1 per root: v0 = Vert(h), v1 = Vert(Next(h)), v2 = mean of the face's
+// vertices.  The mean is accumulated once per face, from the face's smallest
+// halfedge index along Next, in binary32, then divided by the side count, so
+// every root of a face shares the same bits (watertight shared edges).
+static void root_triangles(const cbt_mesh* m, std::vector<float>& out)
+{
+    const int32_t H = m->H;
+    out.assign(9 * (size_t)H, 0.0f);
+    std::vector<int32_t> face_min(H, -1);
+    for (int32_t h = 0; h < H; ++h) {
+        if (face_min[h] >= 0) continue;
+        int32_t mn = h;
+        for (int32_t g = m->next[h]; g != h; g = m->next[g]) mn = g < mn ? g : mn;
+        face_min[h] = mn;
+        for (int32_t g = m->next[h]; g != h; g = m->next[g]) face_min[g] = mn;
+    }
+    std::vector<float> centroid(3 * (size_t)H, 0.0f);
+    std::vector<uint8_t> done(H, 0);
+    for (int32_t h = 0; h < H; ++h) {
+        const int32_t f = face_min[h];
+        if (done[f]) continue;
+        done[f] = 1;
+        float sx = m->pos[3 * m->vert[f] + 0], sy = m->pos[3 * m->vert[f] + 1], sz = m->pos[3 * m->vert[f] + 2];
+        int n = 1;
+        for (int32_t g = m->next[f]; g != f; g = m->next[g]) {
+            sx = sx + m->pos[3 * m->vert[g] + 0];
+            sy = sy + m->pos[3 * m->vert[g] + 1];
+            sz = sz + m->pos[3 * m->vert[g] + 2];
+            ++n;
+        }
+        centroid[3 * f + 0] = sx / (float)n;
+        centroid[3 * f + 1] = sy / (float)n;
+        centroid[3 * f + 2] = sz / (float)n;
+    }
+    for (int32_t h = 0; h < H; ++h) {
+        const float* a = m->pos + 3 * m->vert[h];
+        const float* b = m->pos + 3 * m->vert[m->next[h]];
+        const float* c = centroid.data() + 3 * face_min[h];
+        for (int i = 0; i < 3; ++i) {
+            out[9 * h + i] = a[i];
+            out[9 * h + 3 + i] = b[i];
+            out[9 * h + 6 + i] = c[i];
+        }
+    }
+}
+
+// Frame constants in double precision, each rounded once to float.
+static void make_lodk(const cbt_camera* c, const cbt_lod_params* lp, LodK* K)
+{
+    const double f[3] = {c->fwd[0], c->fwd[1], c->fwd[2]};
+    const double u[3] = {c->up[0], c->up[1], c->up[2]};
+    const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    const double fw[3] = {f[0] / fl, f[1] / fl, f[2] / fl};
+    double r[3] = {fw[1] * u[2] - fw[2] * u[1], fw[2] * u[0] - fw[0] * u[2], fw[0] * u[1] - fw[1] * u[0]};
+    const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    r[0] /= rl;
+    r[1] /= rl;
+    r[2] /= rl;
+    const double up[3] = {r[1] * fw[2] - r[2] * fw[1], r[2] * fw[0] - r[0] * fw[2], r[0] * fw[1] - r[1] * fw[0]};
+    const double th = std::tan(0.5 * (double)c->fovy);
+    const double focal = 0.5 * (double)c->height / th;
+    for (int i = 0; i < 3; ++i) {
+        K->cam[i] = c->pos[i];
+        K->right[i] = (float)r[i];
+        K->up[i] = (float)up[i];
+        K->fwd[i] = (float)fw[i];
+    }
+    K->f2 = (float)(focal * focal);
+    K->t2s = (float)((double)lp->split_px * (double)lp->split_px);
+    K->t2m = (float)((double)lp->merge_px * (double)lp->merge_px);
+    K->tx = (float)(th * (double)c->width / (double)c->height);
+    K->ty = (float)th;
+    K->znear = c->znear;
+    K->table = lp->table;
+    K->res = lp->table_res;
+    K->amp = lp->amplitude;
+    K->mode = lp->mode;
+}
+
+static cbt_status check_lod(cbt_handle h, const cbt_camera* c, const cbt_lod_params* lp)
+{
+    if (!c || !lp) return fail(h, CBT_E_ARG, "camera and LOD parameters are required");
+    if (lp->mode < CBT_MODE_FLAT || lp->mode > CBT_MODE_HEIGHTFIELD) return fail(h, CBT_E_ARG, "unknown LOD mode %d", lp->mode);
+    if (lp->mode != CBT_MODE_FLAT && (!lp->table || lp->table_res < 2))
+        return fail(h, CBT_E_ARG, "LOD mode %d needs a device table of resolution >= 2", lp->mode);
+    if (c->width <= 0 || c->height <= 0 || !(c->fovy > 0.0f && c->fovy < 3.14159f))
+        return fail(h, CBT_E_ARG, "invalid viewport or field of view");
+    return CBT_OK;
+}
+
+extern "C" {
+
+size_t cbt_workspace_bytes(int32_t H, int32_t D)
+{
+    if (H < 3 || D < 5 || D > 30 || D < ceil_log2(H)) return 0;
+    return cbtk::workspace_layout(H, D, nullptr, nullptr);
+}
+
+cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, size_t workspace_bytes,
+                    void* hip_stream, cbt_handle* out)
+{
+    if (!out) return fail(nullptr, CBT_E_ARG, "output handle pointer is NULL");
+    *out = nullptr;
+    cbt_status st = validate_mesh(mesh);
+    if (st) return st;
+    const int k = ceil_log2(mesh->H);
+    if (D < 5 || D > 30 || D < k) return fail(nullptr, CBT_E_DEPTH, "depth %d outside [max(5, ceil(log2 H)=%d), 30]", D, k);
+    const size_t need = cbtk::workspace_layout(mesh->H, D, nullptr, nullptr);
+    if (!device_workspace) return fail(nullptr, CBT_E_ARG, "device workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(device_workspace) & 255) return fail(nullptr, CBT_E_ARG, "workspace must be 256-byte aligned");
+    if (workspace_bytes < need) return fail(nullptr, CBT_E_BUDGET, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+
+    cbt_instance* h = new (std::nothrow) cbt_instance();
+    if (!h) return fail(nullptr, CBT_E_ARG, "out of host memory");
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->ws = reinterpret_cast<char*>(device_workspace);
+    h->ws_bytes = workspace_bytes;
+    cbtk::workspace_layout(mesh->H, D, &h->P, h->ws);
+    h->P.k = k;
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->hctr), sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return fail(nullptr, CBT_E_DEVICE, "pinned host allocation failed");
+    }
+    std::memset(h->hctr, 0, sizeof(Counters));
+
+    // Section 3.3 "Initialization": roots in blocks 0..H-1
+    const int32_t H = mesh->H;
+    std::vector<uint64_t> ids(H);
+    std::vector<int4> links(H);
+    for (int32_t i = 0; i < H; ++i) {
+        ids[i] = (uint64_t(1) << k) + (uint64_t)i;
+        links[i] = make_int4(mesh->twin[i], mesh->next[i], mesh->prev[i], 0);
+    }
+    std::vector<uint32_t> words((H + 31) / 32, 0u);
+    for (int32_t i = 0; i < H; ++i) words[i >> 5] |= 1u << (i & 31);
+    std::vector<float> roots;
+    root_triangles(mesh, roots);
+
+    const Pool& P = h->P;
+    hipStream_t s = h->stream;
+    cbt_status rc = CBT_OK;
+#define INIT_TRY(expr, what)                      \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) {                   \
+            rc = hip_fail(nullptr, e_, what);     \
+            goto init_fail;                       \
+        }                                         \
+    } while (0)
+    INIT_TRY(hipMemsetAsync(P.id, 0, sizeof(uint64_t) * P.cap, s), "clear IDs");
+    INIT_TRY(hipMemsetAsync(P.link, 0xff, sizeof(int4) * P.cap, s), "clear links");
+    INIT_TRY(hipMemsetAsync(P.bits, 0, sizeof(uint32_t) * P.W, s), "clear bitfield");
+    INIT_TRY(hipMemsetAsync(P.fwd, 0xff, sizeof(uint4) * P.cap, s), "clear forwarding");
+    INIT_TRY(hipMemsetAsync(P.live, 0, sizeof(uint32_t) * P.cap, s), "clear rank list");
+    INIT_TRY(hipMemsetAsync(P.freel, 0, sizeof(uint32_t) * P.cap, s), "clear free list");
+    INIT_TRY(hipMemsetAsync(P.pre, 0, sizeof(uint32_t) * P.cap, s), "clear offsets");
+    INIT_TRY(hipMemsetAsync(P.val, 0, sizeof(uint2) * P.cap, s), "clear scan values");
+    INIT_TRY(hipMemsetAsync(P.ctr, 0, sizeof(Counters), s), "clear counters");
+    INIT_TRY(hipMemcpyAsync(P.id, ids.data(), sizeof(uint64_t) * H, hipMemcpyHostToDevice, s), "upload IDs");
+    INIT_TRY(hipMemcpyAsync(P.link, links.data(), sizeof(int4) * H, hipMemcpyHostToDevice, s), "upload links");
+    INIT_TRY(hipMemcpyAsync(P.bits, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice, s), "upload bits");
+    INIT_TRY(hipMemcpyAsync(P.root, roots.data(), sizeof(float) * roots.size(), hipMemcpyHostToDevice, s), "upload roots");
+    INIT_TRY(cbtk::launch_reduce(P, s), "sum reduction");
+    INIT_TRY(hipStreamSynchronize(s), "init synchronise");
+#undef INIT_TRY
+    *out = h;
+    return CBT_OK;
+init_fail:
+    (void)hipStreamSynchronize(s);
+    (void)hipHostFree(h->hctr);
+    delete h;
+    return rc;
+}
+
+static cbt_status read_counters(cbt_handle h)
+{
+    HIP_TRY(h, hipMemcpyAsync(h->hctr, h->P.ctr, sizeof(Counters), hipMemcpyDeviceToHost, h->stream), "read counters");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    if (h->hctr->err) {
+        h->failed = 1;
+        return fail(h, CBT_E_DEVICE, "device check failed (flags 0x%x)", h->hctr->err);
+    }
+    return CBT_OK;
+}
+
+static cbt_status finish_frame(cbt_handle h, cbt_frame_stats* stats)
+{
+    h->last_frame_valid = 1;
+    if (!stats) return CBT_OK;
+    cbt_status st = read_counters(h);
+    if (st) return st;
+    const Counters& c = *h->hctr;
+    h->last_L = c.L;
+    std::memset(stats, 0, sizeof *stats);
+    stats->live_before = c.L;
+    stats->free_before = c.F;
+    stats->split_requests = c.stat[cbtk::kStSplitReq];
+    stats->split_accepted = c.stat[cbtk::kStSplitAcc];
+    stats->merge_requests = c.stat[cbtk::kStMergeReq];
+    stats->merge_configs = c.stat[cbtk::kStMergeCfg];
+    stats->merge_accepted = c.stat[cbtk::kStMergeAcc];
+    stats->merges_executed = c.stat[cbtk::kStMergeExec];
+    stats->split_consumed = c.stat[cbtk::kStSplitConsumed];
+    stats->allocations = c.N;
+    stats->frees = c.stat[cbtk::kStFrees];
+    stats->live_after = (int64_t)c.L + c.N - c.stat[cbtk::kStFrees];
+    return CBT_OK;
+}
+
+cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod, cbt_frame_stats* stats)
+{
+    if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    cbt_status st = check_lod(h, camera, lod);
+    if (st) return st;
+    LodK K;
+    make_lodk(camera, lod, &K);
+    HIP_TRY(h, cbtk::launch_frame(h->P, K, nullptr, h->stream), "frame launch");
+    return finish_frame(h, stats);
+}
+
+cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisions, cbt_frame_stats* stats)
+{
+    if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    if (!device_decisions) return fail(h, CBT_E_ARG, "decision array is NULL");
+    LodK K;
+    std::memset(&K, 0, sizeof K);
+    HIP_TRY(h, cbtk::launch_frame(h->P, K, device_decisions, h->stream), "frame launch");
+    return finish_frame(h, stats);
+}
+
+cbt_status cbt_live_count(cbt_handle h, int64_t* out)
+{
+    if (!h || !out) return fail(h, CBT_E_ARG, "NULL argument");
+    uint32_t L = 0;
+    HIP_TRY(h, hipMemcpyAsync(&L, h->P.tree + 1, sizeof L, hipMemcpyDeviceToHost, h->stream), "read root");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    *out = L;
+    return CBT_OK;
+}
+
+cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
+{
+    if (!h || !out) return fail(h, CBT_E_ARG, "NULL argument");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    const Pool& P = h->P;
+    hipStream_t s = h->stream;
+    h->last_frame_valid = 0;
+    HIP_TRY(h, cbtk::launch_enumerate(P, s), "enumerate");
+    cbt_status st = read_counters(h);
+    if (st) return st;
+    const uint32_t L = h->hctr->L;
+    out->count = L;
+    const bool per = out->slot || out->heap_id || out->twin || out->next || out->prev || out->vertices;
+    if (per && out->capacity < (int64_t)L) return fail(h, CBT_E_CAPACITY, "capacity %lld < %u live bisectors", (long long)out->capacity, L);
+    char* scratch = reinterpret_cast<char*>(P.fwd);   // 16 * cap bytes, free between frames
+    const size_t scratch_bytes = 16 * (size_t)P.cap;
+    if (out->slot && L)
+        HIP_TRY(h, hipMemcpyAsync(out->slot, P.live, sizeof(uint32_t) * L, hipMemcpyDeviceToHost, s), "copy slots");
+    if (out->heap_id && L) {
+        HIP_TRY(h, cbtk::launch_gather_ids(P, 0, L, reinterpret_cast<uint64_t*>(scratch), s), "gather IDs");
+        HIP_TRY(h, hipMemcpyAsync(out->heap_id, scratch, sizeof(uint64_t) * L, hipMemcpyDeviceToHost, s), "copy IDs");
+        HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+    }
+    if ((out->twin || out->next || out->prev) && L) {
+        std::vector<int32_t> tmp(3 * (size_t)L);
+        HIP_TRY(h, cbtk::launch_gather_links(P, 0, L, reinterpret_cast<int32_t*>(scratch), s), "gather links");
+        HIP_TRY(h, hipMemcpyAsync(tmp.data(), scratch, sizeof(int32_t) * 3 * L, hipMemcpyDeviceToHost, s), "copy links");
+        HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+        for (uint32_t i = 0; i < L; ++i) {
+            if (out->twin) out->twin[i] = tmp[3 * (size_t)i];
+            if (out->next) out->next[i] = tmp[3 * (size_t)i + 1];
+            if (out->prev) out->prev[i] = tmp[3 * (size_t)i + 2];
+        }
+    }
+    if (out->vertices && L) {
+        const uint32_t chunk = (uint32_t)(scratch_bytes / (9 * sizeof(float)));
+        for (uint32_t r0 = 0; r0 < L; r0 += chunk) {
+            const uint32_t n = (L - r0) < chunk ? (L - r0) : chunk;
+            HIP_TRY(h, cbtk::launch_gather_vertices(P, r0, n, reinterpret_cast<float*>(scratch), s), "decode vertices");
+            HIP_TRY(h, hipMemcpyAsync(out->vertices + 9 * (size_t)r0, scratch, sizeof(float) * 9 * n, hipMemcpyDeviceToHost, s),
+                    "copy vertices");
+            HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+        }
+    }
+    if (out->tree) {
+        HIP_TRY(h, cbtk::launch_export_heap(P, reinterpret_cast<uint32_t*>(scratch), s), "export tree");
+        HIP_TRY(h, hipMemcpyAsync(out->tree, scratch, sizeof(uint32_t) * 2 * (size_t)P.cap, hipMemcpyDeviceToHost, s), "copy tree");
+    }
+    HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+    return CBT_OK;
+}
+
+cbt_status cbt_query_decisions(cbt_handle h, uint8_t* per_slot)
+{
+    if (!h || !per_slot) return fail(h, CBT_E_ARG, "NULL argument");
+    if (!h->last_frame_valid) return fail(h, CBT_E_STATE, "no frame since the last query");
+    const Pool& P = h->P;
+    cbt_status st = read_counters(h);
+    if (st) return st;
+    uint8_t* scratch = reinterpret_cast<uint8_t*>(P.val);   // 8 * cap bytes
+    HIP_TRY(h, cbtk::launch_gather_decisions(P, h->hctr->L, scratch, h->stream), "gather decisions");
+    HIP_TRY(h, hipMemcpyAsync(per_slot, scratch, P.cap, hipMemcpyDeviceToHost, h->stream), "copy decisions");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    return CBT_OK;
+}
+
+cbt_status cbt_snapshot(cbt_handle h, uint64_t* heap_id, int32_t* twin, int32_t* next, int32_t* prev)
+{
+    if (!h || !heap_id || !twin || !next || !prev) return fail(h, CBT_E_ARG, "NULL argument");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    const Pool& P = h->P;
+    std::vector<int4> links(P.cap);
+    std::vector<uint32_t> words(P.W);
+    HIP_TRY(h, hipMemcpyAsync(heap_id, P.id, sizeof(uint64_t) * P.cap, hipMemcpyDeviceToHost, h->stream), "copy IDs");
+    HIP_TRY(h, hipMemcpyAsync(links.data(), P.link, sizeof(int4) * P.cap, hipMemcpyDeviceToHost, h->stream), "copy links");
+    HIP_TRY(h, hipMemcpyAsync(words.data(), P.bits, sizeof(uint32_t) * P.W, hipMemcpyDeviceToHost, h->stream), "copy bits");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    for (uint32_t i = 0; i < P.cap; ++i) {
+        const bool live = (words[i >> 5] >> (i & 31)) & 1u;
+        if (!live) heap_id[i] = 0;
+        twin[i] = live ? links[i].x : -1;
+        next[i] = live ? links[i].y : -1;
+        prev[i] = live ? links[i].z : -1;
+    }
+    return CBT_OK;
+}
+
+cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twin, const int32_t* next,
+                       const int32_t* prev)
+{
+    if (!h || !heap_id || !twin || !next || !prev) return fail(h, CBT_E_ARG, "NULL argument");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    const Pool& P = h->P;
+    std::vector<int4> links(P.cap);
+    for (uint32_t i = 0; i < P.cap; ++i) {
+        if (heap_id[i]) {
+            const int32_t t = twin[i], n = next[i], p = prev[i];
+            if (t < -1 || t >= (int64_t)P.cap || n < -1 || n >= (int64_t)P.cap || p < -1 || p >= (int64_t)P.cap)
+                return fail(h, CBT_E_ARG, "restore: pointer of slot %u out of range", i);
+            links[i] = make_int4(t, n, p, 0);
+        } else {
+            links[i] = make_int4(-1, -1, -1, 0);
+        }
+    }
+    HIP_TRY(h, hipMemcpyAsync(P.id, heap_id, sizeof(uint64_t) * P.cap, hipMemcpyHostToDevice, h->stream), "upload IDs");
+    HIP_TRY(h, hipMemcpyAsync(P.link, links.data(), sizeof(int4) * P.cap, hipMemcpyHostToDevice, h->stream), "upload links");
+    HIP_TRY(h, cbtk::launch_bits_from_ids(P, h->stream), "bitfield");
+    HIP_TRY(h, cbtk::launch_reduce(P, h->stream), "sum reduction");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    h->last_frame_valid = 0;
+    return CBT_OK;
+}
+
+cbt_status cbt_frame_constants(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod, float* out18)
+{
+    if (!out18) return fail(h, CBT_E_ARG, "NULL output");
+    cbt_lod_params lp = lod ? *lod : cbt_lod_params{CBT_MODE_FLAT, 1.0f, 1.0f, nullptr, 0, 0.0f};
+    lp.mode = CBT_MODE_FLAT;   // the table is irrelevant for the constants
+    cbt_status st = check_lod(h, camera, &lp);
+    if (st) return st;
+    LodK K;
+    make_lodk(camera, &lp, &K);
+    const float v[18] = {K.cam[0], K.cam[1], K.cam[2], K.right[0], K.right[1], K.right[2], K.up[0], K.up[1], K.up[2],
+                         K.fwd[0], K.fwd[1], K.fwd[2], K.f2, K.t2s, K.t2m, K.tx, K.ty, K.znear};
+    std::memcpy(out18, v, sizeof v);
+    return CBT_OK;
+}
+
+cbt_status cbt_destroy(cbt_handle h)
+{
+    if (!h) return CBT_OK;
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipHostFree(h->hctr);
+    delete h;
+    return CBT_OK;
+}
+
+const char* cbt_status_string(cbt_status s)
+{
+    switch (s) {
+    case CBT_OK: return "ok";
+    case CBT_E_ARG: return "invalid argument";
+    case CBT_E_MESH: return "invalid mesh";
+    case CBT_E_DEPTH: return "invalid depth";
+    case CBT_E_CAPACITY: return "output capacity too small";
+    case CBT_E_DEVICE: return "device error";
+    case CBT_E_BUDGET: return "workspace too small";
+    case CBT_E_STATE: return "handle in a failed state";
+    default: return "unknown status";
+    }
+}
+
+const char* cbt_last_error(cbt_handle h) { return h ? h->err : g_err; }
+
+}  // extern "C"

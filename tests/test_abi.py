@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every function declared in include/cbt.h, argument and mesh
+validation happen before any device access, and the workspace size follows
+the paper's memory model (Table 2, Section 4.2)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2407_02215_amd import build as hip_build
+from paper_2407_02215_amd import cbt
+from paper_2407_02215_amd import inputs as I
+from tests.helpers import read_golden, we1_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(cbt.LIB_PATH):
+        hip_build.build()
+    return cbt.load_library()
+
+
+def test_exports_every_declared_function():
+    header = open(os.path.join(ROOT, "include", "cbt.h")).read()
+    declared = set(re.findall(r"\b(cbt_[a-z_]+)\s*\(", header))
+    lib = _lib()
+    missing = [f for f in sorted(declared) if not hasattr(lib, f)]
+    assert not missing, missing
+    assert declared >= set(cbt.EXPORTED)
+
+
+def _init(mesh, D, ws_bytes, ptr=0x100000):
+    lib = _lib()
+    arrs = [np.ascontiguousarray(a, np.int32) for a in (mesh.twin, mesh.next, mesh.prev, mesh.vert)]
+    pos = np.ascontiguousarray(mesh.pos, np.float32)
+    m = cbt.Mesh(mesh.H, *(a.ctypes.data_as(C.c_void_p) for a in arrs), pos.shape[0], pos.ctypes.data_as(C.c_void_p))
+    h = C.c_void_p()
+    st = lib.cbt_init(C.byref(m), D, C.c_void_p(ptr), ws_bytes, None, C.byref(h))
+    return st, lib.cbt_last_error(None).decode()
+
+
+@pytest.mark.parametrize("bad", ["twin", "nextprev", "vert", "corner"])
+def test_invalid_mesh_rejected_before_device_access(bad):
+    m = I.mesh_cube()
+    tw, nx, pv, vt = m.twin.copy(), m.next.copy(), m.prev.copy(), m.vert.copy()
+    if bad == "twin":
+        tw[0], tw[1] = tw[1], tw[0]
+    elif bad == "nextprev":
+        pv[0] = 5
+    elif bad == "vert":
+        vt[3] = 99
+    elif bad == "corner":
+        two = I.mesh_two_triangles(False)
+        tw, nx, pv, vt = two.twin.copy(), two.next.copy(), two.prev.copy(), two.vert.copy()
+        tw[0] = 1   # twin inside its own corner, and not an involution
+        m = two
+    bm = I.HalfedgeMesh(tw, nx, pv, vt, m.edge, m.face, m.pos)
+    st, msg = _init(bm, 10, 1 << 40)
+    assert st == -2, msg
+
+
+def test_depth_and_workspace_checks():
+    mesh = we1_mesh()
+    st, msg = _init(mesh, 3, 1 << 40)
+    assert st == -3, msg                                  # D < ceil(log2 12)
+    st, msg = _init(mesh, 31, 1 << 40)
+    assert st == -3, msg
+    need = cbt.workspace_bytes(mesh.H, 8)
+    assert need > 0
+    st, msg = _init(mesh, 8, need - 1)
+    assert st == -6, msg                                  # workspace too small
+    st, msg = _init(mesh, 8, need, ptr=0x100010)
+    assert st == -1, msg                                  # misaligned workspace
+    assert cbt.workspace_bytes(2, 8) == 0 and cbt.workspace_bytes(12, 3) == 0
+
+
+def test_workspace_follows_paper_memory_model():
+    """Per pool block the paper keeps three 32-bit pointers, a 64-bit index,
+    a 32-bit command and four 32-bit allocation slots (40 bytes), plus two
+    32-bit cached decode results; at D = 17 that, with a 2^18-entry CBT, is
+    7 MiB.  This library keeps the same 40-byte record (ID; twin, next,
+    prev, command; four forwarding slots), the same 8 bytes of rank and
+    free lists, 12 bytes of scan scratch, and a bitfield plus a tree that
+    stops at the word level instead of the 2^(D+1) heap."""
+    g = read_golden("we4_memory.txt")
+    D = int(g["D"])
+    paper = (1 << D) * (3 * 4 + 8 + 4 + 4 * 4) + (1 << D) * 8 + (1 << (D + 1)) * 4
+    assert paper == int(g["total_mib"]) << 20
+    ours = cbt.workspace_bytes(60, D)
+    record_and_lists = (1 << D) * (40 + 8)
+    scan_scratch = (1 << D) * 12
+    cbt_bytes = (1 << D) // 8 + (1 << (D - 4)) * 4
+    assert ours >= record_and_lists + scan_scratch + cbt_bytes
+    assert ours <= record_and_lists + scan_scratch + cbt_bytes + 64 * 1024
+    assert cbt_bytes < (1 << (D + 1)) * 4
+
+
+def test_status_strings():
+    lib = _lib()
+    for code in range(-7, 1):
+        assert lib.cbt_status_string(code)

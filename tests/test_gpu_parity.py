@@ -1,0 +1,231 @@
+"""Parity of the HIP path (through the C ABI) with the CPU reference:
+initialisation, injected-decision frames, the paper's chain example, the
+LOD-driven workloads frame by frame, determinism and snapshot/restore.
+
+Every comparison is element by element on the same seeded inputs: heap IDs
+and neighbour slots of every pool block, the full CBT heap, the per-block
+decisions, and flat-domain vertices (bit-exact; the tolerance the vertices
+are allowed is 1e-5 relative, but both sides evaluate the same binary32
+operations in the same order)."""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (first import can be slow on a fresh box: pay it at collection)
+
+from oracle import Oracle
+from paper_2407_02215_amd import cbt
+from paper_2407_02215_amd import inputs as I
+from tests.gpu_checks import assert_same_state, assert_same_tree, check_properties, log
+from tests.helpers import decisions_for, paper_j_to_heap, we1_mesh
+
+pytestmark = pytest.mark.gpu
+
+
+def _meshes():
+    return {
+        "we1": (we1_mesh(4), 8),
+        "cube": (I.mesh_cube(), 10),
+        "ico": (I.mesh_icosahedron(), 10),
+        "open2": (I.mesh_two_triangles(False), 8),
+        "pillow": (I.mesh_two_triangles(True), 8),
+        "qsphere": (I.mesh_quad_sphere(3, 0.5, 11), 12),
+        "grid64": (I.mesh_grid(64), 16),
+    }
+
+
+def _vertices_match(inst, orc, label):
+    q = inst.query(vertices=True)
+    ov = orc.vertices()
+    gv = q["vertices"]
+    ref = ov[q["slot"]]
+    assert np.array_equal(gv.view(np.uint32), ref.view(np.uint32)), f"{label}: vertices differ"
+
+
+@pytest.mark.parametrize("name", list(_meshes()))
+def test_init_matches_reference(name):
+    mesh, D = _meshes()[name]
+    log(f"[init] {name} H={mesh.H} D={D}")
+    inst = cbt.Instance(mesh, D)
+    orc = Oracle(mesh, D)
+    assert inst.live_count() == mesh.H
+    assert_same_state(inst, orc, name)
+    assert_same_tree(inst, orc, name)
+    _vertices_match(inst, orc, name)
+    inst.close()
+
+
+@pytest.mark.parametrize("name", list(_meshes()))
+def test_injected_frames_match_reference(name):
+    mesh, D = _meshes()[name]
+    inst = cbt.Instance(mesh, D)
+    orc = Oracle(mesh, D)
+    rng = np.random.default_rng(abs(hash(name)) % 9973)
+    for f in range(14):
+        p_split = [0.5, 0.3, 0.1, 0.05][f % 4]
+        p_merge = [0.1, 0.4, 0.7, 0.9][f % 4]
+        dec = I.random_decisions(orc.cap, int(rng.integers(1 << 30)), p_split, p_merge)
+        label = f"{name} frame {f}"
+        log(f"[injected] {label} L={orc.live_count}")
+        gst = inst.update_with_decisions(dec, stats=True)
+        ost = orc.frame(decisions=dec)
+        for key in ("live_before", "split_requests", "split_accepted", "merge_requests", "merge_configs",
+                    "merge_accepted", "merges_executed", "split_consumed", "allocations", "frees", "live_after"):
+            assert gst[key] == getattr(ost, key), f"{label}: {key} gpu={gst[key]} ref={getattr(ost, key)}"
+        gdec = inst.decisions()
+        odec = orc.decisions()[0]
+        was_live = gdec != 255
+        assert was_live.sum() == ost.live_before
+        assert np.array_equal(gdec[was_live], odec[was_live]), f"{label}: decisions differ"
+        assert_same_state(inst, orc, label)
+    assert_same_tree(inst, orc, name)
+    _vertices_match(inst, orc, name)
+    inst.close()
+
+
+def test_saturated_pool_matches_reference():
+    """A pool close to full: the rank-order reservation cut decides."""
+    mesh = I.mesh_cube()
+    D = 7
+    inst = cbt.Instance(mesh, D)
+    orc = Oracle(mesh, D)
+    rng = np.random.default_rng(4)
+    rejected = 0
+    for f in range(30):
+        dec = I.random_decisions(orc.cap, int(rng.integers(1 << 30)), 0.6, 0.3)
+        log(f"[saturated] frame {f} L={orc.live_count}")
+        gst = inst.update_with_decisions(dec, stats=True)
+        ost = orc.frame(decisions=dec)
+        assert gst["split_accepted"] == ost.split_accepted
+        rejected += ost.split_requests - ost.split_accepted
+        assert_same_state(inst, orc, f"saturated frame {f}")
+    assert rejected > 0
+
+
+def test_we3_chain_example_on_gpu():
+    mesh = we1_mesh(seed=1)
+    inst = cbt.Instance(mesh, 6)
+    orc = Oracle(mesh, 6)
+    k = orc.k
+
+    def step(hids, code):
+        dec = decisions_for(orc, hids, code)
+        g = inst.update_with_decisions(dec, stats=True)
+        o = orc.frame(decisions=dec)
+        assert_same_state(inst, orc, f"we3 {hids}")
+        return g, o
+
+    step([paper_j_to_heap(7, 0, k)], I.DEC_SPLIT)
+    g, _ = step([paper_j_to_heap(14, 1, k)], I.DEC_SPLIT)
+    assert g["allocations"] == 5
+    g, _ = step([paper_j_to_heap(j, 2, k) for j in (28, 29, 46, 47)], I.DEC_MERGE)
+    assert g["merges_executed"] == 1
+    g, _ = step([paper_j_to_heap(j, 1, k) for j in (22, 23)], I.DEC_MERGE)
+    assert g["merges_executed"] == 1
+    assert_same_tree(inst, orc, "we3")
+
+
+def test_frame_constants_match_reference():
+    w = I.workload("cube")
+    inst = cbt.Instance(w.mesh, w.depth, w.lod)
+    orc = Oracle(w.mesh, w.depth, w.lod)
+    for cam in w.cameras:
+        g = inst.frame_constants(cam)
+        o = orc.frame_constants(cam)
+        assert np.array_equal(g.view(np.uint32), o.view(np.uint32))
+
+
+def _lockstep(w, frames, label, check_vertices_every=0, tree_every=1):
+    inst = cbt.Instance(w.mesh, w.depth, w.lod)
+    orc = Oracle(w.mesh, w.depth, w.lod)
+    for f, cam in enumerate(w.cameras[:frames]):
+        log(f"[lockstep] {label} frame {f} L={orc.live_count}")
+        gst = inst.update(cam, stats=True)
+        ost = orc.frame(camera=cam)
+        gdec = inst.decisions()
+        odec = orc.decisions()[0]
+        live_before = gdec != 255
+        assert live_before.sum() == ost.live_before
+        mism = np.nonzero(gdec[live_before] != odec[live_before])[0]
+        assert mism.size == 0, f"{label} frame {f}: {mism.size} decisions differ"
+        assert gst["allocations"] == ost.allocations and gst["live_after"] == ost.live_after
+        assert_same_state(inst, orc, f"{label} frame {f}")
+        if tree_every and f % tree_every == 0:
+            assert_same_tree(inst, orc, f"{label} frame {f}")
+        if check_vertices_every and f % check_vertices_every == 0:
+            _vertices_match(inst, orc, f"{label} frame {f}")
+    return inst, orc
+
+
+def test_cube_workload_lockstep():
+    w = I.workload("cube")
+    inst, orc = _lockstep(w, 8, "cube", check_vertices_every=1)
+    assert orc.live_count > 1000
+    inst.close()
+
+
+def test_planet_workload_lockstep_first_frames():
+    w = I.workload("planet", frames=256, table_res=128)
+    inst, orc = _lockstep(w, 40, "planet", check_vertices_every=13, tree_every=10)
+    assert orc.live_count > 100000
+    inst.close()
+
+
+def test_terrain_full_depth_lockstep_first_frames():
+    """Depth-24 pool (16M blocks), the launch configuration of the
+    benchmark; lock-step with the reference while the reference is fast."""
+    w = I.workload("terrain", frames=16, table_res=513)
+    inst, orc = _lockstep(w, 12, "terrain", check_vertices_every=0, tree_every=6)
+    ids, tw, nx, pv = inst.pool()
+    heap = inst.query(tree=True)["tree"]
+    check_properties(ids, tw, nx, pv, heap, orc.k, w.mesh.H, w.depth)
+    inst.close()
+
+
+def test_determinism_run_twice():
+    w = I.workload("planet", frames=24, table_res=64)
+    states = []
+    for rep in range(2):
+        inst = cbt.Instance(w.mesh, w.depth, w.lod)
+        for cam in w.cameras:
+            inst.update(cam)
+        states.append([a.copy() for a in inst.pool()])
+        inst.close()
+    for a, b in zip(*states):
+        assert np.array_equal(a, b)
+
+
+def test_snapshot_restore_continues_identically():
+    w = I.workload("cube")
+    a = cbt.Instance(w.mesh, w.depth, w.lod)
+    for cam in w.cameras[:5]:
+        a.update(cam)
+    snap = a.snapshot()
+    b = cbt.Instance(w.mesh, w.depth, w.lod)
+    b.restore(*snap)
+    for cam in w.cameras[5:]:
+        a.update(cam)
+        b.update(cam)
+    for x, y in zip(a.pool(), b.pool()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_restore_from_reference_state():
+    """A state built by the reference (a valid input to the HIP path) and
+    then advanced on both sides stays identical."""
+    mesh = I.mesh_icosahedron()
+    D = 12
+    orc = Oracle(mesh, D)
+    rng = np.random.default_rng(8)
+    for f in range(6):
+        orc.frame(decisions=I.random_decisions(orc.cap, int(rng.integers(1 << 30)), 0.4, 0.2))
+    inst = cbt.Instance(mesh, D)
+    inst.restore(*orc.pool())
+    assert_same_state(inst, orc, "restored")
+    assert_same_tree(inst, orc, "restored")
+    for f in range(4):
+        dec = I.random_decisions(orc.cap, int(rng.integers(1 << 30)), 0.3, 0.4)
+        inst.update_with_decisions(dec)
+        orc.frame(decisions=dec)
+        assert_same_state(inst, orc, f"after restore frame {f}")
+    inst.close()

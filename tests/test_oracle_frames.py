@@ -140,3 +140,30 @@ def test_cube_workload_frames():
         st = o.frame(camera=cam)
         o.check()
     assert st.live_after > 1000
+
+
+def test_property_checker_accepts_reference_states_and_rejects_corruption():
+    """The vectorised property checker used on GPU outputs accepts valid
+    states and rejects planted mistakes (on CPU arrays)."""
+    from tests.gpu_checks import check_properties
+    mesh = I.mesh_icosahedron()
+    o = Oracle(mesh, 12)
+    rng = np.random.default_rng(12)
+    for f in range(8):
+        o.frame(decisions=I.random_decisions(o.cap, int(rng.integers(1 << 30)), 0.4, 0.3))
+    ids, tw, nx, pv = o.pool()
+    heap = o.heap()
+    check_properties(ids, tw, nx, pv, heap, o.k, mesh.H, o.D)
+    s = np.nonzero(ids)[0]
+    bad = [ids.copy(), tw.copy(), nx.copy(), pv.copy(), heap.copy()]
+    bad[1][s[3]] = nx[s[3]]                 # a wrong twin pointer
+    with pytest.raises(AssertionError):
+        check_properties(*bad, o.k, mesh.H, o.D)
+    bad = [ids.copy(), tw, nx, pv, heap]
+    bad[0][s[5]] = ids[s[5]] * 2            # a bisector replaced by its child
+    with pytest.raises(AssertionError):
+        check_properties(*bad, o.k, mesh.H, o.D)
+    h2 = heap.copy()
+    h2[3] += 1
+    with pytest.raises(AssertionError):
+        check_properties(ids, tw, nx, pv, h2, o.k, mesh.H, o.D)
