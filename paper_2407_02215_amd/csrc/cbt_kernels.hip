@@ -274,7 +274,7 @@ __device__ __forceinline__ float sample_cube(const LodK& K, float x, float y, fl
 __device__ __forceinline__ V3 world(const LodK& K, V3 v)
 {
     if (K.mode == 1) {
-        const float len = __fsqrt_rn((v.x * v.x + v.y * v.y) + v.z * v.z);
+        const float len = __builtin_sqrtf((v.x * v.x + v.y * v.y) + v.z * v.z);
         const float nx = __fdiv_rn(v.x, len), ny = __fdiv_rn(v.y, len), nz = __fdiv_rn(v.z, len);
         const float h = sample_cube(K, nx, ny, nz);
         const float sc = 1.0f + K.amp * h;
