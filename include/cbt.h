@@ -196,6 +196,29 @@ cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twi
 cbt_status cbt_frame_constants(cbt_handle h, const cbt_camera* camera,
                                const cbt_lod_params* lod, float* out18);
 
+/* Stage timing with HIP events on the handle's stream.  After
+ * cbt_time_stage(h, stage), every later update records an event pair around
+ * that stage's launches (at most 8192 pairs are kept; stage 0 disables and
+ * clears).  cbt_stage_time synchronises and returns the number of timed
+ * launches and their summed duration in milliseconds. */
+enum {
+    CBT_STAGE_NONE = 0,
+    CBT_STAGE_ENUMERATE = 1,  /* live blocks in rank order                     */
+    CBT_STAGE_CLASSIFY = 2,   /* decode, LOD test, merge configuration         */
+    CBT_STAGE_VOTE = 3,       /* merge unanimity, reservation amounts          */
+    CBT_STAGE_BUDGET = 4,     /* rank-order reservation cut                    */
+    CBT_STAGE_CHAIN = 5,      /* compatibility-chain split marks               */
+    CBT_STAGE_OWNERS = 6,     /* outputs per owner                             */
+    CBT_STAGE_OFFSETS = 7,    /* allocation offsets                            */
+    CBT_STAGE_FREELIST = 8,   /* free blocks                                   */
+    CBT_STAGE_FILL = 9,       /* new heap IDs, forwarding records              */
+    CBT_STAGE_RESOLVE = 10,   /* neighbour pointers, bitfield clears           */
+    CBT_STAGE_REDUCE = 11,    /* sum-reduction tree                            */
+    CBT_STAGE_FRAME = 12      /* the whole update                              */
+};
+cbt_status cbt_time_stage(cbt_handle h, int32_t stage);
+cbt_status cbt_stage_time(cbt_handle h, int64_t* launches, double* total_ms);
+
 /* Number of live bisectors (synchronises). */
 cbt_status cbt_live_count(cbt_handle h, int64_t* out);
 

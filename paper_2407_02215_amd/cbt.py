@@ -22,7 +22,10 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "invalid mesh", -3: "invalid dept
 
 EXPORTED = ["cbt_workspace_bytes", "cbt_init", "cbt_update", "cbt_update_with_decisions", "cbt_query",
             "cbt_query_decisions", "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count",
-            "cbt_destroy", "cbt_status_string", "cbt_last_error"]
+            "cbt_destroy", "cbt_status_string", "cbt_last_error", "cbt_time_stage", "cbt_stage_time"]
+
+STAGES = {"enumerate": 1, "classify": 2, "vote": 3, "budget": 4, "chain": 5, "owners": 6, "offsets": 7,
+          "freelist": 8, "fill": 9, "resolve": 10, "reduce": 11, "frame": 12}
 
 
 class CbtError(RuntimeError):
@@ -82,12 +85,15 @@ def load_library():
     lib.cbt_frame_constants.argtypes = [vp, C.POINTER(Camera), C.POINTER(LodParams), vp]
     lib.cbt_live_count.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.cbt_destroy.argtypes = [vp]
+    lib.cbt_time_stage.argtypes = [vp, C.c_int32]
+    lib.cbt_stage_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     lib.cbt_status_string.argtypes = [C.c_int32]
     lib.cbt_status_string.restype = C.c_char_p
     lib.cbt_last_error.argtypes = [vp]
     lib.cbt_last_error.restype = C.c_char_p
     for f in ("cbt_init", "cbt_update", "cbt_update_with_decisions", "cbt_query", "cbt_query_decisions",
-              "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count", "cbt_destroy"):
+              "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count", "cbt_destroy",
+              "cbt_time_stage", "cbt_stage_time"):
         getattr(lib, f).restype = C.c_int32
     _LIB = lib
     return lib
@@ -266,6 +272,18 @@ class Instance:
         out = np.zeros(18, np.float32)
         self._check(self.lib.cbt_frame_constants(self.h, C.byref(cam), C.byref(lp), _ptr(out)))
         return out
+
+    def time_stage(self, stage):
+        """Record HIP events around one stage ('classify', ... or 'frame') in
+        later updates; None stops."""
+        self._check(self.lib.cbt_time_stage(self.h, 0 if stage is None else STAGES[stage]))
+
+    def stage_time(self):
+        """(timed launches, total milliseconds) since time_stage()."""
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(self.lib.cbt_stage_time(self.h, C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
 
     def canonical(self):
         return canonical(self.query()["heap_id"], self.k)

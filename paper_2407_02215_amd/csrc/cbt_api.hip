@@ -26,8 +26,13 @@ struct cbt_instance {
     int last_frame_valid;   // the live list still describes the last frame
     uint32_t last_L;
     Counters* hctr;         // pinned host mirror of the device counters
+    int timed_stage;        // stage wrapped by event pairs, 0 = none
+    int n_timed;            // event pairs recorded so far
+    std::vector<hipEvent_t> events;   // 2 per timed launch
     char err[512];
 };
+
+static constexpr int kMaxTimed = 8192;
 
 static thread_local char g_err[512] = "";
 
@@ -283,6 +288,29 @@ static cbt_status read_counters(cbt_handle h)
     return CBT_OK;
 }
 
+// the event pair for this update's timed stage, or NULL
+static const cbtk::StageEvents* next_events(cbt_handle h)
+{
+    thread_local cbtk::StageEvents ev;
+    if (!h->timed_stage || h->n_timed >= kMaxTimed) return nullptr;
+    const size_t i = 2 * (size_t)h->n_timed;
+    if (h->events.size() < i + 2) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return nullptr;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return nullptr;
+        }
+        h->events.push_back(a);
+        h->events.push_back(b);
+    }
+    ev.stage = h->timed_stage;
+    ev.begin = h->events[i];
+    ev.end = h->events[i + 1];
+    h->n_timed++;
+    return &ev;
+}
+
 static cbt_status finish_frame(cbt_handle h, cbt_frame_stats* stats)
 {
     h->last_frame_valid = 1;
@@ -315,7 +343,7 @@ cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_para
     if (st) return st;
     LodK K;
     make_lodk(camera, lod, &K);
-    HIP_TRY(h, cbtk::launch_frame(h->P, K, nullptr, h->stream), "frame launch");
+    HIP_TRY(h, cbtk::launch_frame(h->P, K, nullptr, h->stream, next_events(h)), "frame launch");
     return finish_frame(h, stats);
 }
 
@@ -326,8 +354,33 @@ cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisio
     if (!device_decisions) return fail(h, CBT_E_ARG, "decision array is NULL");
     LodK K;
     std::memset(&K, 0, sizeof K);
-    HIP_TRY(h, cbtk::launch_frame(h->P, K, device_decisions, h->stream), "frame launch");
+    HIP_TRY(h, cbtk::launch_frame(h->P, K, device_decisions, h->stream, next_events(h)), "frame launch");
     return finish_frame(h, stats);
+}
+
+cbt_status cbt_time_stage(cbt_handle h, int32_t stage)
+{
+    if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
+    if (stage < CBT_STAGE_NONE || stage > CBT_STAGE_FRAME) return fail(h, CBT_E_ARG, "unknown stage %d", stage);
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    h->timed_stage = stage;
+    h->n_timed = 0;
+    return CBT_OK;
+}
+
+cbt_status cbt_stage_time(cbt_handle h, int64_t* launches, double* total_ms)
+{
+    if (!h || !launches || !total_ms) return fail(h, CBT_E_ARG, "NULL argument");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    double sum = 0.0;
+    for (int i = 0; i < h->n_timed; ++i) {
+        float ms = 0.0f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, h->events[2 * (size_t)i], h->events[2 * (size_t)i + 1]), "event time");
+        sum += ms;
+    }
+    *launches = h->n_timed;
+    *total_ms = sum;
+    return CBT_OK;
 }
 
 cbt_status cbt_live_count(cbt_handle h, int64_t* out)
@@ -472,6 +525,7 @@ cbt_status cbt_destroy(cbt_handle h)
 {
     if (!h) return CBT_OK;
     (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     (void)hipHostFree(h->hctr);
     delete h;
     return CBT_OK;

@@ -9,7 +9,7 @@
 namespace cbtk {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
-constexpr int kRankGrid = 1024;   // persistent workgroups of the per-bisector kernels
+constexpr int kRankGrid = 2048;   // persistent workgroups of the per-bisector kernels (8 per CU)
 constexpr int kWordsPerBlock = 1024;  // bitfield words per workgroup (enumeration)
 constexpr int kReduceSub = 10;    // tree levels reduced inside one workgroup
 
@@ -96,7 +96,16 @@ struct LodK {
 
 size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base);
 
-hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, hipStream_t s);
+// Optional event pair recorded around the launches of one pipeline stage
+// (stage numbers of include/cbt.h).
+struct StageEvents {
+    int stage;
+    hipEvent_t begin;
+    hipEvent_t end;
+};
+
+hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, hipStream_t s,
+                        const StageEvents* ev);
 hipError_t launch_reduce(const Pool& P, hipStream_t s);
 hipError_t launch_enumerate(const Pool& P, hipStream_t s);
 hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s);

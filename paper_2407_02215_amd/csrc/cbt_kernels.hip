@@ -211,22 +211,26 @@ struct V3 {
 
 // Splitting matrices applied from the root downwards, one path bit per
 // level, most significant first: M0 -> (v0, v2, m), M1 -> (v2, v1, m).
-__device__ __forceinline__ void decode(const Pool& P, uint64_t id, int d, V3& a, V3& b, V3& c)
+// Scalar registers only (struct selects would be lowered through scratch).
+__device__ __forceinline__ void decode(const Pool& P, uint64_t id, int d, V3& A, V3& B, V3& C)
 {
     const int64_t h = (int64_t)(id >> d) - ((int64_t)1 << P.k);
     const float* r = P.root + 9 * h;
-    a = {r[0], r[1], r[2]};
-    b = {r[3], r[4], r[5]};
-    c = {r[6], r[7], r[8]};
+    float ax = r[0], ay = r[1], az = r[2];
+    float bx = r[3], by = r[4], bz = r[5];
+    float cx = r[6], cy = r[7], cz = r[8];
     for (int i = d - 1; i >= 0; --i) {
         const bool bit = (id >> i) & 1u;
-        V3 m = {(a.x + b.x) * 0.5f, (a.y + b.y) * 0.5f, (a.z + b.z) * 0.5f};
-        V3 na = bit ? c : a;
-        V3 nb = bit ? b : c;
-        a = na;
-        b = nb;
-        c = m;
+        const float mx = (ax + bx) * 0.5f, my = (ay + by) * 0.5f, mz = (az + bz) * 0.5f;
+        const float nax = bit ? cx : ax, nay = bit ? cy : ay, naz = bit ? cz : az;
+        const float nbx = bit ? bx : cx, nby = bit ? by : cy, nbz = bit ? bz : cz;
+        ax = nax; ay = nay; az = naz;
+        bx = nbx; by = nby; bz = nbz;
+        cx = mx; cy = my; cz = mz;
     }
+    A = {ax, ay, az};
+    B = {bx, by, bz};
+    C = {cx, cy, cz};
 }
 
 __device__ __forceinline__ float bilinear(const float* T, int res, float s, float t)
@@ -472,26 +476,36 @@ __global__ void __launch_bounds__(kBlock) k_vote(Pool P)
 }
 
 // exclusive saturating scan of the per-workgroup partials (one workgroup of
-// 1024 threads); mode 0: totals are the reservations, mode 1: allocations
+// 1024 threads, kRankGrid / 1024 partials each); mode 0: the totals are the
+// reservations, mode 1: the allocations
 __global__ void __launch_bounds__(1024) k_scan_parts(Pool P, int mode)
 {
+    constexpr int E = kRankGrid / 1024;
     __shared__ uint2 sh[16];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint2 v = threadIdx.x < kRankGrid ? P.part[threadIdx.x] : make_uint2(0, 0);
-    uint2 inc = wave_incl_scan_sat(v);
+    uint2 v[E];
+    uint2 loc = make_uint2(0, 0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        v[e] = P.part[threadIdx.x * E + e];
+        loc = sat_add2(loc, v[e]);
+    }
+    const uint2 inc = wave_incl_scan_sat(loc);
     if (lane == 63) sh[w] = inc;
     __syncthreads();
     uint2 pre = make_uint2(0, 0), tot = make_uint2(0, 0);
     for (int i = 0; i < 16; ++i) {
-        uint2 t = sh[i];
+        const uint2 t = sh[i];
         if (i < w) pre = sat_add2(pre, t);
         tot = sat_add2(tot, t);
     }
-    // exclusive = pre + (inclusive of the lanes before me)
-    uint32_t ex = __shfl_up(inc.x, 1, 64), ey = __shfl_up(inc.y, 1, 64);
-    uint2 excl = lane ? sat_add2(pre, make_uint2(ex, ey)) : pre;
-    __syncthreads();
-    if (threadIdx.x < kRankGrid) P.part[threadIdx.x] = excl;
+    const uint32_t ex = __shfl_up(inc.x, 1, 64), ey = __shfl_up(inc.y, 1, 64);
+    uint2 run = lane ? sat_add2(pre, make_uint2(ex, ey)) : pre;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        P.part[threadIdx.x * E + e] = run;
+        run = sat_add2(run, v[e]);
+    }
     if (threadIdx.x == 0) {
         if (mode == 0) {
             P.ctr->Tm = tot.x;
@@ -685,51 +699,15 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Pool P)
 // split outputs: roles and heap IDs
 // ---------------------------------------------------------------------------
 
-// Roles of a split bisector's outputs (forwarding record order):
+// Forwarding record of a split bisector, by role:
 //   0: first child (2x), or its first child (4x) when the Prev edge splits
 //   1: second child of the first child (4x+1), Prev edge split only
 //   2: second child (2x+1), or its first child (4x+2) when the Next edge splits
 //   3: second child of the second child (4x+3), Next edge split only
 // Outputs take their blocks in ascending heap-ID order.
-__device__ __forceinline__ int split_roles(uint32_t marks, uint64_t x, int* role, uint64_t* ids)
-{
-    const bool n = marks & kMarkN, p = marks & kMarkP;
-    int c = 0;
-    if (!n && !p) {
-        role[0] = 0; ids[0] = 2 * x;
-        role[1] = 2; ids[1] = 2 * x + 1;
-        c = 2;
-    } else if (n && !p) {
-        role[0] = 0; ids[0] = 2 * x;
-        role[1] = 2; ids[1] = 4 * x + 2;
-        role[2] = 3; ids[2] = 4 * x + 3;
-        c = 3;
-    } else if (!n && p) {
-        role[0] = 2; ids[0] = 2 * x + 1;
-        role[1] = 0; ids[1] = 4 * x;
-        role[2] = 1; ids[2] = 4 * x + 1;
-        c = 3;
-    } else {
-        role[0] = 0; ids[0] = 4 * x;
-        role[1] = 1; ids[1] = 4 * x + 1;
-        role[2] = 2; ids[2] = 4 * x + 2;
-        role[3] = 3; ids[3] = 4 * x + 3;
-        c = 4;
-    }
-    return c;
-}
-
 __device__ __forceinline__ uint32_t comp(uint4 v, int i)
 {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
-}
-
-__device__ __forceinline__ void set_comp(uint4& v, int i, uint32_t x)
-{
-    if (i == 0) v.x = x;
-    else if (i == 1) v.y = x;
-    else if (i == 2) v.z = x;
-    else v.w = x;
 }
 
 // the two sibling pairs of a merge configuration, even member first
@@ -763,16 +741,35 @@ __global__ void __launch_bounds__(kBlock) k_fill(Pool P)
         const uint32_t cmd = cmd_of(l);
         const uint32_t base = P.pre[r];
         if (cmd & kMarks) {
-            int role[4];
-            uint64_t ids[4];
-            const int c = split_roles(cmd & kMarks, P.id[s], role, ids);
-            uint4 f = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
-            for (int i = 0; i < c; ++i) {
-                if (base + i >= N) { raise_err(P, kErrAlloc); break; }
-                const uint32_t q = P.freel[base + i];
-                if (q >= P.cap) { raise_err(P, kErrAlloc); break; }
-                P.id[q] = ids[i];
-                set_comp(f, role[i], q);
+            // outputs in ascending heap-ID order take blocks base, base+1, ...
+            const bool hn = cmd & kMarkN, hp = cmd & kMarkP;
+            const uint32_t cnt = 2u + (hn ? 1u : 0u) + (hp ? 1u : 0u);
+            if (base + cnt > N) { raise_err(P, kErrAlloc); continue; }
+            const uint32_t q0 = P.freel[base], q1 = P.freel[base + 1];
+            const uint32_t q2 = cnt > 2 ? P.freel[base + 2] : 0u, q3 = cnt > 3 ? P.freel[base + 3] : 0u;
+            if (q0 >= P.cap || q1 >= P.cap || q2 >= P.cap || q3 >= P.cap) { raise_err(P, kErrAlloc); continue; }
+            const uint64_t x = P.id[s];
+            uint4 f;
+            if (!hn && !hp) {          // 2x, 2x+1
+                P.id[q0] = 2 * x;
+                P.id[q1] = 2 * x + 1;
+                f = make_uint4(q0, 0xffffffffu, q1, 0xffffffffu);
+            } else if (hn && !hp) {    // 2x, 4x+2, 4x+3
+                P.id[q0] = 2 * x;
+                P.id[q1] = 4 * x + 2;
+                P.id[q2] = 4 * x + 3;
+                f = make_uint4(q0, 0xffffffffu, q1, q2);
+            } else if (!hn && hp) {    // 2x+1, 4x, 4x+1
+                P.id[q0] = 2 * x + 1;
+                P.id[q1] = 4 * x;
+                P.id[q2] = 4 * x + 1;
+                f = make_uint4(q1, q2, q0, 0xffffffffu);
+            } else {                   // 4x, 4x+1, 4x+2, 4x+3
+                P.id[q0] = 4 * x;
+                P.id[q1] = 4 * x + 1;
+                P.id[q2] = 4 * x + 2;
+                P.id[q3] = 4 * x + 3;
+                f = make_uint4(q0, q1, q2, q3);
             }
             P.fwd[s] = f;
         } else if ((cmd & (kMExec | kMMin)) == (kMExec | kMMin)) {
@@ -1117,25 +1114,55 @@ hipError_t launch_enumerate(const Pool& P, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, hipStream_t s)
+hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, hipStream_t s,
+                        const StageEvents* ev)
 {
     const dim3 g(kRankGrid), b(kBlock);
     const dim3 gw(cdiv(P.W, kWordsPerBlock));
+    auto mark = [&](int stage, bool begin) {
+        if (ev && ev->stage == stage) (void)hipEventRecord(begin ? ev->begin : ev->end, s);
+    };
+    enum { kEnum = 1, kClass, kVote, kBudget, kChain, kOwners, kOffsets, kFree, kFill, kResolve, kReduce, kFrame };
+    mark(kFrame, true);
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, P);
+    mark(kEnum, true);
     hipLaunchKernelGGL(k_enumerate, gw, b, 0, s, P);
+    mark(kEnum, false);
+    mark(kClass, true);
     if (decisions) hipLaunchKernelGGL(k_classify<true>, g, b, 0, s, P, K, decisions);
     else hipLaunchKernelGGL(k_classify<false>, g, b, 0, s, P, K, decisions);
+    mark(kClass, false);
+    mark(kVote, true);
     hipLaunchKernelGGL(k_vote, g, b, 0, s, P);
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, P, 0);
+    mark(kVote, false);
+    mark(kBudget, true);
     hipLaunchKernelGGL(k_budget, g, b, 0, s, P);
+    mark(kBudget, false);
+    mark(kChain, true);
     hipLaunchKernelGGL(k_chain, g, b, 0, s, P);
+    mark(kChain, false);
+    mark(kOwners, true);
     hipLaunchKernelGGL(k_owners, g, b, 0, s, P);
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, P, 1);
+    mark(kOwners, false);
+    mark(kOffsets, true);
     hipLaunchKernelGGL(k_offsets, g, b, 0, s, P);
+    mark(kOffsets, false);
+    mark(kFree, true);
     hipLaunchKernelGGL(k_freelist, gw, b, 0, s, P);
+    mark(kFree, false);
+    mark(kFill, true);
     hipLaunchKernelGGL(k_fill, g, b, 0, s, P);
+    mark(kFill, false);
+    mark(kResolve, true);
     hipLaunchKernelGGL(k_resolve, g, b, 0, s, P);
-    return launch_reduce(P, s);
+    mark(kResolve, false);
+    mark(kReduce, true);
+    hipError_t e = launch_reduce(P, s);
+    mark(kReduce, false);
+    mark(kFrame, false);
+    return e;
 }
 
 hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s)
