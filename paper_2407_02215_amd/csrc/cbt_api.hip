@@ -26,6 +26,7 @@ struct cbt_instance {
     int last_frame_valid;   // the live list still describes the last frame
     uint32_t last_L;
     Counters* hctr;         // pinned host mirror of the device counters
+    LodK wk;                // world-position parameters the vertex cache holds
     int timed_stage;        // stage wrapped by event pairs, 0 = none
     int n_timed;            // event pairs recorded so far
     std::vector<hipEvent_t> events;   // 2 per timed launch
@@ -256,16 +257,21 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
     INIT_TRY(hipMemsetAsync(P.link, 0xff, sizeof(int4) * P.cap, s), "clear links");
     INIT_TRY(hipMemsetAsync(P.bits, 0, sizeof(uint32_t) * P.W, s), "clear bitfield");
     INIT_TRY(hipMemsetAsync(P.fwd, 0xff, sizeof(uint4) * P.cap, s), "clear forwarding");
+    INIT_TRY(hipMemsetAsync(P.cmd, 0, sizeof(uint32_t) * P.cap, s), "clear commands");
     INIT_TRY(hipMemsetAsync(P.live, 0, sizeof(uint32_t) * P.cap, s), "clear rank list");
     INIT_TRY(hipMemsetAsync(P.freel, 0, sizeof(uint32_t) * P.cap, s), "clear free list");
-    INIT_TRY(hipMemsetAsync(P.pre, 0, sizeof(uint32_t) * P.cap, s), "clear offsets");
-    INIT_TRY(hipMemsetAsync(P.val, 0, sizeof(uint2) * P.cap, s), "clear scan values");
+    INIT_TRY(hipMemsetAsync(P.list, 0, sizeof(uint32_t) * P.cap, s), "clear work lists");
+    INIT_TRY(hipMemsetAsync(P.lcnt, 0, sizeof(uint32_t) * cbtk::kRankGrid, s), "clear list lengths");
+    INIT_TRY(hipMemsetAsync(P.vflat, 0, sizeof(float4) * 3 * (size_t)P.cap, s), "clear vertex cache");
+    INIT_TRY(hipMemsetAsync(P.vworld, 0, sizeof(float4) * 3 * (size_t)P.cap, s), "clear vertex cache");
     INIT_TRY(hipMemsetAsync(P.ctr, 0, sizeof(Counters), s), "clear counters");
     INIT_TRY(hipMemcpyAsync(P.id, ids.data(), sizeof(uint64_t) * H, hipMemcpyHostToDevice, s), "upload IDs");
     INIT_TRY(hipMemcpyAsync(P.link, links.data(), sizeof(int4) * H, hipMemcpyHostToDevice, s), "upload links");
     INIT_TRY(hipMemcpyAsync(P.bits, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice, s), "upload bits");
     INIT_TRY(hipMemcpyAsync(P.root, roots.data(), sizeof(float) * roots.size(), hipMemcpyHostToDevice, s), "upload roots");
     INIT_TRY(cbtk::launch_reduce(P, s), "sum reduction");
+    std::memset(&h->wk, 0, sizeof h->wk);   // flat world positions until LOD parameters arrive
+    INIT_TRY(cbtk::launch_refresh(P, h->wk, 1, s), "vertex cache");
     INIT_TRY(hipStreamSynchronize(s), "init synchronise");
 #undef INIT_TRY
     *out = h;
@@ -343,6 +349,11 @@ cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_para
     if (st) return st;
     LodK K;
     make_lodk(camera, lod, &K);
+    if (K.mode != h->wk.mode || K.table != h->wk.table || K.res != h->wk.res || K.amp != h->wk.amp) {
+        // new world-position parameters: recompute the cached world positions
+        h->wk = K;
+        HIP_TRY(h, cbtk::launch_refresh(h->P, K, 0, h->stream), "vertex cache");
+    }
     HIP_TRY(h, cbtk::launch_frame(h->P, K, nullptr, h->stream, next_events(h)), "frame launch");
     return finish_frame(h, stats);
 }
@@ -352,8 +363,7 @@ cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisio
     if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
     if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
     if (!device_decisions) return fail(h, CBT_E_ARG, "decision array is NULL");
-    LodK K;
-    std::memset(&K, 0, sizeof K);
+    const LodK K = h->wk;   // new vertices keep the cached world-position parameters
     HIP_TRY(h, cbtk::launch_frame(h->P, K, device_decisions, h->stream, next_events(h)), "frame launch");
     return finish_frame(h, stats);
 }
@@ -409,6 +419,7 @@ cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
     if (per && out->capacity < (int64_t)L) return fail(h, CBT_E_CAPACITY, "capacity %lld < %u live bisectors", (long long)out->capacity, L);
     char* scratch = reinterpret_cast<char*>(P.fwd);   // 16 * cap bytes, free between frames
     const size_t scratch_bytes = 16 * (size_t)P.cap;
+    static_assert(sizeof(uint4) == 16, "forwarding record size");
     if (out->slot && L)
         HIP_TRY(h, hipMemcpyAsync(out->slot, P.live, sizeof(uint32_t) * L, hipMemcpyDeviceToHost, s), "copy slots");
     if (out->heap_id && L) {
@@ -452,7 +463,7 @@ cbt_status cbt_query_decisions(cbt_handle h, uint8_t* per_slot)
     const Pool& P = h->P;
     cbt_status st = read_counters(h);
     if (st) return st;
-    uint8_t* scratch = reinterpret_cast<uint8_t*>(P.val);   // 8 * cap bytes
+    uint8_t* scratch = reinterpret_cast<uint8_t*>(P.freel);   // 4 * cap bytes, free between frames
     HIP_TRY(h, cbtk::launch_gather_decisions(P, h->hctr->L, scratch, h->stream), "gather decisions");
     HIP_TRY(h, hipMemcpyAsync(per_slot, scratch, P.cap, hipMemcpyDeviceToHost, h->stream), "copy decisions");
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
@@ -501,6 +512,7 @@ cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twi
     HIP_TRY(h, hipMemcpyAsync(P.link, links.data(), sizeof(int4) * P.cap, hipMemcpyHostToDevice, h->stream), "upload links");
     HIP_TRY(h, cbtk::launch_bits_from_ids(P, h->stream), "bitfield");
     HIP_TRY(h, cbtk::launch_reduce(P, h->stream), "sum reduction");
+    HIP_TRY(h, cbtk::launch_refresh(P, h->wk, 1, h->stream), "vertex cache");
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
     h->last_frame_valid = 0;
     return CBT_OK;

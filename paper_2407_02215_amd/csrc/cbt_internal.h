@@ -24,7 +24,7 @@ enum : uint32_t {
     kMQuad = 1u << 3,  // the configuration is a cycle of four (else a border pair)
     kMMin = 1u << 4,   // smallest heap ID of its configuration
     kMAcc = 1u << 5,   // merge reservation accepted (on the smallest member)
-    kSAcc = 1u << 6,   // split reservation accepted (initiator)
+    kMUnan = 1u << 6,  // every member of the configuration decided MERGE
     kMExec = 1u << 7,  // configuration merges this frame (on every member)
     kMarkB = 1u << 8,  // split marks: base edge, Next edge, Prev edge
     kMarkN = 1u << 9,
@@ -69,14 +69,21 @@ struct Counters {
 // Device state of one instance, carved from the caller's workspace.
 struct Pool {
     uint64_t* id;      // [cap] heap ID per block (stale when free)
-    int4* link;        // [cap] twin, next, prev, command word
-    uint4* fwd;        // [cap] per-frame forwarding: blocks given to outputs
+    int4* link;        // [cap] twin, next, prev (block indices, -1 = border), unused
+    uint32_t* cmd;     // [cap] command word, rewritten every frame
+    uint4* fwd;        // [cap] per-frame forwarding / merge members
+    float4* vflat;     // [3 cap] flat-domain vertices (xyz, w unused)
+    float4* vworld;    // [3 cap] their world positions; w of the first holds
+                       //         the subdivision depth, of the second the
+                       //         parity of the heap ID (as integers)
     uint32_t* bits;    // [W]   occupancy bitfield, bit s&31 of word s>>5
     uint32_t* tree;    // [2^(D-4)] sum-reduction tree down to word level
     uint32_t* live;    // [cap] rank -> block, ascending
-    uint2* val;        // [cap] per-rank scan values
-    uint32_t* pre;     // [cap] per-rank exclusive allocation offsets
     uint32_t* freel;   // [cap] first N free blocks of the pre-frame bitfield
+    uint32_t* list;    // [cap] per-workgroup compacted work lists (blocks), each
+                       //       workgroup's entries from its first rank on: merge
+                       //       candidates, then accepted initiators, then owners
+    uint32_t* lcnt;    // [kRankGrid] entries in each workgroup's list
     uint2* part;       // [kRankGrid] per-workgroup partial sums
     Counters* ctr;
     float* root;       // [9H] root triangle vertices
@@ -108,6 +115,9 @@ hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, 
                         const StageEvents* ev);
 hipError_t launch_reduce(const Pool& P, hipStream_t s);
 hipError_t launch_enumerate(const Pool& P, hipStream_t s);
+// rebuild the vertex cache of every live block (flat != 0: decode the flat
+// vertices from the heap IDs first; otherwise recompute world positions)
+hipError_t launch_refresh(const Pool& P, const LodK& K, int flat, hipStream_t s);
 hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s);
 hipError_t launch_gather_ids(const Pool& P, uint32_t r0, uint32_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_gather_links(const Pool& P, uint32_t r0, uint32_t n, int32_t* out3, hipStream_t s);
@@ -116,3 +126,4 @@ hipError_t launch_gather_decisions(const Pool& P, uint32_t L, uint8_t* out_per_s
 hipError_t launch_export_heap(const Pool& P, uint32_t* out, hipStream_t s);
 
 }  // namespace cbtk
+

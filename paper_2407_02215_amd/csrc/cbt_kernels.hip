@@ -1,34 +1,47 @@
 // gfx950 kernels of the per-frame adaptive bisection update.
 //
-// One frame (Section 3.3 of the paper, nine kernels there) runs here as a
-// fixed sequence of launches on one stream, all of them persistent grids
-// bounded by device-resident counts (there is no indirect dispatch):
+// One frame (the nine-kernel pipeline of Section 3.3) runs as a fixed
+// sequence of launches on one stream.  Every launch is a persistent grid of
+// kRankGrid workgroups, each owning a contiguous chunk of ranks, bounded by
+// device-resident counts (HIP has no indirect dispatch).  Cheap passes over
+// every rank (in rank order, with workgroup scans) alternate with heavy
+// passes over compacted per-workgroup work lists, so divergent pointer work
+// runs with full wavefronts:
 //
-//   begin        L = CBT root, F = 2^D - L                   (kernel 1)
-//   enumerate    rank -> block list from the bitfield, each
-//                workgroup's base taken from the tree       (kernel 2, Alg. 7)
-//   classify     decode (Alg. 2), LOD test, merge
-//                configuration (Alg. 4); fresh command word  (kernels 3, 4)
-//   vote/scan/   merge unanimity; rank-order reservation cut:
-//   budget       merges first, then splits of 3d+4 blocks   (kernel 4)
-//   chain        split marks along compatibility chains
-//                (Alg. 3 as a closure, atomicOr on commands)  (kernel 4)
-//   owners/scan  outputs per owner, exclusive offsets        (kernel 5)
-//   freelist     first N zero bits of the pre-frame bitfield
-//                (Alg. 8 order), bits set                    (kernel 5/8)
-//   fill         heap IDs of new bisectors, forwarding table (kernel 6)
-//   resolve      neighbour pointers of every new bisector and
-//                back-pointers of untouched neighbours
-//                (Table 1, Alg. 5, Alg. 6 and compositions)  (kernel 7)
-//                consumed bits cleared                       (kernel 8)
-//   reduce       sum-reduction tree rebuilt in LDS           (kernel 9)
+//   begin      L = CBT root, F = 2^D - L                              (kernel 1)
+//   enumerate  rank -> block list; each workgroup's base comes from the
+//              tree (the prefix form of the Alg. 7 descent)          (kernel 2)
+//   classify   LOD test on the cached world positions -> command word;
+//              split reservations per workgroup; list: even members
+//              that decided MERGE                                   (kernels 3-4)
+//   vote       (list) merge configuration (Alg. 4), smallest member,
+//              unanimity; merge reservations per workgroup           (kernel 4)
+//   budget     rank-order cut: merges first, then splits of 3d+4 blocks,
+//              against F; list: accepted initiators                  (kernel 4)
+//   walk       (list) split marks along compatibility chains (Alg. 3
+//              as a closure, atomicOr)                               (kernel 4)
+//   owners     outputs per owner; list: owners                       (kernel 5)
+//   freelist   the first N zero bits of the pre-frame bitfield
+//              (ZeroToBitID order, Alg. 8), bits set                (kernels 5, 8)
+//   fill       (list) allocation offsets, new heap IDs, vertex-cache
+//              records, forwarding records                           (kernel 6)
+//   resolve    (list) pointers of every new bisector, back-pointers of
+//              untouched neighbours (Table 1, Alg. 5, Alg. 6 and
+//              compositions); consumed bits cleared                 (kernels 7-8)
+//   reduce     sum-reduction tree in LDS                             (kernel 9)
 //
-// Determinism: allocation uses scans in rank order instead of an atomic
-// counter, every pointer field has exactly one writer, and the only atomics
-// are order-free bitwise ORs/ANDs on command words and bitfield words.
+// Determinism: allocation by scans in rank order (no atomic counter), one
+// writer per pointer field, the only atomics are order-free bitwise OR/AND
+// and counter additions.
 //
-// Floating point: IEEE binary32, no contraction (built with
-// -ffp-contract=off), correctly rounded division and square root.
+// Vertex cache: every block keeps its bisector's flat-domain vertices (the
+// Alg. 2 decode) and their world positions.  Children are midpoints of the
+// parent's vertices and merged parents copy their children's vertices, so
+// the cache equals the decode bit for bit; the LOD test reads it instead of
+// decoding d levels and sampling the displacement table three times.
+//
+// Floating point: IEEE binary32, no contraction (-ffp-contract=off),
+// correctly rounded division and square root.
 
 #include "cbt_internal.h"
 
@@ -119,40 +132,44 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* sh)
     return t;
 }
 
-// rank range [r0, r1) of this workgroup: contiguous chunks of ceil(L/G)
+// ranks per workgroup of the rank-parallel kernels (contiguous chunks)
+__device__ __forceinline__ uint32_t rank_chunk(uint32_t L) { return (L + kRankGrid - 1) / kRankGrid; }
+
 __device__ __forceinline__ void rank_range(uint32_t L, uint32_t* r0, uint32_t* r1)
 {
-    uint32_t chunk = (L + gridDim.x - 1) / gridDim.x;
-    uint64_t a = (uint64_t)blockIdx.x * chunk;
-    uint64_t b = a + chunk;
+    const uint32_t chunk = rank_chunk(L);
+    const uint64_t a = (uint64_t)blockIdx.x * chunk;
+    const uint64_t b = a + chunk;
     *r0 = (uint32_t)(a < L ? a : L);
     *r1 = (uint32_t)(b < L ? b : L);
+}
+
+// Appends the flagged lanes' values to this workgroup's list (rank order
+// kept); n is the running length, updated for the whole workgroup.
+__device__ __forceinline__ void list_append(const Pool& P, uint32_t r0, uint32_t* n, bool flag, uint32_t value,
+                                            uint32_t* sh)
+{
+    uint32_t tot;
+    const uint32_t at = block_excl_scan(flag ? 1u : 0u, sh, &tot);
+    if (flag) P.list[r0 + *n + at] = value;
+    *n += tot;
 }
 
 __device__ __forceinline__ int ilog2_64(uint64_t x) { return 63 - __clzll((long long)x); }
 
 __device__ __forceinline__ void raise_err(const Pool& P, uint32_t e) { atomicOr(&P.ctr->err, e); }
 
-__device__ __forceinline__ uint32_t cmd_of(const int4& l) { return (uint32_t)l.w; }
+__device__ __forceinline__ bool slot_ok(const Pool& P, int32_t s) { return (uint32_t)s < P.cap; }
 
-__device__ __forceinline__ void store_cmd(const Pool& P, uint32_t s, uint32_t cmd)
-{
-    reinterpret_cast<int*>(&P.link[s])[3] = (int)cmd;
-}
-
-__device__ __forceinline__ uint32_t* cmd_ptr(const Pool& P, uint32_t s)
-{
-    return reinterpret_cast<uint32_t*>(&P.link[s]) + 3;
-}
+__device__ __forceinline__ int depth_of_cmd(uint32_t c) { return (int)((c & kDepthMask) >> kDepthShift); }
 
 // number of set bits in the words before word w, read off the tree
-// (the prefix-sum form of the descent of Alg. 7)
 __device__ uint32_t ones_before_word(const Pool& P, uint32_t w)
 {
     const int LW = P.D - 5;
     uint32_t node = 1, sum = 0;
     for (int l = LW - 1; l >= 0; --l) {
-        uint32_t bit = (w >> l) & 1u;
+        const uint32_t bit = (w >> l) & 1u;
         if (bit) sum += P.tree[2 * node];
         node = 2 * node + bit;
     }
@@ -166,7 +183,7 @@ __device__ uint32_t ones_before_word(const Pool& P, uint32_t w)
 __global__ void k_begin(Pool P)
 {
     if (threadIdx.x == 0) {
-        uint32_t L = P.tree[1];
+        const uint32_t L = P.tree[1];
         P.ctr->L = L;
         P.ctr->F = P.cap - L;
         P.ctr->Tm = 0;
@@ -177,12 +194,14 @@ __global__ void k_begin(Pool P)
 }
 
 // ---------------------------------------------------------------------------
-// kernel: enumerate live blocks (rank order = ascending block index)
+// kernel: enumerate live blocks (rank order = ascending block index).  Each
+// 256-word step is staged in LDS so the rank list is written coalesced.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kBlock) k_enumerate(Pool P)
 {
     __shared__ uint32_t sh[8];
+    __shared__ uint32_t stage[kBlock * 32];
     const uint32_t w0 = blockIdx.x * kWordsPerBlock;
     if (w0 >= P.W) return;
     uint32_t base = ones_before_word(P, w0);
@@ -190,24 +209,31 @@ __global__ void __launch_bounds__(kBlock) k_enumerate(Pool P)
         const uint32_t w = w0 + it + threadIdx.x;
         uint32_t word = (w < P.W) ? P.bits[w] : 0u;
         uint32_t tot;
-        uint32_t o = base + block_excl_scan(__popc(word), sh, &tot);
+        uint32_t o = block_excl_scan(__popc(word), sh, &tot);
         while (word) {
-            int j = __ffs(word) - 1;
-            if (o < P.cap) P.live[o] = w * 32u + (uint32_t)j;
-            ++o;
+            const int j = __ffs(word) - 1;
+            stage[o++] = w * 32u + (uint32_t)j;
             word &= word - 1;
         }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < tot; i += kBlock)
+            if (base + i < P.cap) P.live[base + i] = stage[i];
+        __syncthreads();
         base += tot;
     }
 }
 
 // ---------------------------------------------------------------------------
-// bisector geometry (Eq. 1 / Alg. 2) and the LOD test
+// bisector geometry (Eq. 1 / Alg. 2), world position and the LOD test
 // ---------------------------------------------------------------------------
 
 struct V3 {
     float x, y, z;
 };
+
+__device__ __forceinline__ V3 mid3(V3 a, V3 b) { return {(a.x + b.x) * 0.5f, (a.y + b.y) * 0.5f, (a.z + b.z) * 0.5f}; }
+__device__ __forceinline__ V3 ld3(const float4& v) { return {v.x, v.y, v.z}; }
+__device__ __forceinline__ float4 st3(V3 v, int w) { return make_float4(v.x, v.y, v.z, __int_as_float(w)); }
 
 // Splitting matrices applied from the root downwards, one path bit per
 // level, most significant first: M0 -> (v0, v2, m), M1 -> (v2, v1, m).
@@ -233,6 +259,12 @@ __device__ __forceinline__ void decode(const Pool& P, uint64_t id, int d, V3& A,
     C = {cx, cy, cz};
 }
 
+__device__ __forceinline__ bool valid_id(const Pool& P, uint64_t id)
+{
+    const int d = ilog2_64(id) - P.k;
+    return id != 0 && d >= 0 && d <= 63 - P.k && (int64_t)(id >> d) - ((int64_t)1 << P.k) < P.H;
+}
+
 __device__ __forceinline__ float bilinear(const float* T, int res, float s, float t)
 {
     float fs = floorf(s), ft = floorf(t);
@@ -253,6 +285,8 @@ __device__ __forceinline__ float bilinear(const float* T, int res, float s, floa
     return top + fy * (bot - top);
 }
 
+// cube-map face = axis of largest magnitude (ties x, y, z), face order
+// +x -x +y -y +z -z, (u, v) = the other two components over the major one
 __device__ __forceinline__ float sample_cube(const LodK& K, float x, float y, float z)
 {
     const float ax = fabsf(x), ay = fabsf(y), az = fabsf(z);
@@ -260,26 +294,28 @@ __device__ __forceinline__ float sample_cube(const LodK& K, float x, float y, fl
     float u, v;
     if (ax >= ay && ax >= az) {
         f = x >= 0.0f ? 0 : 1;
-        u = __fdiv_rn(y, ax);
-        v = __fdiv_rn(z, ax);
+        u = y / ax;
+        v = z / ax;
     } else if (ay >= az) {
         f = y >= 0.0f ? 2 : 3;
-        u = __fdiv_rn(x, ay);
-        v = __fdiv_rn(z, ay);
+        u = x / ay;
+        v = z / ay;
     } else {
         f = z >= 0.0f ? 4 : 5;
-        u = __fdiv_rn(x, az);
-        v = __fdiv_rn(y, az);
+        u = x / az;
+        v = y / az;
     }
     const float hr = 0.5f * (float)(K.res - 1);
     return bilinear(K.table + (size_t)f * K.res * K.res, K.res, (u + 1.0f) * hr, (v + 1.0f) * hr);
 }
 
+// world position of a flat-domain point (sphere projection + cube-map
+// displacement, or height-field displacement, or identity)
 __device__ __forceinline__ V3 world(const LodK& K, V3 v)
 {
     if (K.mode == 1) {
         const float len = __builtin_sqrtf((v.x * v.x + v.y * v.y) + v.z * v.z);
-        const float nx = __fdiv_rn(v.x, len), ny = __fdiv_rn(v.y, len), nz = __fdiv_rn(v.z, len);
+        const float nx = v.x / len, ny = v.y / len, nz = v.z / len;
         const float h = sample_cube(K, nx, ny, nz);
         const float sc = 1.0f + K.amp * h;
         return {nx * sc, ny * sc, nz * sc};
@@ -292,11 +328,11 @@ __device__ __forceinline__ V3 world(const LodK& K, V3 v)
     return v;
 }
 
-// Projected base-edge length test without division (see the host-side
-// documentation of cbt_lod_params): returns the decision code.
-__device__ __forceinline__ uint32_t lod_decide(const LodK& K, V3 a, V3 b, V3 c)
+// Projected base-edge length test without division (cbt_lod_params):
+// returns the decision code from the three world positions.
+__device__ __forceinline__ uint32_t lod_decide(const LodK& K, V3 p0, V3 p1, V3 p2)
 {
-    V3 p[3] = {world(K, a), world(K, b), world(K, c)};
+    const V3 p[3] = {p0, p1, p2};
     float vx[3], vy[3], vz[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -329,48 +365,24 @@ __device__ __forceinline__ uint32_t lod_decide(const LodK& K, V3 a, V3 b, V3 c)
     return kKeep;
 }
 
-// ---------------------------------------------------------------------------
-// merge configurations (Alg. 4)
-// ---------------------------------------------------------------------------
-
-struct Members {
-    int n;        // 0, 2 (border pair) or 4 (cycle)
-    int32_t m[4]; // j1, j2, j3, j4
-};
-
-__device__ __forceinline__ bool slot_ok(const Pool& P, int32_t s) { return (uint32_t)s < P.cap; }
-
-// Alg. 4 from bisector s (depth >= 1) on the pre-frame pointers.
-__device__ Members merge_members(const Pool& P, int32_t s, uint64_t id, int4 l1)
+// vertex-cache record of block s: flat vertices, world positions, depth and
+// heap-ID parity
+__device__ __forceinline__ void store_vertices(const Pool& P, uint32_t s, V3 a, V3 b, V3 c, V3 pa, V3 pb, V3 pc,
+                                               int depth, int parity)
 {
-    Members M;
-    M.n = 0;
-    const bool bit = id & 1u;
-    const int32_t j2 = bit ? l1.z : l1.y;
-    const int32_t j3 = bit ? l1.y : l1.z;
-    if (j2 < 0) return M;
-    if (!slot_ok(P, j2)) { raise_err(P, kErrPointer); return M; }
-    const uint64_t id2 = P.id[j2];
-    if ((id2 >> 1) != (id >> 1)) return M;
-    M.m[0] = s;
-    M.m[1] = j2;
-    if (j3 < 0) { M.n = 2; return M; }
-    if (!slot_ok(P, j3)) { raise_err(P, kErrPointer); return M; }
-    const uint64_t id3 = P.id[j3];
-    if (ilog2_64(id3) != ilog2_64(id)) return M;
-    const int4 l3 = P.link[j3];
-    const int32_t j4 = bit ? l3.y : l3.z;
-    if (j4 < 0) return M;
-    if (!slot_ok(P, j4)) { raise_err(P, kErrPointer); return M; }
-    if ((P.id[j4] >> 1) != (id3 >> 1)) return M;
-    M.m[2] = j3;
-    M.m[3] = j4;
-    M.n = 4;
-    return M;
+    float4* f = P.vflat + 3 * (size_t)s;
+    float4* w = P.vworld + 3 * (size_t)s;
+    f[0] = st3(a, 0);
+    f[1] = st3(b, 0);
+    f[2] = st3(c, 0);
+    w[0] = st3(pa, depth);
+    w[1] = st3(pb, parity);
+    w[2] = st3(pc, 0);
 }
 
 // ---------------------------------------------------------------------------
-// kernel: classify (decision + merge configuration) -> fresh command word
+// kernel: classify -> fresh command word (the vertex cache holds the world
+// positions, the depth and the parity, so no heap ID is read)
 // ---------------------------------------------------------------------------
 
 template <bool kInjected>
@@ -380,18 +392,16 @@ __global__ void __launch_bounds__(kBlock) k_classify(Pool P, LodK K, const uint8
     uint32_t r0, r1;
     rank_range(P.ctr->L, &r0, &r1);
     const int maxd = 63 - P.k;
-    uint32_t nsplit = 0, nmerge = 0;
+    uint32_t nsplit = 0, nmerge = 0, scost = 0, nlist = 0;
     for (uint32_t base = r0; base < r1; base += kBlock) {
         const uint32_t r = base + threadIdx.x;
+        bool cand = false;
+        uint32_t s = 0;
         if (r < r1) {
-            const uint32_t s = P.live[r];
-            const uint64_t id = P.id[s];
-            const int d = ilog2_64(id) - P.k;
-            if (id == 0 || d < 0 || d > maxd || (int64_t)(id >> d) - ((int64_t)1 << P.k) >= P.H) {
-                raise_err(P, kErrPointer);   // not a bisector of this mesh
-                store_cmd(P, s, kKeep);
-                continue;
-            }
+            s = P.live[r];
+            const float4* w = P.vworld + 3 * (size_t)s;
+            const float4 w0 = w[0], w1 = w[1], w2 = w[2];
+            const int d = __float_as_int(w0.w);
             uint32_t dec;
             if (kInjected) {
                 dec = inj[s];
@@ -400,78 +410,95 @@ __global__ void __launch_bounds__(kBlock) k_classify(Pool P, LodK K, const uint8
                     dec = kKeep;
                 }
             } else {
-                V3 a, b, c;
-                decode(P, id, d, a, b, c);
-                dec = lod_decide(K, a, b, c);
+                dec = lod_decide(K, ld3(w0), ld3(w1), ld3(w2));
             }
             if (dec == kMerge && d == 0) dec = kKeep;       // roots never merge
             if (dec == kSplit && d + 1 > maxd) dec = kKeep; // index width
-            uint32_t cmd = dec | ((uint32_t)d << kDepthShift);
-            if (dec == kMerge) {
-                const int4 l1 = P.link[s];
-                Members M = merge_members(P, (int32_t)s, id, l1);
-                if (M.n) {
-                    cmd |= kMCfg | (M.n == 4 ? kMQuad : 0u);
-                    bool mn = true;
-                    for (int i = 1; i < M.n; ++i) mn = mn && (id < P.id[M.m[i]]);
-                    if (mn) cmd |= kMMin;
-                }
-                ++nmerge;
+            if ((uint32_t)d > 63u) {
+                raise_err(P, kErrPointer);
+                dec = kKeep;
             }
-            if (dec == kSplit) ++nsplit;
-            store_cmd(P, s, cmd);
+            P.cmd[s] = dec | ((uint32_t)d << kDepthShift);
+            if (dec == kSplit) {
+                ++nsplit;
+                scost += 3u * (uint32_t)d + 4u;
+            } else if (dec == kMerge) {
+                ++nmerge;
+                // configurations are found from their even members (Alg. 4)
+                cand = __float_as_int(w1.w) == 0;
+            }
         }
+        list_append(P, r0, &nlist, cand, s, sh);
     }
-    uint32_t a = block_sum(nsplit, sh);
-    uint32_t b = block_sum(nmerge, sh);
+    const uint32_t a = block_sum(nsplit, sh);
+    const uint32_t b = block_sum(nmerge, sh);
+    const uint32_t c = block_sum(scost, sh);
     if (threadIdx.x == 0) {
+        P.part[blockIdx.x] = make_uint2(0, c);
+        P.lcnt[blockIdx.x] = nlist;
         if (a) atomicAdd(&P.ctr->stat[kStSplitReq], a);
         if (b) atomicAdd(&P.ctr->stat[kStMergeReq], b);
     }
 }
 
 // ---------------------------------------------------------------------------
-// kernels: merge unanimity and the reservation scan
+// kernel: merge configurations (list of even MERGE members)
 // ---------------------------------------------------------------------------
 
+// Alg. 4 seen from an even member c0 (depth >= 1): j2 = Next (its sibling),
+// j3 = Prev; a border pair when Prev is null, a cycle of four when j3 has
+// the same depth and j4 = Prev(j3) is j3's sibling.  The smallest ID of a
+// configuration is always an even member (c0 < c1), so configurations are
+// detected, once, from their even members.
+__device__ __forceinline__ int merge_config_even(const Pool& P, uint64_t id, int4 l1, int32_t* j2o, int32_t* j3o,
+                                                 int32_t* j4o)
+{
+    const int32_t j2 = l1.y, j3 = l1.z;
+    if (j2 < 0) return 0;
+    if (!slot_ok(P, j2)) { raise_err(P, kErrPointer); return 0; }
+    if ((P.id[j2] >> 1) != (id >> 1)) return 0;
+    *j2o = j2;
+    if (j3 < 0) return 2;
+    if (!slot_ok(P, j3)) { raise_err(P, kErrPointer); return 0; }
+    const uint64_t id3 = P.id[j3];
+    if (ilog2_64(id3) != ilog2_64(id)) return 0;
+    const int32_t j4 = P.link[j3].z;
+    if (j4 < 0) return 0;
+    if (!slot_ok(P, j4)) { raise_err(P, kErrPointer); return 0; }
+    if ((P.id[j4] >> 1) != (id3 >> 1)) return 0;
+    *j3o = j3;
+    *j4o = j4;
+    return 4;
+}
+
+// A configuration merges only if every member decided MERGE (unanimity);
+// its reservation, one block per parent, is charged to the smallest member.
 __global__ void __launch_bounds__(kBlock) k_vote(Pool P)
 {
-    __shared__ uint2 sh2[8];
     __shared__ uint32_t sh[8];
     uint32_t r0, r1;
     rank_range(P.ctr->L, &r0, &r1);
-    uint2 acc = make_uint2(0, 0);
-    uint32_t ncfg = 0;
-    for (uint32_t base = r0; base < r1; base += kBlock) {
-        const uint32_t r = base + threadIdx.x;
-        uint2 v = make_uint2(0, 0);
-        if (r < r1) {
-            const uint32_t s = P.live[r];
-            const int4 l = P.link[s];
-            const uint32_t cmd = cmd_of(l);
-            if ((cmd & kDecMask) == kSplit) v.y = 3u * ((cmd & kDepthMask) >> kDepthShift) + 4u;
-            if ((cmd & (kMCfg | kMMin)) == (kMCfg | kMMin)) {
-                Members M = merge_members(P, (int32_t)s, P.id[s], l);
-                bool ok = M.n == ((cmd & kMQuad) ? 4 : 2);
-                for (int i = 1; i < M.n && ok; ++i) {
-                    const uint32_t c = *cmd_ptr(P, (uint32_t)M.m[i]);
-                    ok = (c & (kDecMask | kMCfg | kMQuad)) == (kMerge | kMCfg | (cmd & kMQuad));
-                }
-                if (ok) {
-                    v.x = (uint32_t)(M.n / 2);
-                    ++ncfg;
-                }
-            }
-            P.val[r] = v;
-        }
-        uint2 tot;
-        (void)block_incl_scan_sat(v, sh2, &tot);
-        acc = sat_add2(acc, tot);
+    const uint32_t n = P.lcnt[blockIdx.x];
+    uint32_t ncfg = 0, res = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+        const uint32_t s = P.list[r0 + i];
+        const uint64_t id = P.id[s];
+        int32_t j2 = -1, j3 = -1, j4 = -1;
+        const int m = merge_config_even(P, id, P.link[s], &j2, &j3, &j4);
+        if (!m || (m == 4 && P.id[j4] < id)) continue;   // not the smallest member
+        bool ok = (P.cmd[j2] & kDecMask) == kMerge;
+        if (m == 4) ok = ok && (P.cmd[j3] & kDecMask) == kMerge && (P.cmd[j4] & kDecMask) == kMerge;
+        if (!ok) continue;
+        P.cmd[s] |= kMCfg | kMMin | kMUnan | (m == 4 ? kMQuad : 0u);
+        P.fwd[s] = make_uint4((uint32_t)j2, (uint32_t)j3, (uint32_t)j4, (uint32_t)m);
+        res += (uint32_t)m / 2;
+        ++ncfg;
     }
-    uint32_t c = block_sum(ncfg, sh);
+    const uint32_t t = block_sum(res, sh);
+    const uint32_t u = block_sum(ncfg, sh);
     if (threadIdx.x == 0) {
-        P.part[blockIdx.x] = acc;
-        if (c) atomicAdd(&P.ctr->stat[kStMergeCfg], c);
+        P.part[blockIdx.x].x = t;
+        if (u) atomicAdd(&P.ctr->stat[kStMergeCfg], u);
     }
 }
 
@@ -517,9 +544,14 @@ __global__ void __launch_bounds__(1024) k_scan_parts(Pool P, int mode)
     }
 }
 
-// Rank-order cut: merge reservation r accepted when the inclusive merge
-// prefix fits in F; split reservation r when all merge reservations plus
-// the inclusive split prefix fit in F.
+// ---------------------------------------------------------------------------
+// kernel: reservation cut
+// ---------------------------------------------------------------------------
+
+// Rank-order cut: the merge reservation of rank r is accepted when the
+// inclusive merge prefix fits in F; the split reservation (3d + 4) when all
+// merge reservations plus the inclusive split prefix fit in F.  Accepted
+// initiators are listed for the chain walk.
 __global__ void __launch_bounds__(kBlock) k_budget(Pool P)
 {
     __shared__ uint2 sh2[8];
@@ -528,72 +560,79 @@ __global__ void __launch_bounds__(kBlock) k_budget(Pool P)
     rank_range(P.ctr->L, &r0, &r1);
     const uint32_t F = P.ctr->F, Tm = P.ctr->Tm;
     uint2 carry = P.part[blockIdx.x];
-    uint32_t nm = 0, ns = 0;
+    uint32_t nm = 0, nlist = 0;
     for (uint32_t base = r0; base < r1; base += kBlock) {
         const uint32_t r = base + threadIdx.x;
-        const uint2 v = r < r1 ? P.val[r] : make_uint2(0, 0);
+        uint2 v = make_uint2(0, 0);
+        uint32_t s = 0, c = 0;
+        if (r < r1) {
+            s = P.live[r];
+            c = P.cmd[s];
+            if (c & kMUnan) v.x = (c & kMQuad) ? 2u : 1u;
+            if ((c & kDecMask) == kSplit) v.y = 3u * (uint32_t)depth_of_cmd(c) + 4u;
+        }
         uint2 tot;
         const uint2 inc = sat_add2(carry, block_incl_scan_sat(v, sh2, &tot));
-        if (r < r1 && (v.x | v.y)) {
-            const uint32_t s = P.live[r];
-            uint32_t add = 0;
-            if (v.x && inc.x <= F) { add |= kMAcc; ++nm; }
-            if (v.y && sat_add(Tm, inc.y) <= F) { add |= kSAcc; ++ns; }
-            if (add) store_cmd(P, s, *cmd_ptr(P, s) | add);
+        if (v.x && inc.x <= F) {
+            P.cmd[s] = c | kMAcc;
+            ++nm;
         }
+        list_append(P, r0, &nlist, v.y && sat_add(Tm, inc.y) <= F, s, sh);
         carry = sat_add2(carry, tot);
     }
-    uint32_t a = block_sum(nm, sh);
-    uint32_t b = block_sum(ns, sh);
+    const uint32_t a = block_sum(nm, sh);
     if (threadIdx.x == 0) {
+        P.lcnt[blockIdx.x] = nlist;
         if (a) atomicAdd(&P.ctr->stat[kStMergeAcc], a);
-        if (b) atomicAdd(&P.ctr->stat[kStSplitAcc], b);
+        if (nlist) atomicAdd(&P.ctr->stat[kStSplitAcc], nlist);
     }
 }
 
 // ---------------------------------------------------------------------------
-// kernel: compatibility chains (Alg. 3) as split marks
+// kernel: compatibility chains (list of accepted initiators)
 // ---------------------------------------------------------------------------
 
 // Walk from an accepted initiator through Twin: a same-level twin pair ends
 // the chain; a coarser twin receives the mark of the edge it shares (Next or
 // Prev) plus its own base mark and the walk continues from it.  A walk stops
-// as soon as it finds a base mark already set: whoever set it walks (or
-// walked) the same remaining chain, which depends on pre-frame pointers only.
-__global__ void __launch_bounds__(kBlock) k_chain(Pool P)
+// at a base mark already set: whoever set it walks (or walked) the same
+// remaining chain, which depends on pre-frame pointers only.
+__device__ void walk_chain(const Pool& P, uint32_t s)
+{
+    uint32_t old = atomicOr(&P.cmd[s], kMarkB);
+    if (old & kMarkB) return;
+    int32_t cur = (int32_t)s;
+    for (int it = 0; it < 130; ++it) {
+        const int32_t n = P.link[cur].x;
+        if (n < 0) return;
+        if (!slot_ok(P, n)) { raise_err(P, kErrPointer); return; }
+        const int4 ln = P.link[n];
+        if (ln.x == cur) {
+            atomicOr(&P.cmd[n], kMarkB);
+            return;
+        }
+        uint32_t e;
+        if (ln.y == cur) e = kMarkN;
+        else if (ln.z == cur) e = kMarkP;
+        else { raise_err(P, kErrPointer); return; }
+        old = atomicOr(&P.cmd[n], e | kMarkB);
+        if (old & kMarkB) return;
+        cur = n;
+    }
+    raise_err(P, kErrChain);
+}
+
+__global__ void __launch_bounds__(kBlock) k_walk(Pool P)
 {
     uint32_t r0, r1;
     rank_range(P.ctr->L, &r0, &r1);
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-        const uint32_t s = P.live[r];
-        if (!(*cmd_ptr(P, s) & kSAcc)) continue;
-        uint32_t old = atomicOr(cmd_ptr(P, s), kMarkB);
-        if (old & kMarkB) continue;
-        int32_t cur = (int32_t)s;
-        int it = 0;
-        for (; it < 130; ++it) {
-            const int32_t n = P.link[cur].x;
-            if (n < 0) break;
-            if (!slot_ok(P, n)) { raise_err(P, kErrPointer); break; }
-            const int4 ln = P.link[n];
-            if (ln.x == cur) {
-                atomicOr(cmd_ptr(P, (uint32_t)n), kMarkB);
-                break;
-            }
-            uint32_t e;
-            if (ln.y == cur) e = kMarkN;
-            else if (ln.z == cur) e = kMarkP;
-            else { raise_err(P, kErrPointer); break; }
-            old = atomicOr(cmd_ptr(P, (uint32_t)n), e | kMarkB);
-            if (old & kMarkB) break;
-            cur = n;
-        }
-        if (it >= 130) raise_err(P, kErrChain);
-    }
+    const uint32_t n = P.lcnt[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) walk_chain(P, P.list[r0 + i]);
 }
 
 // ---------------------------------------------------------------------------
-// kernels: owners and their allocation offsets
+// kernel: owners (split-marked bisectors, executing merges), their output
+// counts per workgroup, and the owner list
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint32_t split_outputs(uint32_t cmd)
@@ -606,70 +645,57 @@ __global__ void __launch_bounds__(kBlock) k_owners(Pool P)
     __shared__ uint32_t sh[8];
     uint32_t r0, r1;
     rank_range(P.ctr->L, &r0, &r1);
-    uint32_t acc = 0, nexec = 0, nsc = 0, nfree = 0;
+    uint32_t acc = 0, nexec = 0, nsc = 0, nfree = 0, nlist = 0;
     for (uint32_t base = r0; base < r1; base += kBlock) {
         const uint32_t r = base + threadIdx.x;
-        uint32_t n = 0;
+        uint32_t s = 0;
+        bool owner = false;
         if (r < r1) {
-            const uint32_t s = P.live[r];
-            const int4 l = P.link[s];
-            const uint32_t cmd = cmd_of(l);
-            if (cmd & kMarks) {
-                n = split_outputs(cmd);
+            s = P.live[r];
+            const uint32_t c = P.cmd[s];
+            if (c & kMarks) {
+                acc += split_outputs(c);
                 ++nsc;
                 ++nfree;
-            } else if (cmd & kMAcc) {
-                Members M = merge_members(P, (int32_t)s, P.id[s], l);
-                bool clean = M.n > 0;
-                for (int i = 0; i < M.n; ++i) clean = clean && !(*cmd_ptr(P, (uint32_t)M.m[i]) & kMarks);
+                owner = true;
+            } else if (c & kMAcc) {
+                // splits win: a configuration with a split-marked member stays
+                const uint4 m = P.fwd[s];
+                bool clean = !(P.cmd[m.x] & kMarks);
+                if (m.w == 4) clean = clean && !(P.cmd[m.y] & kMarks) && !(P.cmd[m.z] & kMarks);
                 if (clean) {
-                    n = (uint32_t)(M.n / 2);
-                    for (int i = 0; i < M.n; ++i) atomicOr(cmd_ptr(P, (uint32_t)M.m[i]), kMExec);
+                    P.cmd[s] = c | kMExec;
+                    acc += m.w / 2;
                     ++nexec;
-                    nfree += (uint32_t)M.n;
+                    nfree += m.w;
+                    owner = true;
                 }
             }
-            P.val[r].x = n;
         }
-        uint32_t tot;
-        (void)block_excl_scan(n, sh, &tot);
-        acc += tot;
+        list_append(P, r0, &nlist, owner, s, sh);
     }
+    const uint32_t t = block_sum(acc, sh);
     const uint32_t a = block_sum(nexec, sh);
     const uint32_t b = block_sum(nsc, sh);
     const uint32_t c = block_sum(nfree, sh);
     if (threadIdx.x == 0) {
-        P.part[blockIdx.x] = make_uint2(acc, 0);
+        P.part[blockIdx.x] = make_uint2(t, 0);
+        P.lcnt[blockIdx.x] = nlist;
         if (a) atomicAdd(&P.ctr->stat[kStMergeExec], a);
         if (b) atomicAdd(&P.ctr->stat[kStSplitConsumed], b);
         if (c) atomicAdd(&P.ctr->stat[kStFrees], c);
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_offsets(Pool P)
-{
-    __shared__ uint32_t sh[8];
-    uint32_t r0, r1;
-    rank_range(P.ctr->L, &r0, &r1);
-    uint32_t carry = P.part[blockIdx.x].x;
-    for (uint32_t base = r0; base < r1; base += kBlock) {
-        const uint32_t r = base + threadIdx.x;
-        const uint32_t n = r < r1 ? P.val[r].x : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(n, sh, &tot);
-        if (r < r1) P.pre[r] = carry + ex;
-        carry += tot;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // kernel: the first N free blocks (ZeroToBitID(0..N-1) of the pre-frame
-// tree, Alg. 8), marked occupied
+// tree, Alg. 8), marked occupied; staged in LDS for coalesced writes
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kBlock) k_freelist(Pool P)
 {
     __shared__ uint32_t sh[8];
+    __shared__ uint32_t stage[kBlock * 32];
     const uint32_t N = P.ctr->N;
     const uint32_t w0 = blockIdx.x * kWordsPerBlock;
     if (w0 >= P.W || N == 0) return;
@@ -679,24 +705,30 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Pool P)
         const uint32_t w = w0 + it + threadIdx.x;
         const uint32_t word = (w < P.W) ? P.bits[w] : 0xffffffffu;
         uint32_t tot;
-        uint32_t o = zb + block_excl_scan(__popc(~word), sh, &tot);
-        if (w < P.W && o < N) {
+        uint32_t o = block_excl_scan(__popc(~word), sh, &tot);
+        if (w < P.W && zb + o < N) {
             uint32_t inv = ~word, nw = word;
-            while (inv && o < N) {
+            while (inv && zb + o < N) {
                 const int j = __ffs(inv) - 1;
-                P.freel[o++] = w * 32u + (uint32_t)j;
+                stage[o++] = w * 32u + (uint32_t)j;
                 nw |= 1u << j;
                 inv &= inv - 1;
             }
             P.bits[w] = nw;
         }
+        __syncthreads();
+        const uint32_t take = (N - zb) < tot ? (N - zb) : tot;
+        for (uint32_t i = threadIdx.x; i < take; i += kBlock) P.freel[zb + i] = stage[i];
+        __syncthreads();
         zb += tot;
         if (zb >= N) break;
     }
 }
 
 // ---------------------------------------------------------------------------
-// split outputs: roles and heap IDs
+// kernel: fill (owner list) -- allocation offsets (exclusive scan of the
+// output counts in rank order), new heap IDs, vertex-cache records and the
+// forwarding records of consumed bisectors
 // ---------------------------------------------------------------------------
 
 // Forwarding record of a split bisector, by role:
@@ -704,100 +736,134 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Pool P)
 //   1: second child of the first child (4x+1), Prev edge split only
 //   2: second child (2x+1), or its first child (4x+2) when the Next edge splits
 //   3: second child of the second child (4x+3), Next edge split only
-// Outputs take their blocks in ascending heap-ID order.
-__device__ __forceinline__ uint32_t comp(uint4 v, int i)
+// Outputs take their blocks in ascending heap-ID order.  A merged member's
+// record holds its parent's block first; the owner's record also keeps the
+// other members (second, third, fourth fields) for the pointer pass.
+
+__device__ __forceinline__ void fill_split(const Pool& P, uint32_t s, uint32_t c, uint32_t base, uint32_t N,
+                                           const LodK& K)
 {
-    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+    const bool hn = c & kMarkN, hp = c & kMarkP;
+    const uint32_t cnt = 2u + (hn ? 1u : 0u) + (hp ? 1u : 0u);
+    if (base + cnt > N) { raise_err(P, kErrAlloc); return; }
+    const uint32_t q0 = P.freel[base], q1 = P.freel[base + 1];
+    const uint32_t q2 = cnt > 2 ? P.freel[base + 2] : 0u, q3 = cnt > 3 ? P.freel[base + 3] : 0u;
+    if (q0 >= P.cap || q1 >= P.cap || q2 >= P.cap || q3 >= P.cap) { raise_err(P, kErrAlloc); return; }
+    const uint64_t x = P.id[s];
+    const int d = depth_of_cmd(c);
+    const float4* fv = P.vflat + 3 * (size_t)s;
+    const float4* wv = P.vworld + 3 * (size_t)s;
+    const V3 v0 = ld3(fv[0]), v1 = ld3(fv[1]), v2 = ld3(fv[2]);
+    const V3 w0 = ld3(wv[0]), w1 = ld3(wv[1]), w2 = ld3(wv[2]);
+    const V3 m = mid3(v0, v1);
+    const V3 wm = world(K, m);
+    uint32_t r0q, r1q = 0xffffffffu, r2q, r3q = 0xffffffffu;
+    if (!hn && !hp) {          // 2x, 2x+1
+        r0q = q0; r2q = q1;
+    } else if (hn && !hp) {    // 2x, 4x+2, 4x+3
+        r0q = q0; r2q = q1; r3q = q2;
+    } else if (!hn && hp) {    // 2x+1, 4x, 4x+1
+        r2q = q0; r0q = q1; r1q = q2;
+    } else {                   // 4x .. 4x+3
+        r0q = q0; r1q = q1; r2q = q2; r3q = q3;
+    }
+    // first child (v0, v2, m), or its children (v0, m, m0) and (m, v2, m0)
+    if (!hp) {
+        P.id[r0q] = 2 * x;
+        store_vertices(P, r0q, v0, v2, m, w0, w2, wm, d + 1, 0);
+    } else {
+        const V3 m0 = mid3(v0, v2);
+        const V3 wm0 = world(K, m0);
+        P.id[r0q] = 4 * x;
+        P.id[r1q] = 4 * x + 1;
+        store_vertices(P, r0q, v0, m, m0, w0, wm, wm0, d + 2, 0);
+        store_vertices(P, r1q, m, v2, m0, wm, w2, wm0, d + 2, 1);
+    }
+    // second child (v2, v1, m), or its children (v2, m, m1) and (m, v1, m1)
+    if (!hn) {
+        P.id[r2q] = 2 * x + 1;
+        store_vertices(P, r2q, v2, v1, m, w2, w1, wm, d + 1, 1);
+    } else {
+        const V3 m1 = mid3(v2, v1);
+        const V3 wm1 = world(K, m1);
+        P.id[r2q] = 4 * x + 2;
+        P.id[r3q] = 4 * x + 3;
+        store_vertices(P, r2q, v2, m, m1, w2, wm, wm1, d + 2, 0);
+        store_vertices(P, r3q, m, v1, m1, wm, w1, wm1, d + 2, 1);
+    }
+    P.fwd[s] = make_uint4(r0q, r1q, r2q, r3q);
 }
 
-// the two sibling pairs of a merge configuration, even member first
-__device__ __forceinline__ void merge_pairs(const Pool& P, const Members& M, int32_t* a0, int32_t* a1,
-                                            int32_t* b0, int32_t* b1)
+// parent of the sibling pair (c0 even, c1 odd): vertices (c0.v0, c1.v1, c0.v1)
+__device__ __forceinline__ void fill_parent(const Pool& P, uint32_t q, int32_t c0, int32_t c1, int depth)
 {
-    const bool odd = P.id[M.m[0]] & 1u;
-    *a0 = odd ? M.m[1] : M.m[0];
-    *a1 = odd ? M.m[0] : M.m[1];
-    if (M.n == 4) {
-        const bool odd3 = P.id[M.m[2]] & 1u;
-        *b0 = odd3 ? M.m[3] : M.m[2];
-        *b1 = odd3 ? M.m[2] : M.m[3];
-    } else {
-        *b0 = *b1 = -1;
+    const float4* f0 = P.vflat + 3 * (size_t)c0;
+    const float4* f1 = P.vflat + 3 * (size_t)c1;
+    const float4* w0 = P.vworld + 3 * (size_t)c0;
+    const float4* w1 = P.vworld + 3 * (size_t)c1;
+    float4* fq = P.vflat + 3 * (size_t)q;
+    float4* wq = P.vworld + 3 * (size_t)q;
+    const uint64_t id = P.id[c0] >> 1;
+    fq[0] = f0[0];
+    fq[1] = f1[1];
+    fq[2] = f0[1];
+    const float4 a = w0[0], b = w1[1], c = w0[1];
+    wq[0] = make_float4(a.x, a.y, a.z, __int_as_float(depth));
+    wq[1] = make_float4(b.x, b.y, b.z, __int_as_float((int)(id & 1u)));
+    wq[2] = make_float4(c.x, c.y, c.z, 0.0f);
+    P.id[q] = id;
+}
+
+__device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c, uint32_t base, uint32_t N)
+{
+    const uint4 m = P.fwd[s];   // (sibling, other odd, other even, members)
+    const bool quad = m.w == 4;
+    if (base + (quad ? 2u : 1u) > N) { raise_err(P, kErrAlloc); return; }
+    uint32_t qa = P.freel[base], qb = 0xffffffffu;
+    if (quad) {
+        const uint32_t q1 = P.freel[base + 1];
+        const bool a_first = (P.id[s] >> 1) < (P.id[m.z] >> 1);
+        qb = a_first ? q1 : qa;
+        qa = a_first ? qa : q1;
+    }
+    if (qa >= P.cap || (quad && qb >= P.cap)) { raise_err(P, kErrAlloc); return; }
+    const int dp = depth_of_cmd(c) - 1;
+    fill_parent(P, qa, (int32_t)s, (int32_t)m.x, dp);
+    P.fwd[s] = make_uint4(qa, m.x, m.y, m.z);
+    P.fwd[m.x] = make_uint4(qa, 0, 0, 0);
+    P.cmd[m.x] |= kMExec;
+    if (quad) {
+        fill_parent(P, qb, (int32_t)m.z, (int32_t)m.y, dp);
+        P.fwd[m.y] = make_uint4(qb, 0, 0, 0);
+        P.fwd[m.z] = make_uint4(qb, 0, 0, 0);
+        P.cmd[m.y] |= kMExec;
+        P.cmd[m.z] |= kMExec;
     }
 }
 
-// ---------------------------------------------------------------------------
-// kernel: fill new blocks (heap IDs) and the forwarding records
-// ---------------------------------------------------------------------------
-
-__global__ void __launch_bounds__(kBlock) k_fill(Pool P)
+__global__ void __launch_bounds__(kBlock) k_fill(Pool P, LodK K)
 {
+    __shared__ uint32_t sh[8];
     uint32_t r0, r1;
     rank_range(P.ctr->L, &r0, &r1);
     const uint32_t N = P.ctr->N;
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-        const uint32_t s = P.live[r];
-        const int4 l = P.link[s];
-        const uint32_t cmd = cmd_of(l);
-        const uint32_t base = P.pre[r];
-        if (cmd & kMarks) {
-            // outputs in ascending heap-ID order take blocks base, base+1, ...
-            const bool hn = cmd & kMarkN, hp = cmd & kMarkP;
-            const uint32_t cnt = 2u + (hn ? 1u : 0u) + (hp ? 1u : 0u);
-            if (base + cnt > N) { raise_err(P, kErrAlloc); continue; }
-            const uint32_t q0 = P.freel[base], q1 = P.freel[base + 1];
-            const uint32_t q2 = cnt > 2 ? P.freel[base + 2] : 0u, q3 = cnt > 3 ? P.freel[base + 3] : 0u;
-            if (q0 >= P.cap || q1 >= P.cap || q2 >= P.cap || q3 >= P.cap) { raise_err(P, kErrAlloc); continue; }
-            const uint64_t x = P.id[s];
-            uint4 f;
-            if (!hn && !hp) {          // 2x, 2x+1
-                P.id[q0] = 2 * x;
-                P.id[q1] = 2 * x + 1;
-                f = make_uint4(q0, 0xffffffffu, q1, 0xffffffffu);
-            } else if (hn && !hp) {    // 2x, 4x+2, 4x+3
-                P.id[q0] = 2 * x;
-                P.id[q1] = 4 * x + 2;
-                P.id[q2] = 4 * x + 3;
-                f = make_uint4(q0, 0xffffffffu, q1, q2);
-            } else if (!hn && hp) {    // 2x+1, 4x, 4x+1
-                P.id[q0] = 2 * x + 1;
-                P.id[q1] = 4 * x;
-                P.id[q2] = 4 * x + 1;
-                f = make_uint4(q1, q2, q0, 0xffffffffu);
-            } else {                   // 4x, 4x+1, 4x+2, 4x+3
-                P.id[q0] = 4 * x;
-                P.id[q1] = 4 * x + 1;
-                P.id[q2] = 4 * x + 2;
-                P.id[q3] = 4 * x + 3;
-                f = make_uint4(q0, q1, q2, q3);
-            }
-            P.fwd[s] = f;
-        } else if ((cmd & (kMExec | kMMin)) == (kMExec | kMMin)) {
-            const Members M = merge_members(P, (int32_t)s, P.id[s], l);
-            if (M.n == 0) { raise_err(P, kErrPointer); continue; }
-            int32_t a0, a1, b0, b1;
-            merge_pairs(P, M, &a0, &a1, &b0, &b1);
-            const uint64_t pa = P.id[a0] >> 1;
-            const uint64_t pb = M.n == 4 ? (P.id[b0] >> 1) : 0;
-            if (base + (M.n / 2) > N) { raise_err(P, kErrAlloc); continue; }
-            uint32_t qa, qb = 0xffffffffu;
-            if (M.n == 4) {
-                const uint32_t q0 = P.freel[base], q1 = P.freel[base + 1];
-                qa = pa < pb ? q0 : q1;
-                qb = pa < pb ? q1 : q0;
-            } else {
-                qa = P.freel[base];
-            }
-            if (qa >= P.cap || (M.n == 4 && qb >= P.cap)) { raise_err(P, kErrAlloc); continue; }
-            P.id[qa] = pa;
-            P.fwd[a0] = make_uint4(qa, 0, 0, 0);
-            P.fwd[a1] = make_uint4(qa, 0, 0, 0);
-            if (M.n == 4) {
-                P.id[qb] = pb;
-                P.fwd[b0] = make_uint4(qb, 0, 0, 0);
-                P.fwd[b1] = make_uint4(qb, 0, 0, 0);
-            }
+    const uint32_t n = P.lcnt[blockIdx.x];
+    uint32_t carry = P.part[blockIdx.x].x;
+    for (uint32_t ib = 0; ib < n; ib += kBlock) {
+        const uint32_t i = ib + threadIdx.x;
+        uint32_t s = 0, c = 0, k = 0;
+        if (i < n) {
+            s = P.list[r0 + i];
+            c = P.cmd[s];
+            k = (c & kMarks) ? split_outputs(c) : ((c & kMQuad) ? 2u : 1u);
         }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(k, sh, &tot);
+        if (i < n) {
+            if (c & kMarks) fill_split(P, s, c, carry + ex, N, K);
+            else fill_merge(P, s, c, carry + ex, N);
+        }
+        carry += tot;
     }
 }
 
@@ -827,36 +893,65 @@ __device__ __forceinline__ int cover_role(uint32_t marks, int edge, int piece)
     return piece == kWhole ? 0 : -1;
 }
 
-__device__ __forceinline__ int32_t link_field(const int4& l, int e) { return e == 0 ? l.x : (e == 1 ? l.y : l.z); }
-
-// New neighbour across (a piece of) edge e of the consumed bisector b, seen
-// from its output x.  The old neighbour n is found through b's pre-frame
-// pointer; n is then untouched (x takes n, and n's back-pointer is
-// rewritten to x -- its only writer), split (the output of n covering the
-// same piece: on a shared edge the halves swap between bisectors of equal
-// depth and keep their names across a depth difference of one), or merged
-// (its parent).
-__device__ int32_t resolve_edge(const Pool& P, int32_t b, const int4& lb, int db, int e, int piece, uint32_t x)
+__device__ __forceinline__ uint32_t comp(uint4 v, int i)
 {
-    const int32_t n = link_field(lb, e);
-    if (n < 0) return -1;
-    if (!slot_ok(P, n)) { raise_err(P, kErrPointer); return -1; }
-    const int4 ln = P.link[n];
-    const int f = ln.x == b ? 0 : (ln.y == b ? 1 : (ln.z == b ? 2 : -1));
-    if (f < 0) { raise_err(P, kErrPointer); return -1; }
-    const uint32_t cn = cmd_of(ln);
-    if (cn & kMarks) {
-        const int dn = (int)((cn & kDepthMask) >> kDepthShift);
-        int pn = piece;
-        if (piece != kWhole && dn == db) pn = piece == kHalf0 ? kHalf1 : kHalf0;
-        const int role = cover_role(cn & kMarks, f, pn);
-        if (role < 0) { raise_err(P, kErrEdge); return -1; }
-        return (int32_t)comp(P.fwd[n], role);
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+// The old neighbour across one edge of a consumed bisector b, loaded once:
+// its block, which of its fields pointed to b, its command word and (when it
+// is consumed too) its forwarding record.
+struct Nb {
+    int32_t n;
+    int f;
+    uint32_t c;
+    uint4 fw;
+};
+
+__device__ __forceinline__ Nb load_nb(const Pool& P, int32_t b, int32_t n)
+{
+    Nb r;
+    r.n = n;
+    r.f = -1;
+    r.c = 0;
+    r.fw = make_uint4(0, 0, 0, 0);
+    if (n < 0) return r;
+    if (!slot_ok(P, n)) {
+        raise_err(P, kErrPointer);
+        r.n = -1;
+        return r;
     }
-    if (cn & kMExec) return (int32_t)P.fwd[n].x;
+    const int4 ln = P.link[n];
+    r.f = ln.x == b ? 0 : (ln.y == b ? 1 : (ln.z == b ? 2 : -1));
+    if (r.f < 0) {
+        raise_err(P, kErrPointer);
+        r.n = -1;
+        return r;
+    }
+    r.c = P.cmd[n];
+    if (r.c & (kMarks | kMExec)) r.fw = P.fwd[n];
+    return r;
+}
+
+// New neighbour across (a piece of) an old edge, seen from output x: the
+// untouched neighbour itself (whose back-pointer x then takes over -- its
+// only writer), the output of a split neighbour covering the same piece
+// (halves swap names between bisectors of equal depth and keep them across a
+// depth difference of one), or a merged neighbour's parent.
+__device__ __forceinline__ int32_t piece_target(const Pool& P, const Nb& nb, int db, int piece, uint32_t x)
+{
+    if (nb.n < 0) return -1;
+    if (nb.c & kMarks) {
+        int pn = piece;
+        if (piece != kWhole && depth_of_cmd(nb.c) == db) pn = piece == kHalf0 ? kHalf1 : kHalf0;
+        const int role = cover_role(nb.c & kMarks, nb.f, pn);
+        if (role < 0) { raise_err(P, kErrEdge); return -1; }
+        return (int32_t)comp(nb.fw, role);
+    }
+    if (nb.c & kMExec) return (int32_t)nb.fw.x;
     if (piece != kWhole) { raise_err(P, kErrEdge); return -1; }
-    reinterpret_cast<int*>(&P.link[n])[f] = (int)x;
-    return n;
+    reinterpret_cast<int*>(&P.link[nb.n])[nb.f] = (int)x;
+    return nb.n;
 }
 
 __device__ __forceinline__ void store_link(const Pool& P, uint32_t q, int32_t t, int32_t n, int32_t p)
@@ -870,60 +965,64 @@ __device__ __forceinline__ void clear_bit(const Pool& P, uint32_t s)
     atomicAnd(&P.bits[s >> 5], ~(1u << (s & 31u)));
 }
 
+__device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t c)
+{
+    const int db = depth_of_cmd(c);
+    const bool hn = c & kMarkN, hp = c & kMarkP;
+    const int4 lb = P.link[b];
+    const uint4 f = P.fwd[b];
+    const Nb nT = load_nb(P, b, lb.x);
+    const Nb nN = load_nb(P, b, lb.y);
+    const Nb nP = load_nb(P, b, lb.z);
+    if (!hp) {  // first child (v0, v2, m)
+        store_link(P, f.x, piece_target(P, nP, db, kWhole, f.x), (int32_t)f.z, piece_target(P, nT, db, kHalf0, f.x));
+    } else {    // its two children
+        store_link(P, f.x, piece_target(P, nT, db, kHalf0, f.x), (int32_t)f.y, piece_target(P, nP, db, kHalf1, f.x));
+        store_link(P, f.y, (int32_t)f.z, piece_target(P, nP, db, kHalf0, f.y), (int32_t)f.x);
+    }
+    if (!hn) {  // second child (v2, v1, m)
+        store_link(P, f.z, piece_target(P, nN, db, kWhole, f.z), piece_target(P, nT, db, kHalf1, f.z),
+                   (int32_t)(hp ? f.y : f.x));
+    } else {    // its two children
+        store_link(P, f.z, (int32_t)(hp ? f.y : f.x), (int32_t)f.w, piece_target(P, nN, db, kHalf1, f.z));
+        store_link(P, f.w, piece_target(P, nT, db, kHalf1, f.w), piece_target(P, nN, db, kHalf0, f.w), (int32_t)f.z);
+    }
+    clear_bit(P, (uint32_t)b);
+}
+
+// parent q of the sibling pair (c0, c1): Next edge = c1's base edge, Prev
+// edge = c0's base edge, Twin = the other parent (or the border)
+__device__ __forceinline__ void resolve_parent(const Pool& P, uint32_t q, int32_t twin, int32_t c0, int32_t c1, int d)
+{
+    const Nb n1 = load_nb(P, c1, P.link[c1].x);
+    const Nb n0 = load_nb(P, c0, P.link[c0].x);
+    store_link(P, q, twin, piece_target(P, n1, d, kWhole, q), piece_target(P, n0, d, kWhole, q));
+}
+
 __global__ void __launch_bounds__(kBlock) k_resolve(Pool P)
 {
     uint32_t r0, r1;
     rank_range(P.ctr->L, &r0, &r1);
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-        const int32_t b = (int32_t)P.live[r];
-        const int4 lb = P.link[b];
-        const uint32_t cmd = cmd_of(lb);
-        if (cmd & kMarks) {
-            const int db = (int)((cmd & kDepthMask) >> kDepthShift);
-            const bool hn = cmd & kMarkN, hp = cmd & kMarkP;
-            const uint4 f = P.fwd[b];
-            if (!hp) {  // first child (v0, v2, m)
-                store_link(P, f.x, resolve_edge(P, b, lb, db, kEdgeP, kWhole, f.x), (int32_t)f.z,
-                           resolve_edge(P, b, lb, db, kEdgeT, kHalf0, f.x));
-            } else {    // its two children
-                store_link(P, f.x, resolve_edge(P, b, lb, db, kEdgeT, kHalf0, f.x), (int32_t)f.y,
-                           resolve_edge(P, b, lb, db, kEdgeP, kHalf1, f.x));
-                store_link(P, f.y, (int32_t)f.z, resolve_edge(P, b, lb, db, kEdgeP, kHalf0, f.y), (int32_t)f.x);
-            }
-            if (!hn) {  // second child (v2, v1, m)
-                store_link(P, f.z, resolve_edge(P, b, lb, db, kEdgeN, kWhole, f.z),
-                           resolve_edge(P, b, lb, db, kEdgeT, kHalf1, f.z), (int32_t)(hp ? f.y : f.x));
-            } else {    // its two children
-                store_link(P, f.z, (int32_t)(hp ? f.y : f.x), (int32_t)f.w,
-                           resolve_edge(P, b, lb, db, kEdgeN, kHalf1, f.z));
-                store_link(P, f.w, resolve_edge(P, b, lb, db, kEdgeT, kHalf1, f.w),
-                           resolve_edge(P, b, lb, db, kEdgeN, kHalf0, f.w), (int32_t)f.z);
+    const uint32_t n = P.lcnt[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+        const int32_t b = (int32_t)P.list[r0 + i];
+        const uint32_t c = P.cmd[b];
+        if (c & kMarks) {
+            resolve_split(P, b, c);
+        } else {
+            const uint4 f = P.fwd[b];   // (parent, sibling, other odd, other even)
+            const int d = depth_of_cmd(c);
+            if (c & kMQuad) {
+                const uint32_t qb = P.fwd[f.w].x;
+                resolve_parent(P, f.x, (int32_t)qb, b, (int32_t)f.y, d);
+                resolve_parent(P, qb, (int32_t)f.x, (int32_t)f.w, (int32_t)f.z, d);
+                clear_bit(P, f.z);
+                clear_bit(P, f.w);
+            } else {
+                resolve_parent(P, f.x, -1, b, (int32_t)f.y, d);
             }
             clear_bit(P, (uint32_t)b);
-        } else if ((cmd & (kMExec | kMMin)) == (kMExec | kMMin)) {
-            const Members M = merge_members(P, b, P.id[b], lb);
-            if (M.n == 0) { raise_err(P, kErrPointer); continue; }
-            int32_t a0, a1, b0, b1;
-            merge_pairs(P, M, &a0, &a1, &b0, &b1);
-            const uint32_t qa = P.fwd[a0].x;
-            const uint32_t qb = M.n == 4 ? P.fwd[b0].x : 0xffffffffu;
-            // parent of a sibling pair: Next edge = odd child's base edge,
-            // Prev edge = even child's base edge, Twin = the other parent
-            {
-                const int4 l0 = P.link[a0], l1 = P.link[a1];
-                const int d0 = (int)((cmd_of(l0) & kDepthMask) >> kDepthShift);
-                const int32_t nn = resolve_edge(P, a1, l1, d0, kEdgeT, kWhole, qa);
-                const int32_t pp = resolve_edge(P, a0, l0, d0, kEdgeT, kWhole, qa);
-                store_link(P, qa, M.n == 4 ? (int32_t)qb : -1, nn, pp);
-            }
-            if (M.n == 4) {
-                const int4 l0 = P.link[b0], l1 = P.link[b1];
-                const int d0 = (int)((cmd_of(l0) & kDepthMask) >> kDepthShift);
-                const int32_t nn = resolve_edge(P, b1, l1, d0, kEdgeT, kWhole, qb);
-                const int32_t pp = resolve_edge(P, b0, l0, d0, kEdgeT, kWhole, qb);
-                store_link(P, qb, (int32_t)qa, nn, pp);
-            }
-            for (int i = 0; i < M.n; ++i) clear_bit(P, (uint32_t)M.m[i]);
+            clear_bit(P, f.y);
         }
     }
 }
@@ -974,8 +1073,34 @@ __global__ void __launch_bounds__(1024) k_reduce_top(Pool P)
 }
 
 // ---------------------------------------------------------------------------
-// kernels used by queries and restore
+// kernels: vertex-cache refresh, queries and restore
 // ---------------------------------------------------------------------------
+
+// Rebuild the cache of every live block: flat vertices by the Alg. 2 decode
+// (when flat is set) and world positions from them.
+__global__ void __launch_bounds__(kBlock) k_refresh(Pool P, LodK K, int flat)
+{
+    const uint32_t L = P.ctr->L;
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < L; r += gridDim.x * kBlock) {
+        const uint32_t s = P.live[r];
+        const uint64_t id = P.id[s];
+        V3 a = {0, 0, 0}, b = a, c = a;
+        int d = 0;
+        if (valid_id(P, id)) {
+            d = ilog2_64(id) - P.k;
+            if (flat) decode(P, id, d, a, b, c);
+        } else {
+            raise_err(P, kErrPointer);
+        }
+        if (!flat) {
+            const float4* f = P.vflat + 3 * (size_t)s;
+            a = ld3(f[0]);
+            b = ld3(f[1]);
+            c = ld3(f[2]);
+        }
+        store_vertices(P, s, a, b, c, world(K, a), world(K, b), world(K, c), d, (int)(id & 1u));
+    }
+}
 
 __global__ void k_bits_from_ids(Pool P)
 {
@@ -1004,19 +1129,19 @@ __global__ void k_gather_links(Pool P, uint32_t r0, uint32_t n, int32_t* out)
     out[3 * (size_t)i + 2] = l.z;
 }
 
+// flat-domain vertices from the vertex cache
 __global__ void k_gather_vertices(Pool P, uint32_t r0, uint32_t n, float* out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint64_t id = P.id[P.live[r0 + i]];
-    const int d = ilog2_64(id) - P.k;
-    V3 a = {0, 0, 0}, b = a, c = a;
-    if (id != 0 && d >= 0 && d <= 63 - P.k && (int64_t)(id >> d) - ((int64_t)1 << P.k) < P.H)
-        decode(P, id, d, a, b, c);
+    const float4* f = P.vflat + 3 * (size_t)P.live[r0 + i];
     float* o = out + 9 * (size_t)i;
-    o[0] = a.x; o[1] = a.y; o[2] = a.z;
-    o[3] = b.x; o[4] = b.y; o[5] = b.z;
-    o[6] = c.x; o[7] = c.y; o[8] = c.z;
+    for (int v = 0; v < 3; ++v) {
+        const float4 x = f[v];
+        o[3 * v + 0] = x.x;
+        o[3 * v + 1] = x.y;
+        o[3 * v + 2] = x.z;
+    }
 }
 
 __global__ void k_fill_bytes(uint8_t* out, uint32_t n, uint8_t v)
@@ -1030,7 +1155,7 @@ __global__ void k_gather_decisions(Pool P, uint32_t L, uint8_t* out)
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= L) return;
     const uint32_t s = P.live[r];
-    out[s] = (uint8_t)(*cmd_ptr(P, s) & kDecMask);
+    out[s] = (uint8_t)(P.cmd[s] & kDecMask);
 }
 
 __global__ void k_export_heap(Pool P, uint32_t* out)
@@ -1071,21 +1196,25 @@ size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
         off = (off + bytes + 255) & ~(size_t)255;
         return o;
     };
-    const size_t o_id = take(8 * cap), o_link = take(16 * cap), o_fwd = take(16 * cap);
+    const size_t o_id = take(8 * cap), o_link = take(16 * cap), o_cmd = take(4 * cap), o_fwd = take(16 * cap);
+    const size_t o_flat = take(48 * cap), o_world = take(48 * cap);
     const size_t o_bits = take(4 * W), o_tree = take(4 * TW), o_live = take(4 * cap);
-    const size_t o_val = take(8 * cap), o_pre = take(4 * cap), o_free = take(4 * cap);
+    const size_t o_free = take(4 * cap), o_list = take(4 * cap), o_lcnt = take(4 * (size_t)kRankGrid);
     const size_t o_part = take(sizeof(uint2) * kRankGrid), o_ctr = take(sizeof(Counters));
     const size_t o_root = take(36 * (size_t)H);
     if (P) {
         P->id = reinterpret_cast<uint64_t*>(base + o_id);
         P->link = reinterpret_cast<int4*>(base + o_link);
+        P->cmd = reinterpret_cast<uint32_t*>(base + o_cmd);
         P->fwd = reinterpret_cast<uint4*>(base + o_fwd);
+        P->vflat = reinterpret_cast<float4*>(base + o_flat);
+        P->vworld = reinterpret_cast<float4*>(base + o_world);
         P->bits = reinterpret_cast<uint32_t*>(base + o_bits);
         P->tree = reinterpret_cast<uint32_t*>(base + o_tree);
         P->live = reinterpret_cast<uint32_t*>(base + o_live);
-        P->val = reinterpret_cast<uint2*>(base + o_val);
-        P->pre = reinterpret_cast<uint32_t*>(base + o_pre);
         P->freel = reinterpret_cast<uint32_t*>(base + o_free);
+        P->list = reinterpret_cast<uint32_t*>(base + o_list);
+        P->lcnt = reinterpret_cast<uint32_t*>(base + o_lcnt);
         P->part = reinterpret_cast<uint2*>(base + o_part);
         P->ctr = reinterpret_cast<Counters*>(base + o_ctr);
         P->root = reinterpret_cast<float*>(base + o_root);
@@ -1114,6 +1243,14 @@ hipError_t launch_enumerate(const Pool& P, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_refresh(const Pool& P, const LodK& K, int flat, hipStream_t s)
+{
+    hipError_t e = launch_enumerate(P, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_refresh, dim3(kRankGrid), dim3(kBlock), 0, s, P, K, flat);
+    return hipGetLastError();
+}
+
 hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, hipStream_t s,
                         const StageEvents* ev)
 {
@@ -1134,26 +1271,25 @@ hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, 
     mark(kClass, false);
     mark(kVote, true);
     hipLaunchKernelGGL(k_vote, g, b, 0, s, P);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, P, 0);
     mark(kVote, false);
     mark(kBudget, true);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, P, 0);
     hipLaunchKernelGGL(k_budget, g, b, 0, s, P);
     mark(kBudget, false);
     mark(kChain, true);
-    hipLaunchKernelGGL(k_chain, g, b, 0, s, P);
+    hipLaunchKernelGGL(k_walk, g, b, 0, s, P);
     mark(kChain, false);
     mark(kOwners, true);
     hipLaunchKernelGGL(k_owners, g, b, 0, s, P);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, P, 1);
     mark(kOwners, false);
     mark(kOffsets, true);
-    hipLaunchKernelGGL(k_offsets, g, b, 0, s, P);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, P, 1);
     mark(kOffsets, false);
     mark(kFree, true);
     hipLaunchKernelGGL(k_freelist, gw, b, 0, s, P);
     mark(kFree, false);
     mark(kFill, true);
-    hipLaunchKernelGGL(k_fill, g, b, 0, s, P);
+    hipLaunchKernelGGL(k_fill, g, b, 0, s, P, K);
     mark(kFill, false);
     mark(kResolve, true);
     hipLaunchKernelGGL(k_resolve, g, b, 0, s, P);
