@@ -1,20 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the per-frame adaptive bisection update on one MI355X.
 
-A step is one frame of the update (every stage of the pipeline) along the
-seeded camera path of the workload.  The first W frames are warm-up (the
-triangulation grows from the base mesh to its steady size); the next K frames
-are timed between two stream synchronisations.  Bisector updates/s =
-sum over the timed frames of the live count at frame start / elapsed time.
+Modes
+  single (default)  one instance, the terrain workload (depth-24 pool, 64x64
+                    quad grid, ridged height field): a step is one frame of
+                    the update (every stage of the pipeline) along the seeded
+                    flythrough.  The first W frames are warm-up (the
+                    triangulation grows from the base mesh); the next K are
+                    timed between two stream synchronisations.
+                    Bisector updates/s = sum over the timed frames of the
+                    live count at frame start / elapsed time.
+  batch             many instances of uneven size and depth (128 by default),
+                    the same frames run one instance per launch sequence and
+                    then batched (one launch per stage for all instances,
+                    replayed from a HIP graph); both must give identical
+                    states.
+  serve             Poisson request stream over resident instances through
+                    the serving loop (continuous batching, admission by
+                    footprint, eviction to host), and the same trace served
+                    one request per launch; p50/p99 request latency.
 
-Measurement protocol (deterministic pipeline):
+Single-mode protocol (the pipeline is deterministic):
   1. warm up W frames;  2. snapshot the pool;
-  3. run the K frames once with per-frame counters (untimed) to get the live
-     counts;  4. restore the snapshot;
-  5. run the same K frames again, timed, with HIP events around the profiled
-     stage on the library's stream.
-The roofline object reports that stage: algorithmic bytes per launch over
-its mean event-timed duration, against the 8 TB/s HBM peak.
+  3. run the K frames once with per-frame counters (untimed) for the live
+     counts and the algorithmic bytes;  4. restore;
+  5. run the K frames timed, with HIP events around the profiled stage on the
+     library's stream (roofline);  6. restore;
+  7. run the K frames again with events around every whole frame (p50/p99
+     frame latency) and check the final state equals the timed pass's.
 """
 from __future__ import annotations
 
@@ -28,29 +41,52 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "bisector updates/s per frame (% HBM roofline); p50/p99 update latency"
 
 
-def algorithmic_bytes(stage: str, st: dict, cap: int) -> float:
-    """Bytes a stage must move per launch, from the frame's counters.
+def algorithmic_bytes(stage: str, st: dict) -> float:
+    """Bytes a stage must move per launch, from one frame's counters.
 
     L live bisectors, R merge requests, S bisectors consumed by splits,
-    M merged configurations, N new bisectors."""
+    C merge configurations executed, M merged members, P parents (M / 2),
+    O split outputs (allocations - P)."""
     L = st["live_before"]
     R = st["merge_requests"]
     S = st["split_consumed"]
-    N = st["allocations"]
-    consumed = st["frees"]
+    C = st["merges_executed"]
+    M = st["frees"] - S
+    P = M // 2
+    O = st["allocations"] - P
     if stage == "classify":
-        # heap ID read (8 B) + command write (4 B) per bisector; a merge
-        # request also reads its pointers (12 B) and three neighbour IDs (24 B)
-        return 12.0 * L + 36.0 * R
+        # rank -> block (4), cached world positions (48), command write (4);
+        # even merge requests are listed (8)
+        return 56.0 * L + 4.0 * R
+    if stage == "fill":
+        # owner entries (8 + 4); a split bisector's vertex record read (96) and
+        # its fate + forwarding written (20); per split output a free-list
+        # entry (4) and a vertex record (96); a merge reads its members'
+        # forwarding (16) and IDs (8 per parent), per parent the children's
+        # vertex halves (96), a free-list entry (4) and the parent's record
+        # (96); every merged member's fate + forwarding (20)
+        return 12.0 * (S + C) + 116.0 * S + 100.0 * O + 16.0 * C + 204.0 * P + 20.0 * M
+    if stage == "resolve":
+        # owner entries (8); a split bisector's ID, pointers, forwarding (40),
+        # its three neighbours' pointers (48), its bit (4); per output ID +
+        # pointers (24); a merge's forwarding and IDs (24 per parent), per
+        # parent the children's pointers (32) and their two outer
+        # neighbours' pointers (32), ID + pointers (24), two bits (8)
+        return 8.0 * (S + C) + 92.0 * S + 24.0 * O + 120.0 * P
     if stage == "frame":
-        # per bisector: ID read and command write/read (16 B); per consumed
-        # bisector: record read (20 B), forwarding write (16 B), neighbour
-        # fix-ups (12 B); per new bisector: record write (20 B) and bit (4 B);
-        # bitfield read twice and the tree levels above the word (3/8 B/slot)
-        return 16.0 * L + 48.0 * consumed + 24.0 * N + 0.375 * cap
+        # every stage: rank passes over L (enumerate 4, classify 56, budget 8,
+        # owners 8), the fill and resolve bytes, and the bitfield + tree
+        # passes (3/8 byte per pool block, taken as L here)
+        return 76.0 * L + algorithmic_bytes("fill", st) + algorithmic_bytes("resolve", st)
     raise KeyError(stage)
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, np.float64), q)) if len(xs) else None
 
 
 def cpu_baseline(workload: str, budget_s: float) -> dict:
@@ -78,32 +114,8 @@ def cpu_baseline(workload: str, budget_s: float) -> dict:
                       f"{total_t:.1f} s single-threaded on {os.cpu_count()} host cores"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--workload", default="terrain", choices=["terrain", "planet", "cube"])
-    ap.add_argument("--stage", default="classify", choices=["classify", "frame"])
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run plain 256 MiB device copies (scale of the HBM byte counters)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": a.numel(), "copies": 5}))
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build"}))
-        sys.exit(2)
-
+def run_single(args) -> dict:
+    import numpy as np
     import torch
     from paper_2407_02215_amd import cbt
     from paper_2407_02215_amd import inputs as I
@@ -112,9 +124,8 @@ def main():
     w = I.workload(args.workload, frames=max(frames, 8))
     if len(w.cameras) < frames:
         raise SystemExit(f"workload {args.workload} has {len(w.cameras)} frames, asked for {frames}")
-    inst = cbt.Instance(w.mesh, w.depth, w.lod)
-    stream = inst.stream
-    print(f"# warm-up {args.warmup} frames", file=sys.stderr, flush=True)
+    inst = cbt.Instance(w.mesh, w.depth, w.lod, tuned=True)
+    print(f"# warm-up {args.warmup} frames, schedule {inst.schedule()}", file=sys.stderr, flush=True)
     for cam in w.cameras[:args.warmup]:
         inst.update(cam)
     torch.cuda.synchronize()
@@ -133,22 +144,24 @@ def main():
     elapsed = time.perf_counter() - t0
     launches, stage_ms = inst.stage_time()
     inst.time_stage(None)
-    # the timed pass must reproduce the counted one
-    check = inst.pool()
+    check = [a.copy() for a in inst.pool()]
+    print("# latency pass", file=sys.stderr, flush=True)
     inst.restore(*snap)
+    inst.time_stage("frame")
     for cam in timed:
         inst.update(cam)
+    frame_ms = inst.stage_times()
+    inst.time_stage(None)
     again = inst.pool()
-    import numpy as np
     assert all(np.array_equal(a, b) for a, b in zip(check, again)), "non-deterministic frame"
 
     updates = sum(s["live_before"] for s in stats)
     value = updates / elapsed
-    alg = sum(algorithmic_bytes(args.stage, s, inst.cap) for s in stats) / len(stats)
+    alg = sum(algorithmic_bytes(args.stage, s) for s in stats) / len(stats)
     mean_ms = stage_ms / max(1, launches)
     achieved = alg / (mean_ms * 1e-3) / 1e9
     out = {
-        "metric": "bisector updates/s per frame (% HBM roofline); p50/p99 update latency",
+        "metric": METRIC,
         "value": value,
         "unit": "bisector updates/s",
         "n_gpus": 1,
@@ -161,16 +174,234 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded workload generator)",
         "config": {"workload": args.workload, "cbt_depth": w.depth, "halfedges": w.mesh.H,
-                   "frames": f"{args.warmup}..{frames - 1}", "mean_live": updates / len(stats)},
+                   "frames": f"{args.warmup}..{frames - 1}", "mean_live": updates / len(stats),
+                   "schedule": list(inst.schedule())},
+        "latency_ms": {"p50": percentile(frame_ms, 50), "p99": percentile(frame_ms, 99),
+                       "what": "GPU time of one whole update, HIP events"},
         "roofline": {"bound": "hbm", "kernel": args.stage, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": args.traffic,
                      "mean_launch_ms": mean_ms, "alg_bytes_per_launch": alg},
     }
-    if not args.no_cpu_baseline:
-        print("# CPU reference baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
-    print(json.dumps(out), flush=True)
     inst.close()
+    return out
+
+
+def run_batch(args) -> dict:
+    import numpy as np
+    import torch
+    from paper_2407_02215_amd import cbt
+    from paper_2407_02215_amd import inputs as I
+
+    frames = args.warmup + args.steps
+    print(f"# building {args.instances} instances", file=sys.stderr, flush=True)
+    ws = I.batched_workloads(args.instances, frames=frames, seed=4)
+    insts = [cbt.Instance(w.mesh, w.depth, w.lod, tuned=True) for w in ws]
+    print(f"# warm-up {args.warmup} frames (one launch sequence per instance)", file=sys.stderr, flush=True)
+    for f in range(args.warmup):
+        for x, w in zip(insts, ws):
+            x.update(w.cameras[f])
+    torch.cuda.synchronize()
+    snaps = [x.snapshot() for x in insts]
+    timed = range(args.warmup, frames)
+    print("# counting pass", file=sys.stderr, flush=True)
+    updates = 0
+    for f in timed:
+        for x, w in zip(insts, ws):
+            updates += x.update(w.cameras[f], stats=True)["live_before"]
+    for x, s in zip(insts, snaps):
+        x.restore(*s)
+    print("# one instance per launch sequence", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in timed:
+        for x, w in zip(insts, ws):
+            x.update(w.cameras[f])
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    ref = [[a.copy() for a in x.pool()] for x in insts]
+    for x, s in zip(insts, snaps):
+        x.restore(*s)
+    batch = cbt.Batch(insts, graph=True)
+    print("# batched (graph replay)", file=sys.stderr, flush=True)
+    batch.update([w.cameras[args.warmup] for w in ws])     # capture (counts as the first frame)
+    batch.synchronize()
+    t0 = time.perf_counter()
+    for f in list(timed)[1:]:
+        batch.update([w.cameras[f] for w in ws])
+    batch.synchronize()
+    t_batch_rest = time.perf_counter() - t0
+    same = all(all(np.array_equal(a, b) for a, b in zip(r, x.pool())) for r, x in zip(ref, insts))
+    # the graph capture frame is timed separately: replay time per frame
+    n = len(timed)
+    t_batch = t_batch_rest * n / max(1, n - 1)
+    batch.close()
+    for x in insts:
+        x.close()
+    return {
+        "metric": "batched bisector updates/s",
+        "value": updates / t_batch,
+        "unit": "bisector updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batch * 1e3 / n,
+        "higher_is_better": True,
+        "vs_one_launch_per_instance": t_single / t_batch,
+        "one_launch_per_instance": {"value": updates / t_single, "ms_per_step": t_single * 1e3 / n},
+        "identical_states": bool(same),
+        "dtype": "f32",
+        "data": "synthetic (seeded workload generator)",
+        "config": {"workload": "batched", "instances": args.instances,
+                   "halfedges": [int(min(w.mesh.H for w in ws)), int(max(w.mesh.H for w in ws))],
+                   "depths": [int(min(w.depth for w in ws)), int(max(w.depth for w in ws))],
+                   "pool_blocks": int(sum(1 << w.depth for w in ws)), "mean_live_per_frame": updates / n},
+    }
+
+
+def run_serve(args) -> dict:
+    import numpy as np
+    import torch
+    from paper_2407_02215_amd import cbt
+    from paper_2407_02215_amd import inputs as I
+
+    rng = np.random.default_rng(11)
+    n_req = int(args.rate * args.duration)
+    gaps = rng.exponential(1.0 / args.rate, n_req)
+    arrivals = np.cumsum(gaps)
+    new_frac = 0.10
+    base = I.batched_workloads(args.meshes, frames=64, seed=4)
+    depth_lo, depth_hi = 14, 22
+    specs = []   # (workload, depth, cameras) per instance, resident ones first
+
+    def new_spec():
+        w = base[int(rng.integers(len(base)))]
+        D = I.depth_for(w.mesh.H, int(rng.integers(depth_lo, depth_hi + 1)))
+        cams = I.camera_path_orbit(64, int(rng.integers(1 << 30)))
+        specs.append((w, D, cams))
+        return len(specs) - 1
+
+    for _ in range(args.instances):
+        new_spec()
+    trace = []   # (arrival, spec index, camera index)
+    counts = {}
+    for t in arrivals:
+        if rng.random() < new_frac:
+            k = new_spec()
+        else:
+            k = int(rng.integers(len(specs)))
+        c = counts.get(k, 0)
+        counts[k] = c + 1
+        trace.append((float(t), k, c % 64))
+    free, total = torch.cuda.mem_get_info()
+    arena = int(min(args.budget_gb * (1 << 30), 0.8 * free))
+    print(f"# {len(specs)} instances, {n_req} requests at {args.rate}/s, arena {arena / 2**30:.1f} GiB",
+          file=sys.stderr, flush=True)
+
+    def serve(max_batch, slots):
+        srv = cbt.Server(arena_bytes=arena, memory_budget=arena, max_batch=max_batch, slots=slots,
+                         map_capacity=1 << 22)
+        ids = {}
+        for k in range(args.instances):
+            w, D, _ = specs[k]
+            ids[k] = srv.open(w.mesh, D, w.lod)
+        done = []
+        t0 = time.perf_counter()
+        for t, k, c in trace:
+            while time.perf_counter() - t0 < t:
+                done += srv.poll()
+            if k not in ids:
+                w, D, _ = specs[k]
+                ids[k] = srv.open(w.mesh, D, w.lod)
+            srv.submit(ids[k], specs[k][2][c], len(done))
+        done += srv.drain()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        lat = [d["latency_ms"] for d in done]
+        ok = all(d["status"] == 0 for d in done)
+        res = {"p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+               "value": st["bisector_updates"] / wall, "wall_s": wall, "requests": len(done), "all_ok": ok,
+               "batches": st["batches"], "mean_batch": len(done) / max(1, st["batches"]),
+               "admissions": st["admissions"], "evictions": st["evictions"]}
+        sample = sorted(ids)[:: max(1, len(ids) // 16)]
+        states = {k: srv.query(ids[k]) for k in sample}
+        srv.close()
+        return res, states
+
+    print("# continuous batching", file=sys.stderr, flush=True)
+    batched, s1 = serve(args.max_batch, 2)
+    print("# one request per launch", file=sys.stderr, flush=True)
+    single, s2 = serve(1, 1)
+    same = all(all(np.array_equal(s1[k][f], s2[k][f]) for f in ("slot", "heap_id", "twin", "next", "prev"))
+               for k in s1)
+    return {
+        "metric": "served bisector updates/s; p50/p99 request latency",
+        "value": batched["value"],
+        "unit": "bisector updates/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "latency_ms": {"p50": batched["p50_ms"], "p99": batched["p99_ms"],
+                       "what": "submit to completion observed by the host"},
+        "served": batched,
+        "one_request_per_launch": single,
+        "identical_states_sampled": bool(same),
+        "dtype": "f32",
+        "data": "synthetic (seeded workload generator)",
+        "config": {"workload": "served", "rate_per_s": args.rate, "duration_s": args.duration,
+                   "resident_instances": args.instances, "new_instance_fraction": new_frac,
+                   "distinct_meshes": args.meshes, "arena_gib": arena / 2**30},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="terrain", choices=["terrain", "planet", "cube"])
+    ap.add_argument("--stage", default="fill", choices=["classify", "fill", "resolve", "frame"])
+    ap.add_argument("--traffic", type=float, default=None,
+                    help="HBM bytes per launch of the profiled stage from the byte counters, if measured")
+    ap.add_argument("--instances", type=int, default=None)
+    ap.add_argument("--meshes", type=int, default=32)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--max-batch", type=int, default=128)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 256 MiB device copies (scale of the HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel(), "copies": 5}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build"}))
+        sys.exit(2)
+    if args.mode == "single":
+        args.steps = 200 if args.steps is None else args.steps
+        args.warmup = 40 if args.warmup is None else args.warmup
+        out = run_single(args)
+        if not args.no_cpu_baseline:
+            print("# CPU reference baseline", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
+    elif args.mode == "batch":
+        args.steps = 48 if args.steps is None else args.steps
+        args.warmup = 16 if args.warmup is None else args.warmup
+        args.instances = 128 if args.instances is None else args.instances
+        out = run_batch(args)
+    else:
+        args.instances = 512 if args.instances is None else args.instances
+        out = run_serve(args)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -218,6 +218,126 @@ enum {
 };
 cbt_status cbt_time_stage(cbt_handle h, int32_t stage);
 cbt_status cbt_stage_time(cbt_handle h, int64_t* launches, double* total_ms);
+/* The same launches one by one (milliseconds each, in update order); count
+ * receives their number, CBT_E_CAPACITY when capacity is smaller. */
+cbt_status cbt_stage_times(cbt_handle h, double* out_ms, int64_t capacity, int64_t* count);
+
+/* Launch schedule of the handle's per-bisector kernels (not part of the
+ * method; results do not depend on it): rank_groups workgroups, each owning
+ * a contiguous chunk of ceil(L / rank_groups) ranks, in [16, 2048], and
+ * reduce_levels tree levels reduced inside one workgroup of the sum
+ * reduction, in [5, 10].  The default is about one workgroup per 512 pool
+ * blocks and 10 levels.  Takes effect at the next update. */
+cbt_status cbt_set_schedule(cbt_handle h, int32_t rank_groups, int32_t reduce_levels);
+cbt_status cbt_get_schedule(cbt_handle h, int32_t* rank_groups, int32_t* reduce_levels);
+
+/* ---- Batched update ------------------------------------------------------
+ * Many instances, of uneven mesh size and depth, advanced together: every
+ * stage of the Section 3.3 pipeline is one launch whose workgroups are
+ * spread over all member instances (each member keeps the schedule it had
+ * when the batch was created), optionally captured once as a HIP graph and
+ * replayed every frame.  Each member's result is the one cbt_update gives
+ * (bit for bit): instances share launches, not state.
+ *  - Memory: the caller owns a device workspace of
+ *    cbt_batch_workspace_bytes(members, n) bytes (256-byte aligned) holding
+ *    the instance descriptors, the counters and the block maps; the
+ *    library allocates pinned host staging only.
+ *  - Streams: all batch work runs on the batch's stream.  cbt_batch_create
+ *    synchronises the members' own streams; afterwards the caller must not
+ *    run work on a member concurrently with the batch.
+ *  - Graphs: with CBT_BATCH_GRAPH (needs a non-null stream) the first
+ *    update captures the kernel sequence; later updates upload the frame's
+ *    descriptors (outside the graph) and replay it. */
+typedef struct cbt_batch_s* cbt_batch;
+#define CBT_BATCH_GRAPH 1
+
+/* 0 when the member list is invalid (NULL, repeated or failed handles,
+ * n outside [1, 4096]). */
+size_t cbt_batch_workspace_bytes(const cbt_handle* members, int32_t n);
+cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_workspace,
+                            size_t workspace_bytes, void* hip_stream, int32_t flags,
+                            cbt_batch* out);
+/* One frame for every member: cameras[i], lods[i] as for cbt_update.  With
+ * stats non-NULL (n entries) it synchronises and reports device checks as
+ * CBT_E_DEVICE; otherwise it is asynchronous on the batch's stream. */
+cbt_status cbt_batch_update(cbt_batch b, const cbt_camera* cameras, const cbt_lod_params* lods,
+                            cbt_frame_stats* stats);
+/* Test hook: device_decisions[i] as for cbt_update_with_decisions. */
+cbt_status cbt_batch_update_with_decisions(cbt_batch b, const uint8_t* const* device_decisions,
+                                           cbt_frame_stats* stats);
+/* Releases the batch (not its workspace, not the members); synchronises. */
+cbt_status cbt_batch_destroy(cbt_batch b);
+
+/* ---- Serving loop ----------------------------------------------------------
+ * Tessellation-update requests (instance, camera) arrive at any time and are
+ * batched continuously: whenever one of the server's launch slots is free,
+ * every instance with a queued request and none in flight joins the next
+ * batched frame (the cbt_batch path), which runs on that slot's own stream,
+ * so batches overlap on the device.  At most one request per instance is in
+ * flight and an instance's requests run in arrival order, so its states are
+ * the ones cbt_update gives for the same cameras.
+ *  - Memory: the caller owns one device arena (256-byte aligned).  Its first
+ *    cbt_server_overhead_bytes(cfg) bytes hold the launch slots; instance
+ *    workspaces (cbt_workspace_bytes each) are carved from the rest, up to
+ *    memory_budget bytes.  An instance is admitted when its workspace fits;
+ *    otherwise idle instances (none queued, none in flight) are evicted,
+ *    least recently used first, to host snapshots and re-admitted (restored)
+ *    when a request for them arrives.  The server creates its own streams
+ *    (default priority) and pinned host staging.
+ *  - Latency of a request: from cbt_server_submit to the poll that observes
+ *    its batch finished (host steady clock); queue_ms up to its launch.
+ *  - Threads: a server is not thread-safe. */
+typedef struct cbt_server_s* cbt_server;
+
+typedef struct {
+    int64_t memory_budget;  /* bytes for instance workspaces (0: the whole arena) */
+    int32_t max_batch;      /* instances per batched launch, 1..4096            */
+    int32_t slots;          /* batches in flight, each on its own stream, 1..8  */
+    int64_t map_capacity;   /* workgroups per batched launch (all three grids)  */
+} cbt_server_config;
+
+typedef struct {
+    uint64_t tag;           /* as given to cbt_server_submit                    */
+    int64_t instance;
+    int32_t status;         /* CBT_OK, or the reason the request failed         */
+    int32_t batch_size;     /* instances in the batch that ran it               */
+    double latency_ms;
+    double queue_ms;
+    int64_t live_before;
+    int64_t live_after;
+} cbt_completion;
+
+typedef struct {
+    int64_t instances, resident, queued, in_flight;
+    int64_t requests, admissions, evictions, batches, frames;
+    int64_t bisector_updates;   /* sum of live counts over served frames */
+    int64_t bytes_resident, bytes_budget;
+} cbt_server_stats;
+
+size_t cbt_server_overhead_bytes(const cbt_server_config* cfg);   /* 0: invalid cfg */
+cbt_status cbt_server_create(const cbt_server_config* cfg, void* device_arena, size_t arena_bytes,
+                             cbt_server* out);
+/* Registers an instance (the mesh is validated and copied; lod->table must
+ * stay valid) and admits it if it fits; CBT_E_BUDGET if its workspace
+ * exceeds the whole budget. */
+cbt_status cbt_server_open(cbt_server s, const cbt_mesh* mesh, int32_t D, const cbt_lod_params* lod,
+                           int64_t* instance_id);
+cbt_status cbt_server_set_schedule(cbt_server s, int64_t instance_id, int32_t rank_groups,
+                                   int32_t reduce_levels);
+cbt_status cbt_server_submit(cbt_server s, int64_t instance_id, const cbt_camera* camera, uint64_t tag);
+/* Collects finished batches, launches new ones, and returns up to capacity
+ * completions (with wait != 0 it blocks until at least one batch ends when
+ * none is ready). */
+cbt_status cbt_server_poll(cbt_server s, int32_t wait, cbt_completion* out, int32_t capacity,
+                           int32_t* count);
+/* Runs until no request is queued or in flight (completions stay for poll). */
+cbt_status cbt_server_drain(cbt_server s);
+/* cbt_query of the instance's current state (waits for its request in
+ * flight; re-admits it if evicted). */
+cbt_status cbt_server_query(cbt_server s, int64_t instance_id, cbt_bisectors* out);
+cbt_status cbt_server_close(cbt_server s, int64_t instance_id);
+cbt_status cbt_server_get_stats(cbt_server s, cbt_server_stats* out);
+cbt_status cbt_server_destroy(cbt_server s);
 
 /* Number of live bisectors (synchronises). */
 cbt_status cbt_live_count(cbt_handle h, int64_t* out);

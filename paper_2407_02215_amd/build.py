@@ -9,7 +9,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("cbt_kernels.hip", "cbt_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("cbt_kernels.hip", "cbt_api.hip", "cbt_batch.hip", "cbt_server.hip")]
 LIB = os.path.join(HERE, "libcbt_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

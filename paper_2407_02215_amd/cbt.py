@@ -22,7 +22,9 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "invalid mesh", -3: "invalid dept
 
 EXPORTED = ["cbt_workspace_bytes", "cbt_init", "cbt_update", "cbt_update_with_decisions", "cbt_query",
             "cbt_query_decisions", "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count",
-            "cbt_destroy", "cbt_status_string", "cbt_last_error", "cbt_time_stage", "cbt_stage_time"]
+            "cbt_destroy", "cbt_status_string", "cbt_last_error", "cbt_time_stage", "cbt_stage_time",
+            "cbt_set_schedule", "cbt_get_schedule", "cbt_stage_times", "cbt_batch_workspace_bytes", "cbt_batch_create",
+            "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy"]
 
 STAGES = {"enumerate": 1, "classify": 2, "vote": 3, "budget": 4, "chain": 5, "owners": 6, "offsets": 7,
           "freelist": 8, "fill": 9, "resolve": 10, "reduce": 11, "frame": 12}
@@ -87,13 +89,23 @@ def load_library():
     lib.cbt_destroy.argtypes = [vp]
     lib.cbt_time_stage.argtypes = [vp, C.c_int32]
     lib.cbt_stage_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    lib.cbt_stage_times.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.cbt_set_schedule.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.cbt_get_schedule.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.cbt_batch_workspace_bytes.argtypes = [vp, C.c_int32]
+    lib.cbt_batch_workspace_bytes.restype = C.c_size_t
+    lib.cbt_batch_create.argtypes = [vp, C.c_int32, vp, C.c_size_t, vp, C.c_int32, C.POINTER(vp)]
+    lib.cbt_batch_update.argtypes = [vp, vp, vp, vp]
+    lib.cbt_batch_update_with_decisions.argtypes = [vp, vp, vp]
+    lib.cbt_batch_destroy.argtypes = [vp]
     lib.cbt_status_string.argtypes = [C.c_int32]
     lib.cbt_status_string.restype = C.c_char_p
     lib.cbt_last_error.argtypes = [vp]
     lib.cbt_last_error.restype = C.c_char_p
     for f in ("cbt_init", "cbt_update", "cbt_update_with_decisions", "cbt_query", "cbt_query_decisions",
               "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count", "cbt_destroy",
-              "cbt_time_stage", "cbt_stage_time"):
+              "cbt_time_stage", "cbt_stage_time", "cbt_stage_times", "cbt_set_schedule", "cbt_get_schedule", "cbt_batch_create",
+              "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy"):
         getattr(lib, f).restype = C.c_int32
     _LIB = lib
     return lib
@@ -132,7 +144,7 @@ def canonical(heap_ids, k: int):
 class Instance:
     """One bisection-update instance resident on the GPU."""
 
-    def __init__(self, mesh, depth: int, lod=None, device: str = "cuda", stream=None):
+    def __init__(self, mesh, depth: int, lod=None, device: str = "cuda", stream=None, tuned: bool = False):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -161,6 +173,11 @@ class Instance:
         self._table = None
         if lod is not None:
             self.set_lod(lod)
+        if tuned:
+            from . import tune
+            entry = tune.lookup(self.D, tune.load_table())
+            if entry is not None:
+                self.set_schedule(*entry)
 
     # -- lifecycle --------------------------------------------------------
     def close(self):
@@ -285,5 +302,258 @@ class Instance:
         self._check(self.lib.cbt_stage_time(self.h, C.byref(n), C.byref(ms)))
         return int(n.value), float(ms.value)
 
+    def stage_times(self) -> np.ndarray:
+        """Milliseconds of each timed launch since time_stage(), in order."""
+        n = C.c_int64()
+        n_total, _ = self.stage_time()
+        out = np.zeros(max(1, n_total), np.float64)
+        self._check(self.lib.cbt_stage_times(self.h, _ptr(out), out.size, C.byref(n)))
+        return out[:int(n.value)]
+
+    def set_schedule(self, rank_groups: int, reduce_levels: int = 10):
+        """Launch schedule of the per-bisector kernels (results do not depend
+        on it)."""
+        self._check(self.lib.cbt_set_schedule(self.h, int(rank_groups), int(reduce_levels)))
+
+    def schedule(self):
+        g = C.c_int32()
+        r = C.c_int32()
+        self._check(self.lib.cbt_get_schedule(self.h, C.byref(g), C.byref(r)))
+        return int(g.value), int(r.value)
+
     def canonical(self):
         return canonical(self.query()["heap_id"], self.k)
+
+
+BATCH_GRAPH = 1
+
+
+class Batch:
+    """Instances advanced together: one launch per pipeline stage for all of
+    them, optionally replayed from a captured HIP graph (cbt_batch_*)."""
+
+    def __init__(self, instances, graph: bool = True, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.members = list(instances)
+        n = len(self.members)
+        self._handles = (C.c_void_p * n)(*[m.h for m in self.members])
+        nbytes = int(self.lib.cbt_batch_workspace_bytes(self._handles, n))
+        if nbytes == 0:
+            raise CbtError(-1, self.lib.cbt_last_error(None).decode())
+        dev = self.members[0].device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.Stream(dev)
+        h = C.c_void_p()
+        st = self.lib.cbt_batch_create(self._handles, n, C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                       C.c_void_p(self.stream.cuda_stream), BATCH_GRAPH if graph else 0,
+                                       C.byref(h))
+        if st != CBT_OK:
+            raise CbtError(st, self.lib.cbt_last_error(None).decode())
+        self.h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cbt_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != CBT_OK:
+            raise CbtError(st, self.lib.cbt_last_error(None).decode())
+
+    def update(self, cameras, stats: bool = False):
+        """One frame for every member; cameras[i] for member i (each member's
+        LOD parameters are the ones set on its Instance)."""
+        assert len(cameras) == self.n
+        cams = (Camera * self.n)(*[make_camera(c) for c in cameras])
+        lods = (LodParams * self.n)(*[m._lodp for m in self.members])
+        st = (FrameStats * self.n)() if stats else None
+        self._check(self.lib.cbt_batch_update(self.h, cams, lods, st))
+        return [s.as_dict() for s in st] if stats else None
+
+    def update_with_decisions(self, decisions, stats: bool = False):
+        torch = self._torch
+        devs = []
+        for m, d in zip(self.members, decisions):
+            if isinstance(d, np.ndarray):
+                t = torch.from_numpy(np.ascontiguousarray(d, np.uint8)).to(m.device)
+            else:
+                t = d.to(m.device, torch.uint8).contiguous()
+            assert t.numel() == m.cap
+            devs.append(t)
+        self._dec_keep = devs
+        ptrs = (C.c_void_p * self.n)(*[t.data_ptr() for t in devs])
+        st = (FrameStats * self.n)() if stats else None
+        self._check(self.lib.cbt_batch_update_with_decisions(self.h, ptrs, st))
+        return [s.as_dict() for s in st] if stats else None
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("memory_budget", C.c_int64), ("max_batch", C.c_int32), ("slots", C.c_int32),
+                ("map_capacity", C.c_int64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("instance", C.c_int64), ("status", C.c_int32), ("batch_size", C.c_int32),
+                ("latency_ms", C.c_double), ("queue_ms", C.c_double), ("live_before", C.c_int64),
+                ("live_after", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "instances", "resident", "queued", "in_flight", "requests", "admissions", "evictions", "batches", "frames",
+        "bisector_updates", "bytes_resident", "bytes_budget")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+SERVER_EXPORTS = ["cbt_server_overhead_bytes", "cbt_server_create", "cbt_server_open", "cbt_server_set_schedule",
+                  "cbt_server_submit", "cbt_server_poll", "cbt_server_drain", "cbt_server_query",
+                  "cbt_server_close", "cbt_server_get_stats", "cbt_server_destroy"]
+EXPORTED += SERVER_EXPORTS
+
+
+def _server_signatures(lib):
+    vp = C.c_void_p
+    lib.cbt_server_overhead_bytes.argtypes = [C.POINTER(ServerConfig)]
+    lib.cbt_server_overhead_bytes.restype = C.c_size_t
+    lib.cbt_server_create.argtypes = [C.POINTER(ServerConfig), vp, C.c_size_t, C.POINTER(vp)]
+    lib.cbt_server_open.argtypes = [vp, C.POINTER(Mesh), C.c_int32, C.POINTER(LodParams), C.POINTER(C.c_int64)]
+    lib.cbt_server_set_schedule.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32]
+    lib.cbt_server_submit.argtypes = [vp, C.c_int64, C.POINTER(Camera), C.c_uint64]
+    lib.cbt_server_poll.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_int32)]
+    lib.cbt_server_drain.argtypes = [vp]
+    lib.cbt_server_query.argtypes = [vp, C.c_int64, C.POINTER(Bisectors)]
+    lib.cbt_server_close.argtypes = [vp, C.c_int64]
+    lib.cbt_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.cbt_server_destroy.argtypes = [vp]
+    for f in SERVER_EXPORTS[1:]:
+        getattr(lib, f).restype = C.c_int32
+
+
+class Server:
+    """Serving loop over resident instances (cbt_server_*): requests are
+    submitted as they arrive and batched continuously on the device."""
+
+    def __init__(self, arena_bytes: int, memory_budget: int = 0, max_batch: int = 128, slots: int = 2,
+                 map_capacity: int = 1 << 22, device: str = "cuda"):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        _server_signatures(self.lib)
+        self.device = torch.device(device)
+        self.cfg = ServerConfig(int(memory_budget), int(max_batch), int(slots), int(map_capacity))
+        over = int(self.lib.cbt_server_overhead_bytes(C.byref(self.cfg)))
+        if over == 0:
+            raise CbtError(-1, "invalid server configuration")
+        self.arena = torch.empty(int(arena_bytes) + over, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        st = self.lib.cbt_server_create(C.byref(self.cfg), C.c_void_p(self.arena.data_ptr()), self.arena.numel(),
+                                        C.byref(h))
+        if st != CBT_OK:
+            raise CbtError(st, self.lib.cbt_last_error(None).decode())
+        self.h = h
+        self._tables = {}
+        self._meta = {}
+        self._buf = (Completion * 4096)()
+
+    def _check(self, st):
+        if st != CBT_OK:
+            raise CbtError(st, self.lib.cbt_last_error(None).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cbt_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open(self, mesh, depth: int, lod) -> int:
+        torch = self._torch
+        table = None
+        if lod.table is not None:
+            key = id(lod.table)
+            if key not in self._tables:
+                self._tables[key] = (lod.table, torch.from_numpy(np.ascontiguousarray(lod.table, np.float32)).to(self.device))
+            table = self._tables[key][1]
+        lp = LodParams(int(lod.mode), float(lod.split_px), float(lod.merge_px),
+                       C.c_void_p(table.data_ptr()) if table is not None else None, int(lod.table_res),
+                       float(lod.amplitude))
+        arrays = [np.ascontiguousarray(a, np.int32) for a in (mesh.twin, mesh.next, mesh.prev, mesh.vert)]
+        pos = np.ascontiguousarray(mesh.pos, np.float32)
+        m = Mesh(int(mesh.H), *(_ptr(a) for a in arrays), int(pos.shape[0]), _ptr(pos))
+        iid = C.c_int64()
+        self._check(self.lib.cbt_server_open(self.h, C.byref(m), int(depth), C.byref(lp), C.byref(iid)))
+        self._meta[int(iid.value)] = (int(mesh.H), int(depth))
+        return int(iid.value)
+
+    def set_schedule(self, iid: int, rank_groups: int, reduce_levels: int = 10):
+        self._check(self.lib.cbt_server_set_schedule(self.h, int(iid), int(rank_groups), int(reduce_levels)))
+
+    def submit(self, iid: int, camera, tag: int = 0):
+        cam = make_camera(camera)
+        self._check(self.lib.cbt_server_submit(self.h, int(iid), C.byref(cam), int(tag)))
+
+    def poll(self, wait: bool = False):
+        n = C.c_int32()
+        out = []
+        while True:
+            self._check(self.lib.cbt_server_poll(self.h, 1 if wait else 0, self._buf, len(self._buf), C.byref(n)))
+            out += [self._buf[i].as_dict() for i in range(n.value)]
+            if n.value < len(self._buf):
+                return out
+            wait = False
+
+    def drain(self):
+        self._check(self.lib.cbt_server_drain(self.h))
+        return self.poll()
+
+    def query(self, iid: int, tree: bool = False):
+        H, D = self._meta[int(iid)]
+        b = Bisectors()
+        b.capacity = 0
+        self._check(self.lib.cbt_server_query(self.h, int(iid), C.byref(b)))
+        L = int(b.count)
+        slot = np.zeros(L, np.int32)
+        ids = np.zeros(L, np.uint64)
+        tw = np.zeros(L, np.int32)
+        nx = np.zeros(L, np.int32)
+        pv = np.zeros(L, np.int32)
+        b2 = Bisectors(L, 0, _ptr(slot), _ptr(ids), _ptr(tw), _ptr(nx), _ptr(pv), None, None)
+        heap = None
+        if tree:
+            heap = np.zeros(2 << D, np.uint32)
+            b2.tree = _ptr(heap)
+        self._check(self.lib.cbt_server_query(self.h, int(iid), C.byref(b2)))
+        out = {"count": L, "slot": slot, "heap_id": ids, "twin": tw, "next": nx, "prev": pv}
+        if tree:
+            out["tree"] = heap
+        return out
+
+    def stats(self):
+        s = ServerStats()
+        self._check(self.lib.cbt_server_get_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def close_instance(self, iid: int):
+        self._check(self.lib.cbt_server_close(self.h, int(iid)))
+        self._meta.pop(int(iid), None)

@@ -3,8 +3,7 @@
 // constants, and the query / snapshot paths.  All device work is done by the
 // kernels of cbt_kernels.hip on the caller's stream.
 
-#include "cbt.h"
-#include "cbt_internal.h"
+#include "cbt_host.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -17,27 +16,13 @@ using cbtk::Counters;
 using cbtk::LodK;
 using cbtk::Pool;
 
-struct cbt_instance {
-    Pool P;
-    hipStream_t stream;
-    char* ws;
-    size_t ws_bytes;
-    int failed;
-    int last_frame_valid;   // the live list still describes the last frame
-    uint32_t last_L;
-    Counters* hctr;         // pinned host mirror of the device counters
-    LodK wk;                // world-position parameters the vertex cache holds
-    int timed_stage;        // stage wrapped by event pairs, 0 = none
-    int n_timed;            // event pairs recorded so far
-    std::vector<hipEvent_t> events;   // 2 per timed launch
-    char err[512];
-};
-
 static constexpr int kMaxTimed = 8192;
 
 static thread_local char g_err[512] = "";
 
-static cbt_status fail(cbt_handle h, cbt_status st, const char* fmt, ...)
+namespace cbth {
+
+cbt_status fail(cbt_handle h, cbt_status st, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -49,17 +34,97 @@ static cbt_status fail(cbt_handle h, cbt_status st, const char* fmt, ...)
     return st;
 }
 
-static cbt_status hip_fail(cbt_handle h, hipError_t e, const char* what)
+cbt_status hip_fail(cbt_handle h, hipError_t e, const char* what)
 {
     if (h) h->failed = 1;
     return fail(h, CBT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(h, expr, what)                        \
-    do {                                              \
-        hipError_t e_ = (expr);                       \
-        if (e_ != hipSuccess) return hip_fail(h, e_, what); \
-    } while (0)
+// Frame constants in double precision, each rounded once to float.
+void make_lodk(const cbt_camera* c, const cbt_lod_params* lp, LodK* K)
+{
+    const double f[3] = {c->fwd[0], c->fwd[1], c->fwd[2]};
+    const double u[3] = {c->up[0], c->up[1], c->up[2]};
+    const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    const double fw[3] = {f[0] / fl, f[1] / fl, f[2] / fl};
+    double r[3] = {fw[1] * u[2] - fw[2] * u[1], fw[2] * u[0] - fw[0] * u[2], fw[0] * u[1] - fw[1] * u[0]};
+    const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    r[0] /= rl;
+    r[1] /= rl;
+    r[2] /= rl;
+    const double up[3] = {r[1] * fw[2] - r[2] * fw[1], r[2] * fw[0] - r[0] * fw[2], r[0] * fw[1] - r[1] * fw[0]};
+    const double th = std::tan(0.5 * (double)c->fovy);
+    const double focal = 0.5 * (double)c->height / th;
+    for (int i = 0; i < 3; ++i) {
+        K->cam[i] = c->pos[i];
+        K->right[i] = (float)r[i];
+        K->up[i] = (float)up[i];
+        K->fwd[i] = (float)fw[i];
+    }
+    K->f2 = (float)(focal * focal);
+    K->t2s = (float)((double)lp->split_px * (double)lp->split_px);
+    K->t2m = (float)((double)lp->merge_px * (double)lp->merge_px);
+    K->tx = (float)(th * (double)c->width / (double)c->height);
+    K->ty = (float)th;
+    K->znear = c->znear;
+    K->table = lp->table;
+    K->res = lp->table_res;
+    K->amp = lp->amplitude;
+    K->mode = lp->mode;
+}
+
+cbt_status check_lod(cbt_handle h, const cbt_camera* c, const cbt_lod_params* lp)
+{
+    if (!c || !lp) return fail(h, CBT_E_ARG, "camera and LOD parameters are required");
+    if (lp->mode < CBT_MODE_FLAT || lp->mode > CBT_MODE_HEIGHTFIELD) return fail(h, CBT_E_ARG, "unknown LOD mode %d", lp->mode);
+    if (lp->mode != CBT_MODE_FLAT && (!lp->table || lp->table_res < 2))
+        return fail(h, CBT_E_ARG, "LOD mode %d needs a device table of resolution >= 2", lp->mode);
+    if (c->width <= 0 || c->height <= 0 || !(c->fovy > 0.0f && c->fovy < 3.14159f))
+        return fail(h, CBT_E_ARG, "invalid viewport or field of view");
+    return CBT_OK;
+}
+
+bool world_changed(const LodK& a, const LodK& b)
+{
+    return a.mode != b.mode || a.table != b.table || a.res != b.res || a.amp != b.amp;
+}
+
+cbt_status stats_from_counters(cbt_handle h, const Counters& c, cbt_frame_stats* stats)
+{
+    if (c.err) {
+        h->failed = 1;
+        return fail(h, CBT_E_DEVICE, "device check failed (flags 0x%x)", c.err);
+    }
+    if (!stats) return CBT_OK;
+    std::memset(stats, 0, sizeof *stats);
+    stats->live_before = c.L;
+    stats->free_before = c.F;
+    stats->split_requests = c.stat[cbtk::kStSplitReq];
+    stats->split_accepted = c.stat[cbtk::kStSplitAcc];
+    stats->merge_requests = c.stat[cbtk::kStMergeReq];
+    stats->merge_configs = c.stat[cbtk::kStMergeCfg];
+    stats->merge_accepted = c.stat[cbtk::kStMergeAcc];
+    stats->merges_executed = c.stat[cbtk::kStMergeExec];
+    stats->split_consumed = c.stat[cbtk::kStSplitConsumed];
+    stats->allocations = c.N;
+    stats->frees = c.stat[cbtk::kStFrees];
+    stats->live_after = (int64_t)c.L + c.N - c.stat[cbtk::kStFrees];
+    return CBT_OK;
+}
+
+// Default schedule: about 512 pool blocks per rank workgroup, within the
+// grid limits.
+uint32_t default_rank_groups(int32_t D)
+{
+    const uint64_t g = (1ull << D) / 512;
+    return (uint32_t)(g < cbtk::kMinRankGroups ? cbtk::kMinRankGroups
+                                               : (g > cbtk::kMaxRankGroups ? cbtk::kMaxRankGroups : g));
+}
+
+}  // namespace cbth
+
+using cbth::fail;
+using cbth::hip_fail;
 
 static int ceil_log2(int64_t n)
 {
@@ -69,7 +134,7 @@ static int ceil_log2(int64_t n)
 }
 
 // Section 2.1 halfedge requirements (see cbt_mesh in cbt.h).
-static cbt_status validate_mesh(const cbt_mesh* m)
+cbt_status cbth::validate_mesh(const cbt_mesh* m)
 {
     if (!m || !m->twin || !m->next || !m->prev || !m->vert || !m->pos)
         return fail(nullptr, CBT_E_ARG, "mesh arrays must not be NULL");
@@ -150,48 +215,12 @@ static void root_triangles(const cbt_mesh* m, std::vector<float>& out)
     }
 }
 
-// Frame constants in double precision, each rounded once to float.
-static void make_lodk(const cbt_camera* c, const cbt_lod_params* lp, LodK* K)
+// Device scratch that is free between frames: the work-list region
+// (8 bytes per pool block).
+static char* list_scratch(const Pool& P, size_t* bytes)
 {
-    const double f[3] = {c->fwd[0], c->fwd[1], c->fwd[2]};
-    const double u[3] = {c->up[0], c->up[1], c->up[2]};
-    const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-    const double fw[3] = {f[0] / fl, f[1] / fl, f[2] / fl};
-    double r[3] = {fw[1] * u[2] - fw[2] * u[1], fw[2] * u[0] - fw[0] * u[2], fw[0] * u[1] - fw[1] * u[0]};
-    const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    r[0] /= rl;
-    r[1] /= rl;
-    r[2] /= rl;
-    const double up[3] = {r[1] * fw[2] - r[2] * fw[1], r[2] * fw[0] - r[0] * fw[2], r[0] * fw[1] - r[1] * fw[0]};
-    const double th = std::tan(0.5 * (double)c->fovy);
-    const double focal = 0.5 * (double)c->height / th;
-    for (int i = 0; i < 3; ++i) {
-        K->cam[i] = c->pos[i];
-        K->right[i] = (float)r[i];
-        K->up[i] = (float)up[i];
-        K->fwd[i] = (float)fw[i];
-    }
-    K->f2 = (float)(focal * focal);
-    K->t2s = (float)((double)lp->split_px * (double)lp->split_px);
-    K->t2m = (float)((double)lp->merge_px * (double)lp->merge_px);
-    K->tx = (float)(th * (double)c->width / (double)c->height);
-    K->ty = (float)th;
-    K->znear = c->znear;
-    K->table = lp->table;
-    K->res = lp->table_res;
-    K->amp = lp->amplitude;
-    K->mode = lp->mode;
-}
-
-static cbt_status check_lod(cbt_handle h, const cbt_camera* c, const cbt_lod_params* lp)
-{
-    if (!c || !lp) return fail(h, CBT_E_ARG, "camera and LOD parameters are required");
-    if (lp->mode < CBT_MODE_FLAT || lp->mode > CBT_MODE_HEIGHTFIELD) return fail(h, CBT_E_ARG, "unknown LOD mode %d", lp->mode);
-    if (lp->mode != CBT_MODE_FLAT && (!lp->table || lp->table_res < 2))
-        return fail(h, CBT_E_ARG, "LOD mode %d needs a device table of resolution >= 2", lp->mode);
-    if (c->width <= 0 || c->height <= 0 || !(c->fovy > 0.0f && c->fovy < 3.14159f))
-        return fail(h, CBT_E_ARG, "invalid viewport or field of view");
-    return CBT_OK;
+    *bytes = sizeof(uint2) * (size_t)P.cap;
+    return reinterpret_cast<char*>(P.list);
 }
 
 extern "C" {
@@ -207,7 +236,7 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
 {
     if (!out) return fail(nullptr, CBT_E_ARG, "output handle pointer is NULL");
     *out = nullptr;
-    cbt_status st = validate_mesh(mesh);
+    cbt_status st = cbth::validate_mesh(mesh);
     if (st) return st;
     const int k = ceil_log2(mesh->H);
     if (D < 5 || D > 30 || D < k) return fail(nullptr, CBT_E_DEPTH, "depth %d outside [max(5, ceil(log2 H)=%d), 30]", D, k);
@@ -223,19 +252,25 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
     h->ws_bytes = workspace_bytes;
     cbtk::workspace_layout(mesh->H, D, &h->P, h->ws);
     h->P.k = k;
+    h->P.G = cbth::default_rank_groups(D);
+    h->P.sub = cbtk::kMaxReduceSub;
     if (hipHostMalloc(reinterpret_cast<void**>(&h->hctr), sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
         delete h;
         return fail(nullptr, CBT_E_DEVICE, "pinned host allocation failed");
     }
     std::memset(h->hctr, 0, sizeof(Counters));
 
-    // Section 3.3 "Initialization": roots in blocks 0..H-1
+    // Section 3.3 "Initialization": roots in blocks 0..H-1, packed as
+    // (id low, id high, twin, next, prev)
     const int32_t H = mesh->H;
-    std::vector<uint64_t> ids(H);
-    std::vector<int4> links(H);
+    std::vector<uint32_t> recs(5 * (size_t)H);
     for (int32_t i = 0; i < H; ++i) {
-        ids[i] = (uint64_t(1) << k) + (uint64_t)i;
-        links[i] = make_int4(mesh->twin[i], mesh->next[i], mesh->prev[i], 0);
+        const uint64_t id = (uint64_t(1) << k) + (uint64_t)i;
+        recs[5 * (size_t)i + 0] = (uint32_t)id;
+        recs[5 * (size_t)i + 1] = (uint32_t)(id >> 32);
+        recs[5 * (size_t)i + 2] = (uint32_t)mesh->twin[i];
+        recs[5 * (size_t)i + 3] = (uint32_t)mesh->next[i];
+        recs[5 * (size_t)i + 4] = (uint32_t)mesh->prev[i];
     }
     std::vector<uint32_t> words((H + 31) / 32, 0u);
     for (int32_t i = 0; i < H; ++i) words[i >> 5] |= 1u << (i & 31);
@@ -244,6 +279,8 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
 
     const Pool& P = h->P;
     hipStream_t s = h->stream;
+    // the flat-vertex region (48 bytes per block, cap >= H) stages the roots
+    uint32_t* staging = reinterpret_cast<uint32_t*>(P.vflat);
     cbt_status rc = CBT_OK;
 #define INIT_TRY(expr, what)                      \
     do {                                          \
@@ -254,24 +291,26 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
         }                                         \
     } while (0)
     INIT_TRY(hipMemsetAsync(P.id, 0, sizeof(uint64_t) * P.cap, s), "clear IDs");
-    INIT_TRY(hipMemsetAsync(P.link, 0xff, sizeof(int4) * P.cap, s), "clear links");
-    INIT_TRY(hipMemsetAsync(P.bits, 0, sizeof(uint32_t) * P.W, s), "clear bitfield");
+    INIT_TRY(hipMemsetAsync(P.link, 0, sizeof(int4) * P.cap, s), "clear pointers");
     INIT_TRY(hipMemsetAsync(P.fwd, 0xff, sizeof(uint4) * P.cap, s), "clear forwarding");
+    INIT_TRY(hipMemsetAsync(P.lpre, 0, sizeof(uint32_t) * P.cap, s), "clear list offsets");
+    INIT_TRY(hipMemsetAsync(P.bits, 0, sizeof(uint32_t) * P.W, s), "clear bitfield");
     INIT_TRY(hipMemsetAsync(P.cmd, 0, sizeof(uint32_t) * P.cap, s), "clear commands");
     INIT_TRY(hipMemsetAsync(P.live, 0, sizeof(uint32_t) * P.cap, s), "clear rank list");
     INIT_TRY(hipMemsetAsync(P.freel, 0, sizeof(uint32_t) * P.cap, s), "clear free list");
-    INIT_TRY(hipMemsetAsync(P.list, 0, sizeof(uint32_t) * P.cap, s), "clear work lists");
-    INIT_TRY(hipMemsetAsync(P.lcnt, 0, sizeof(uint32_t) * cbtk::kRankGrid, s), "clear list lengths");
+    INIT_TRY(hipMemsetAsync(P.list, 0, sizeof(uint2) * P.cap, s), "clear work lists");
+    INIT_TRY(hipMemsetAsync(P.lcnt, 0, sizeof(uint32_t) * cbtk::kMaxRankGroups, s), "clear list lengths");
+    INIT_TRY(hipMemsetAsync(P.part, 0, sizeof(uint2) * cbtk::kMaxRankGroups, s), "clear partials");
+    INIT_TRY(hipMemsetAsync(P.ctr, 0, sizeof(Counters), s), "clear counters");
+    INIT_TRY(hipMemcpyAsync(staging, recs.data(), sizeof(uint32_t) * recs.size(), hipMemcpyHostToDevice, s), "upload roots");
+    INIT_TRY(cbtk::launch_import_records(P, 0, (uint32_t)H, staging, s), "root records");
     INIT_TRY(hipMemsetAsync(P.vflat, 0, sizeof(float4) * 3 * (size_t)P.cap, s), "clear vertex cache");
     INIT_TRY(hipMemsetAsync(P.vworld, 0, sizeof(float4) * 3 * (size_t)P.cap, s), "clear vertex cache");
-    INIT_TRY(hipMemsetAsync(P.ctr, 0, sizeof(Counters), s), "clear counters");
-    INIT_TRY(hipMemcpyAsync(P.id, ids.data(), sizeof(uint64_t) * H, hipMemcpyHostToDevice, s), "upload IDs");
-    INIT_TRY(hipMemcpyAsync(P.link, links.data(), sizeof(int4) * H, hipMemcpyHostToDevice, s), "upload links");
     INIT_TRY(hipMemcpyAsync(P.bits, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice, s), "upload bits");
-    INIT_TRY(hipMemcpyAsync(P.root, roots.data(), sizeof(float) * roots.size(), hipMemcpyHostToDevice, s), "upload roots");
-    INIT_TRY(cbtk::launch_reduce(P, s), "sum reduction");
+    INIT_TRY(hipMemcpyAsync(P.root, roots.data(), sizeof(float) * roots.size(), hipMemcpyHostToDevice, s), "upload root triangles");
     std::memset(&h->wk, 0, sizeof h->wk);   // flat world positions until LOD parameters arrive
-    INIT_TRY(cbtk::launch_refresh(P, h->wk, 1, s), "vertex cache");
+    INIT_TRY(cbtk::launch_reduce(cbtk::single_launch(P, h->wk, nullptr), s), "sum reduction");
+    INIT_TRY(cbtk::launch_refresh(cbtk::single_launch(P, h->wk, nullptr), 1, s), "vertex cache");
     INIT_TRY(hipStreamSynchronize(s), "init synchronise");
 #undef INIT_TRY
     *out = h;
@@ -323,38 +362,23 @@ static cbt_status finish_frame(cbt_handle h, cbt_frame_stats* stats)
     if (!stats) return CBT_OK;
     cbt_status st = read_counters(h);
     if (st) return st;
-    const Counters& c = *h->hctr;
-    h->last_L = c.L;
-    std::memset(stats, 0, sizeof *stats);
-    stats->live_before = c.L;
-    stats->free_before = c.F;
-    stats->split_requests = c.stat[cbtk::kStSplitReq];
-    stats->split_accepted = c.stat[cbtk::kStSplitAcc];
-    stats->merge_requests = c.stat[cbtk::kStMergeReq];
-    stats->merge_configs = c.stat[cbtk::kStMergeCfg];
-    stats->merge_accepted = c.stat[cbtk::kStMergeAcc];
-    stats->merges_executed = c.stat[cbtk::kStMergeExec];
-    stats->split_consumed = c.stat[cbtk::kStSplitConsumed];
-    stats->allocations = c.N;
-    stats->frees = c.stat[cbtk::kStFrees];
-    stats->live_after = (int64_t)c.L + c.N - c.stat[cbtk::kStFrees];
-    return CBT_OK;
+    return cbth::stats_from_counters(h, *h->hctr, stats);
 }
 
 cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod, cbt_frame_stats* stats)
 {
     if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
     if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
-    cbt_status st = check_lod(h, camera, lod);
+    cbt_status st = cbth::check_lod(h, camera, lod);
     if (st) return st;
     LodK K;
-    make_lodk(camera, lod, &K);
-    if (K.mode != h->wk.mode || K.table != h->wk.table || K.res != h->wk.res || K.amp != h->wk.amp) {
+    cbth::make_lodk(camera, lod, &K);
+    if (cbth::world_changed(K, h->wk)) {
         // new world-position parameters: recompute the cached world positions
         h->wk = K;
-        HIP_TRY(h, cbtk::launch_refresh(h->P, K, 0, h->stream), "vertex cache");
+        HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), 0, h->stream), "vertex cache");
     }
-    HIP_TRY(h, cbtk::launch_frame(h->P, K, nullptr, h->stream, next_events(h)), "frame launch");
+    HIP_TRY(h, cbtk::launch_frame(cbtk::single_launch(h->P, K, nullptr), h->stream, next_events(h)), "frame launch");
     return finish_frame(h, stats);
 }
 
@@ -363,9 +387,30 @@ cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisio
     if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
     if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
     if (!device_decisions) return fail(h, CBT_E_ARG, "decision array is NULL");
-    const LodK K = h->wk;   // new vertices keep the cached world-position parameters
-    HIP_TRY(h, cbtk::launch_frame(h->P, K, device_decisions, h->stream, next_events(h)), "frame launch");
+    // new vertices keep the cached world-position parameters
+    HIP_TRY(h, cbtk::launch_frame(cbtk::single_launch(h->P, h->wk, device_decisions), h->stream, next_events(h)),
+            "frame launch");
     return finish_frame(h, stats);
+}
+
+cbt_status cbt_set_schedule(cbt_handle h, int32_t rank_groups, int32_t reduce_levels)
+{
+    if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
+    if (rank_groups < cbtk::kMinRankGroups || rank_groups > cbtk::kMaxRankGroups)
+        return fail(h, CBT_E_ARG, "rank_groups %d outside [%d, %d]", rank_groups, cbtk::kMinRankGroups, cbtk::kMaxRankGroups);
+    if (reduce_levels < cbtk::kMinReduceSub || reduce_levels > cbtk::kMaxReduceSub)
+        return fail(h, CBT_E_ARG, "reduce_levels %d outside [%d, %d]", reduce_levels, cbtk::kMinReduceSub, cbtk::kMaxReduceSub);
+    h->P.G = (uint32_t)rank_groups;
+    h->P.sub = reduce_levels;
+    return CBT_OK;
+}
+
+cbt_status cbt_get_schedule(cbt_handle h, int32_t* rank_groups, int32_t* reduce_levels)
+{
+    if (!h || !rank_groups || !reduce_levels) return fail(h, CBT_E_ARG, "NULL argument");
+    *rank_groups = (int32_t)h->P.G;
+    *reduce_levels = h->P.sub;
+    return CBT_OK;
 }
 
 cbt_status cbt_time_stage(cbt_handle h, int32_t stage)
@@ -393,6 +438,20 @@ cbt_status cbt_stage_time(cbt_handle h, int64_t* launches, double* total_ms)
     return CBT_OK;
 }
 
+cbt_status cbt_stage_times(cbt_handle h, double* out_ms, int64_t capacity, int64_t* count)
+{
+    if (!h || !count || (capacity > 0 && !out_ms) || capacity < 0) return fail(h, CBT_E_ARG, "invalid argument");
+    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    *count = h->n_timed;
+    if (capacity < h->n_timed) return fail(h, CBT_E_CAPACITY, "capacity %lld < %d timed launches", (long long)capacity, h->n_timed);
+    for (int i = 0; i < h->n_timed; ++i) {
+        float ms = 0.0f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, h->events[2 * (size_t)i], h->events[2 * (size_t)i + 1]), "event time");
+        out_ms[i] = ms;
+    }
+    return CBT_OK;
+}
+
 cbt_status cbt_live_count(cbt_handle h, int64_t* out)
 {
     if (!h || !out) return fail(h, CBT_E_ARG, "NULL argument");
@@ -410,16 +469,15 @@ cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
     const Pool& P = h->P;
     hipStream_t s = h->stream;
     h->last_frame_valid = 0;
-    HIP_TRY(h, cbtk::launch_enumerate(P, s), "enumerate");
+    HIP_TRY(h, cbtk::launch_enumerate(cbtk::single_launch(P, h->wk, nullptr), s), "enumerate");
     cbt_status st = read_counters(h);
     if (st) return st;
     const uint32_t L = h->hctr->L;
     out->count = L;
     const bool per = out->slot || out->heap_id || out->twin || out->next || out->prev || out->vertices;
     if (per && out->capacity < (int64_t)L) return fail(h, CBT_E_CAPACITY, "capacity %lld < %u live bisectors", (long long)out->capacity, L);
-    char* scratch = reinterpret_cast<char*>(P.fwd);   // 16 * cap bytes, free between frames
-    const size_t scratch_bytes = 16 * (size_t)P.cap;
-    static_assert(sizeof(uint4) == 16, "forwarding record size");
+    size_t scratch_bytes;
+    char* scratch = list_scratch(P, &scratch_bytes);
     if (out->slot && L)
         HIP_TRY(h, hipMemcpyAsync(out->slot, P.live, sizeof(uint32_t) * L, hipMemcpyDeviceToHost, s), "copy slots");
     if (out->heap_id && L) {
@@ -429,9 +487,14 @@ cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
     }
     if ((out->twin || out->next || out->prev) && L) {
         std::vector<int32_t> tmp(3 * (size_t)L);
-        HIP_TRY(h, cbtk::launch_gather_links(P, 0, L, reinterpret_cast<int32_t*>(scratch), s), "gather links");
-        HIP_TRY(h, hipMemcpyAsync(tmp.data(), scratch, sizeof(int32_t) * 3 * L, hipMemcpyDeviceToHost, s), "copy links");
-        HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+        const uint32_t chunk = (uint32_t)(scratch_bytes / (3 * sizeof(int32_t)));
+        for (uint32_t r0 = 0; r0 < L; r0 += chunk) {
+            const uint32_t n = (L - r0) < chunk ? (L - r0) : chunk;
+            HIP_TRY(h, cbtk::launch_gather_links(P, r0, n, reinterpret_cast<int32_t*>(scratch), s), "gather links");
+            HIP_TRY(h, hipMemcpyAsync(tmp.data() + 3 * (size_t)r0, scratch, sizeof(int32_t) * 3 * n, hipMemcpyDeviceToHost, s),
+                    "copy links");
+            HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+        }
         for (uint32_t i = 0; i < L; ++i) {
             if (out->twin) out->twin[i] = tmp[3 * (size_t)i];
             if (out->next) out->next[i] = tmp[3 * (size_t)i + 1];
@@ -442,13 +505,14 @@ cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
         const uint32_t chunk = (uint32_t)(scratch_bytes / (9 * sizeof(float)));
         for (uint32_t r0 = 0; r0 < L; r0 += chunk) {
             const uint32_t n = (L - r0) < chunk ? (L - r0) : chunk;
-            HIP_TRY(h, cbtk::launch_gather_vertices(P, r0, n, reinterpret_cast<float*>(scratch), s), "decode vertices");
+            HIP_TRY(h, cbtk::launch_gather_vertices(P, r0, n, reinterpret_cast<float*>(scratch), s), "gather vertices");
             HIP_TRY(h, hipMemcpyAsync(out->vertices + 9 * (size_t)r0, scratch, sizeof(float) * 9 * n, hipMemcpyDeviceToHost, s),
                     "copy vertices");
             HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
         }
     }
     if (out->tree) {
+        static_assert(sizeof(uint2) == 2 * sizeof(uint32_t), "scratch holds the 2^(D+1) heap");
         HIP_TRY(h, cbtk::launch_export_heap(P, reinterpret_cast<uint32_t*>(scratch), s), "export tree");
         HIP_TRY(h, hipMemcpyAsync(out->tree, scratch, sizeof(uint32_t) * 2 * (size_t)P.cap, hipMemcpyDeviceToHost, s), "copy tree");
     }
@@ -475,19 +539,28 @@ cbt_status cbt_snapshot(cbt_handle h, uint64_t* heap_id, int32_t* twin, int32_t*
     if (!h || !heap_id || !twin || !next || !prev) return fail(h, CBT_E_ARG, "NULL argument");
     if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
     const Pool& P = h->P;
-    std::vector<int4> links(P.cap);
+    size_t scratch_bytes;
+    uint32_t* scratch = reinterpret_cast<uint32_t*>(list_scratch(P, &scratch_bytes));
+    const uint32_t chunk = (uint32_t)(scratch_bytes / (5 * sizeof(uint32_t)));
+    std::vector<uint32_t> recs(5 * (size_t)P.cap);
     std::vector<uint32_t> words(P.W);
-    HIP_TRY(h, hipMemcpyAsync(heap_id, P.id, sizeof(uint64_t) * P.cap, hipMemcpyDeviceToHost, h->stream), "copy IDs");
-    HIP_TRY(h, hipMemcpyAsync(links.data(), P.link, sizeof(int4) * P.cap, hipMemcpyDeviceToHost, h->stream), "copy links");
     HIP_TRY(h, hipMemcpyAsync(words.data(), P.bits, sizeof(uint32_t) * P.W, hipMemcpyDeviceToHost, h->stream), "copy bits");
-    HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    for (uint32_t b0 = 0; b0 < P.cap; b0 += chunk) {
+        const uint32_t n = (P.cap - b0) < chunk ? (P.cap - b0) : chunk;
+        HIP_TRY(h, cbtk::launch_export_records(P, b0, n, scratch, h->stream), "export records");
+        HIP_TRY(h, hipMemcpyAsync(recs.data() + 5 * (size_t)b0, scratch, sizeof(uint32_t) * 5 * n, hipMemcpyDeviceToHost,
+                                  h->stream), "copy records");
+        HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    }
     for (uint32_t i = 0; i < P.cap; ++i) {
         const bool live = (words[i >> 5] >> (i & 31)) & 1u;
-        if (!live) heap_id[i] = 0;
-        twin[i] = live ? links[i].x : -1;
-        next[i] = live ? links[i].y : -1;
-        prev[i] = live ? links[i].z : -1;
+        const uint32_t* r = recs.data() + 5 * (size_t)i;
+        heap_id[i] = live ? ((uint64_t)r[0] | ((uint64_t)r[1] << 32)) : 0;
+        twin[i] = live ? (int32_t)r[2] : -1;
+        next[i] = live ? (int32_t)r[3] : -1;
+        prev[i] = live ? (int32_t)r[4] : -1;
     }
+    h->last_frame_valid = 0;
     return CBT_OK;
 }
 
@@ -497,22 +570,36 @@ cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twi
     if (!h || !heap_id || !twin || !next || !prev) return fail(h, CBT_E_ARG, "NULL argument");
     if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
     const Pool& P = h->P;
-    std::vector<int4> links(P.cap);
+    std::vector<uint32_t> recs(5 * (size_t)P.cap);
     for (uint32_t i = 0; i < P.cap; ++i) {
+        uint32_t* r = recs.data() + 5 * (size_t)i;
+        r[0] = (uint32_t)heap_id[i];
+        r[1] = (uint32_t)(heap_id[i] >> 32);
         if (heap_id[i]) {
             const int32_t t = twin[i], n = next[i], p = prev[i];
             if (t < -1 || t >= (int64_t)P.cap || n < -1 || n >= (int64_t)P.cap || p < -1 || p >= (int64_t)P.cap)
                 return fail(h, CBT_E_ARG, "restore: pointer of slot %u out of range", i);
-            links[i] = make_int4(t, n, p, 0);
+            r[2] = (uint32_t)t;
+            r[3] = (uint32_t)n;
+            r[4] = (uint32_t)p;
         } else {
-            links[i] = make_int4(-1, -1, -1, 0);
+            r[2] = r[3] = r[4] = 0xffffffffu;
         }
     }
-    HIP_TRY(h, hipMemcpyAsync(P.id, heap_id, sizeof(uint64_t) * P.cap, hipMemcpyHostToDevice, h->stream), "upload IDs");
-    HIP_TRY(h, hipMemcpyAsync(P.link, links.data(), sizeof(int4) * P.cap, hipMemcpyHostToDevice, h->stream), "upload links");
+    size_t scratch_bytes;
+    uint32_t* scratch = reinterpret_cast<uint32_t*>(list_scratch(P, &scratch_bytes));
+    const uint32_t chunk = (uint32_t)(scratch_bytes / (5 * sizeof(uint32_t)));
+    for (uint32_t b0 = 0; b0 < P.cap; b0 += chunk) {
+        const uint32_t n = (P.cap - b0) < chunk ? (P.cap - b0) : chunk;
+        HIP_TRY(h, hipMemcpyAsync(scratch, recs.data() + 5 * (size_t)b0, sizeof(uint32_t) * 5 * n, hipMemcpyHostToDevice,
+                                  h->stream), "upload records");
+        HIP_TRY(h, cbtk::launch_import_records(P, b0, n, scratch, h->stream), "import records");
+        HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
+    }
+    const cbtk::Launch X = cbtk::single_launch(P, h->wk, nullptr);
     HIP_TRY(h, cbtk::launch_bits_from_ids(P, h->stream), "bitfield");
-    HIP_TRY(h, cbtk::launch_reduce(P, h->stream), "sum reduction");
-    HIP_TRY(h, cbtk::launch_refresh(P, h->wk, 1, h->stream), "vertex cache");
+    HIP_TRY(h, cbtk::launch_reduce(X, h->stream), "sum reduction");
+    HIP_TRY(h, cbtk::launch_refresh(X, 1, h->stream), "vertex cache");
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
     h->last_frame_valid = 0;
     return CBT_OK;
@@ -523,10 +610,10 @@ cbt_status cbt_frame_constants(cbt_handle h, const cbt_camera* camera, const cbt
     if (!out18) return fail(h, CBT_E_ARG, "NULL output");
     cbt_lod_params lp = lod ? *lod : cbt_lod_params{CBT_MODE_FLAT, 1.0f, 1.0f, nullptr, 0, 0.0f};
     lp.mode = CBT_MODE_FLAT;   // the table is irrelevant for the constants
-    cbt_status st = check_lod(h, camera, &lp);
+    cbt_status st = cbth::check_lod(h, camera, &lp);
     if (st) return st;
     LodK K;
-    make_lodk(camera, &lp, &K);
+    cbth::make_lodk(camera, &lp, &K);
     const float v[18] = {K.cam[0], K.cam[1], K.cam[2], K.right[0], K.right[1], K.right[2], K.up[0], K.up[1], K.up[2],
                          K.fwd[0], K.fwd[1], K.fwd[2], K.f2, K.t2s, K.t2m, K.tx, K.ty, K.znear};
     std::memcpy(out18, v, sizeof v);

@@ -8,10 +8,14 @@
 
 namespace cbtk {
 
-constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
-constexpr int kRankGrid = 2048;   // persistent workgroups of the per-bisector kernels (8 per CU)
-constexpr int kWordsPerBlock = 1024;  // bitfield words per workgroup (enumeration)
-constexpr int kReduceSub = 10;    // tree levels reduced inside one workgroup
+constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
+constexpr int kMaxRankGroups = 2048;   // rank workgroups of one instance, at most
+constexpr int kMinRankGroups = 16;
+constexpr int kWordsPerBlock = 1024;   // bitfield words per workgroup (enumeration, free list)
+constexpr int kMaxReduceSub = 10;      // tree levels reduced inside one workgroup, at most
+constexpr int kMinReduceSub = 5;
+constexpr int kMaxBatch = 4096;        // instances in one batched launch
+constexpr uint32_t kMapShift = 20;     // block map entry: instance << 20 | local block
 
 // Command word of a live bisector, rewritten every frame (the pipeline's
 // per-bisector command integer of Section 3.3, plus bookkeeping bits).
@@ -20,12 +24,12 @@ enum : uint32_t {
     kKeep = 0u,
     kSplit = 1u,
     kMerge = 2u,
-    kMCfg = 1u << 2,   // member of a merge configuration (Alg. 4)
+    kMCfg = 1u << 2,   // smallest member of a merge configuration (Alg. 4)
     kMQuad = 1u << 3,  // the configuration is a cycle of four (else a border pair)
     kMMin = 1u << 4,   // smallest heap ID of its configuration
     kMAcc = 1u << 5,   // merge reservation accepted (on the smallest member)
     kMUnan = 1u << 6,  // every member of the configuration decided MERGE
-    kMExec = 1u << 7,  // configuration merges this frame (on every member)
+    kMExec = 1u << 7,  // configuration merges this frame
     kMarkB = 1u << 8,  // split marks: base edge, Next edge, Prev edge
     kMarkN = 1u << 9,
     kMarkP = 1u << 10,
@@ -66,32 +70,7 @@ struct Counters {
     uint32_t stat[kStCount];
 };
 
-// Device state of one instance, carved from the caller's workspace.
-struct Pool {
-    uint64_t* id;      // [cap] heap ID per block (stale when free)
-    int4* link;        // [cap] twin, next, prev (block indices, -1 = border), unused
-    uint32_t* cmd;     // [cap] command word, rewritten every frame
-    uint4* fwd;        // [cap] per-frame forwarding / merge members
-    float4* vflat;     // [3 cap] flat-domain vertices (xyz, w unused)
-    float4* vworld;    // [3 cap] their world positions; w of the first holds
-                       //         the subdivision depth, of the second the
-                       //         parity of the heap ID (as integers)
-    uint32_t* bits;    // [W]   occupancy bitfield, bit s&31 of word s>>5
-    uint32_t* tree;    // [2^(D-4)] sum-reduction tree down to word level
-    uint32_t* live;    // [cap] rank -> block, ascending
-    uint32_t* freel;   // [cap] first N free blocks of the pre-frame bitfield
-    uint32_t* list;    // [cap] per-workgroup compacted work lists (blocks), each
-                       //       workgroup's entries from its first rank on: merge
-                       //       candidates, then accepted initiators, then owners
-    uint32_t* lcnt;    // [kRankGrid] entries in each workgroup's list
-    uint2* part;       // [kRankGrid] per-workgroup partial sums
-    Counters* ctr;
-    float* root;       // [9H] root triangle vertices
-    int32_t D, k, H;
-    uint32_t cap, W;
-};
-
-// Per-frame LOD constants (Section 3.3 kernel 4), passed by value.
+// Per-frame LOD constants (Section 3.3 kernel 4).
 struct LodK {
     float cam[3], right[3], up[3], fwd[3];
     float f2, t2s, t2m, tx, ty, znear;
@@ -101,7 +80,80 @@ struct LodK {
     int32_t mode;
 };
 
+// Device state of one instance, carved from its workspace.
+struct Pool {
+    uint64_t* id;      // [cap] heap ID per block (stale when free)
+    int4* link;        // [cap] twin, next, prev (blocks, -1 on a border) and
+                       //       the bisector's fate this frame: 0 between
+                       //       frames; once the fill has run, the command word
+                       //       of a bisector consumed by a split (marks and
+                       //       depth), or kMExec for a merged member
+    uint4* fwd;        // [cap] during a frame: blocks given to a split
+                       //       bisector's outputs, or the parent block of a
+                       //       merged member; on the smallest member of a
+                       //       merge configuration first its other members,
+                       //       then (parent, members)
+    float4* vflat;    // [3 cap] flat-domain vertices (xyz, w unused)
+    float4* vworld;    // [3 cap] their world positions; w of the first holds
+                       //         the subdivision depth, of the second the
+                       //         parity of the heap ID (as integers)
+    uint32_t* cmd;     // [cap] command word, rewritten every frame
+    uint32_t* bits;    // [W]   occupancy bitfield, bit s&31 of word s>>5
+    uint32_t* tree;    // [2^(D-4)] sum-reduction tree down to word level
+    uint32_t* live;    // [cap] rank -> block, ascending
+    uint32_t* freel;   // [cap] first N free blocks of the pre-frame bitfield
+    uint2* list;       // [cap] per-workgroup compacted work lists, each
+                       //       workgroup's entries from its first rank on:
+                       //       merge candidates, then accepted initiators,
+                       //       then owners with their command words
+    uint32_t* lpre;    // [cap] beside each owner entry: outputs of the
+                       //       workgroup's earlier owners
+    uint32_t* lcnt;   // [kMaxRankGroups] entries in each workgroup's list
+    uint2* part;       // [kMaxRankGroups] per-workgroup partial sums
+    Counters* ctr;
+    float* root;       // [9H] root triangle vertices
+    int32_t D, k, H;
+    uint32_t cap, W;
+    uint32_t G;        // rank workgroups (launch schedule)
+    int32_t sub;       // tree levels per reduction workgroup (launch schedule)
+};
+
+// One instance as the kernels see it: state, this frame's constants and the
+// injected decisions (NULL: LOD test).
+struct Inst {
+    Pool P;
+    LodK K;
+    const uint8_t* inj;
+};
+
+// Instances updated by the same launches.  Each block map holds, per
+// workgroup of the batched grid, (instance << kMapShift) | workgroup within
+// that instance's own grid.
+struct Batch {
+    int n;
+    const Inst* inst;
+    const uint32_t* map_rank;
+    const uint32_t* map_word;
+    const uint32_t* map_red;
+};
+
+// Everything a launch sequence needs: either one instance passed by value
+// (batched = false) or a batch in device memory, and the grid sizes.
+struct Launch {
+    bool batched;
+    Inst one;
+    Batch B;
+    uint32_t n_inst;
+    uint32_t grid_rank, grid_word, grid_red;
+};
+
+// per-instance grid sizes
+uint32_t word_groups(const Pool& P);
+uint32_t reduce_groups(const Pool& P);
+int reduce_levels(const Pool& P);
+
 size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base);
+Launch single_launch(const Pool& P, const LodK& K, const uint8_t* inj);
 
 // Optional event pair recorded around the launches of one pipeline stage
 // (stage numbers of include/cbt.h).
@@ -111,19 +163,26 @@ struct StageEvents {
     hipEvent_t end;
 };
 
-hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, hipStream_t s,
-                        const StageEvents* ev);
-hipError_t launch_reduce(const Pool& P, hipStream_t s);
-hipError_t launch_enumerate(const Pool& P, hipStream_t s);
+hipError_t launch_frame(const Launch& X, hipStream_t s, const StageEvents* ev);
+hipError_t launch_reduce(const Launch& X, hipStream_t s);
+hipError_t launch_enumerate(const Launch& X, hipStream_t s);
 // rebuild the vertex cache of every live block (flat != 0: decode the flat
-// vertices from the heap IDs first; otherwise recompute world positions)
-hipError_t launch_refresh(const Pool& P, const LodK& K, int flat, hipStream_t s);
+// vertices from the heap IDs first; otherwise recompute world positions
+// with the instance's K)
+hipError_t launch_refresh(const Launch& X, int flat, hipStream_t s);
+
+// the counters of every instance of a batch -> out[n_inst]
+hipError_t launch_gather_counters(const Launch& X, Counters* out, hipStream_t s);
+
+// single-instance helpers for queries, snapshot and restore
 hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s);
 hipError_t launch_gather_ids(const Pool& P, uint32_t r0, uint32_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_gather_links(const Pool& P, uint32_t r0, uint32_t n, int32_t* out3, hipStream_t s);
 hipError_t launch_gather_vertices(const Pool& P, uint32_t r0, uint32_t n, float* out9, hipStream_t s);
 hipError_t launch_gather_decisions(const Pool& P, uint32_t L, uint8_t* out_per_slot, hipStream_t s);
 hipError_t launch_export_heap(const Pool& P, uint32_t* out, hipStream_t s);
+// blocks [b0, b0+n) <-> packed records (id low, id high, twin, next, prev)
+hipError_t launch_export_records(const Pool& P, uint32_t b0, uint32_t n, uint32_t* out5, hipStream_t s);
+hipError_t launch_import_records(const Pool& P, uint32_t b0, uint32_t n, const uint32_t* in5, hipStream_t s);
 
 }  // namespace cbtk
-

@@ -1,12 +1,12 @@
 // gfx950 kernels of the per-frame adaptive bisection update.
 //
 // One frame (the nine-kernel pipeline of Section 3.3) runs as a fixed
-// sequence of launches on one stream.  Every launch is a persistent grid of
-// kRankGrid workgroups, each owning a contiguous chunk of ranks, bounded by
-// device-resident counts (HIP has no indirect dispatch).  Cheap passes over
-// every rank (in rank order, with workgroup scans) alternate with heavy
-// passes over compacted per-workgroup work lists, so divergent pointer work
-// runs with full wavefronts:
+// sequence of launches on one stream.  Every per-bisector launch is a
+// persistent grid of G workgroups per instance, each owning a contiguous
+// chunk of ranks, bounded by device-resident counts (HIP has no indirect
+// dispatch).  Cheap passes over every rank (in rank order, with workgroup
+// scans) alternate with heavy passes over compacted per-workgroup work
+// lists, so divergent pointer work runs with full wavefronts:
 //
 //   begin      L = CBT root, F = 2^D - L                              (kernel 1)
 //   enumerate  rank -> block list; each workgroup's base comes from the
@@ -20,15 +20,19 @@
 //              against F; list: accepted initiators                  (kernel 4)
 //   walk       (list) split marks along compatibility chains (Alg. 3
 //              as a closure, atomicOr)                               (kernel 4)
-//   owners     outputs per owner; list: owners                       (kernel 5)
+//   owners     outputs per owner; list: owners and command words     (kernel 5)
 //   freelist   the first N zero bits of the pre-frame bitfield
 //              (ZeroToBitID order, Alg. 8), bits set                (kernels 5, 8)
-//   fill       (list) allocation offsets, new heap IDs, vertex-cache
-//              records, forwarding records                           (kernel 6)
-//   resolve    (list) pointers of every new bisector, back-pointers of
-//              untouched neighbours (Table 1, Alg. 5, Alg. 6 and
-//              compositions); consumed bits cleared                 (kernels 7-8)
+//   fill       (list) allocation offsets, vertex-cache records of the
+//              outputs, forwarding records of consumed bisectors     (kernel 6)
+//   resolve    (list) heap IDs and pointers of every new bisector,
+//              back-pointers of untouched neighbours (Table 1, Alg. 5,
+//              Alg. 6 and compositions); consumed bits cleared      (kernels 7-8)
 //   reduce     sum-reduction tree in LDS                             (kernel 9)
+//
+// Every kernel exists in two forms: one instance passed by value in the
+// kernel arguments, or a batch of instances in device memory, where a block
+// map sends each workgroup of the batched grid to its instance.
 //
 // Determinism: allocation by scans in rank order (no atomic counter), one
 // writer per pointer field, the only atomics are order-free bitwise OR/AND
@@ -132,13 +136,57 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* sh)
     return t;
 }
 
-// ranks per workgroup of the rank-parallel kernels (contiguous chunks)
-__device__ __forceinline__ uint32_t rank_chunk(uint32_t L) { return (L + kRankGrid - 1) / kRankGrid; }
+// ---------------------------------------------------------------------------
+// instance selection
+// ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void rank_range(uint32_t L, uint32_t* r0, uint32_t* r1)
+// The instance a workgroup serves and the workgroup's index in that
+// instance's own grid: from the kernel arguments, or through a block map.
+template <bool kB>
+__device__ __forceinline__ uint32_t pick(const Batch& B, const Inst& one, const uint32_t* map, Pool& P)
 {
-    const uint32_t chunk = rank_chunk(L);
-    const uint64_t a = (uint64_t)blockIdx.x * chunk;
+    if constexpr (kB) {
+        const uint32_t e = map[blockIdx.x];
+        P = B.inst[e >> kMapShift].P;
+        return e & ((1u << kMapShift) - 1u);
+    } else {
+        P = one.P;
+        return blockIdx.x;
+    }
+}
+
+template <bool kB>
+__device__ __forceinline__ uint32_t pick_k(const Batch& B, const Inst& one, const uint32_t* map, Pool& P, LodK& K,
+                                           const uint8_t*& inj)
+{
+    if constexpr (kB) {
+        const uint32_t e = map[blockIdx.x];
+        const Inst& I = B.inst[e >> kMapShift];
+        P = I.P;
+        K = I.K;
+        inj = I.inj;
+        return e & ((1u << kMapShift) - 1u);
+    } else {
+        P = one.P;
+        K = one.K;
+        inj = one.inj;
+        return blockIdx.x;
+    }
+}
+
+// one workgroup per instance
+template <bool kB>
+__device__ __forceinline__ void pick_inst(const Batch& B, const Inst& one, Pool& P)
+{
+    if constexpr (kB) P = B.inst[blockIdx.x].P;
+    else P = one.P;
+}
+
+// ranks of workgroup blk: a contiguous chunk of ceil(L / G)
+__device__ __forceinline__ void rank_range(uint32_t L, uint32_t G, uint32_t blk, uint32_t* r0, uint32_t* r1)
+{
+    const uint32_t chunk = (L + G - 1) / G;
+    const uint64_t a = (uint64_t)blk * chunk;
     const uint64_t b = a + chunk;
     *r0 = (uint32_t)(a < L ? a : L);
     *r1 = (uint32_t)(b < L ? b : L);
@@ -146,13 +194,68 @@ __device__ __forceinline__ void rank_range(uint32_t L, uint32_t* r0, uint32_t* r
 
 // Appends the flagged lanes' values to this workgroup's list (rank order
 // kept); n is the running length, updated for the whole workgroup.
-__device__ __forceinline__ void list_append(const Pool& P, uint32_t r0, uint32_t* n, bool flag, uint32_t value,
+__device__ __forceinline__ void list_append(const Pool& P, uint32_t r0, uint32_t* n, bool flag, uint2 value,
                                             uint32_t* sh)
 {
     uint32_t tot;
     const uint32_t at = block_excl_scan(flag ? 1u : 0u, sh, &tot);
     if (flag) P.list[r0 + *n + at] = value;
     *n += tot;
+}
+
+// The lists of all rank workgroups form one list in rank order.  Consumers
+// share it evenly: each workgroup scans the list lengths into LDS
+// (base[w] = entries before workgroup w's, base[G] = total) and takes a
+// contiguous 1/G of the entries, so the work no longer follows where in
+// rank order the split and merge activity happens to be.
+struct ListShare {
+    uint32_t i0, i1;      // this workgroup's entries [i0, i1)
+    uint32_t chunk;       // ranks per rank workgroup
+};
+
+__device__ __forceinline__ ListShare list_share(const Pool& P, uint32_t blk, uint32_t* base, uint32_t* sh)
+{
+    constexpr int E = kMaxRankGroups / kBlock;
+    const uint32_t G = P.G;
+    uint32_t v[E], loc = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t w = threadIdx.x * E + e;
+        v[e] = w < G ? P.lcnt[w] : 0u;
+        loc += v[e];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(loc, sh, &tot);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t w = threadIdx.x * E + e;
+        if (w < G) base[w] = run;
+        run += v[e];
+    }
+    if (threadIdx.x == 0) base[G] = tot;
+    __syncthreads();
+    const uint32_t per = (tot + G - 1) / G;
+    const uint64_t a = (uint64_t)blk * per, b = a + per;
+    ListShare s;
+    s.i0 = (uint32_t)(a < tot ? a : tot);
+    s.i1 = (uint32_t)(b < tot ? b : tot);
+    s.chunk = (P.ctr->L + G - 1) / G;
+    return s;
+}
+
+// position in P.list of entry i of the concatenated list (base[0] <= i <
+// base[G]); *w receives the rank workgroup that wrote it
+__device__ __forceinline__ uint32_t list_at(const uint32_t* base, uint32_t G, uint32_t chunk, uint32_t i,
+                                            uint32_t* w)
+{
+    uint32_t lo = 0, hi = G;   // base[lo] <= i < base[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    *w = lo;
+    return lo * chunk + (i - base[lo]);
 }
 
 __device__ __forceinline__ int ilog2_64(uint64_t x) { return 63 - __clzll((long long)x); }
@@ -177,11 +280,14 @@ __device__ uint32_t ones_before_word(const Pool& P, uint32_t w)
 }
 
 // ---------------------------------------------------------------------------
-// kernel: frame begin
+// kernel: frame begin (one workgroup per instance)
 // ---------------------------------------------------------------------------
 
-__global__ void k_begin(Pool P)
+template <bool kB>
+__global__ void k_begin(Batch B, Inst one)
 {
+    Pool P;
+    pick_inst<kB>(B, one, P);
     if (threadIdx.x == 0) {
         const uint32_t L = P.tree[1];
         P.ctr->L = L;
@@ -198,11 +304,14 @@ __global__ void k_begin(Pool P)
 // 256-word step is staged in LDS so the rank list is written coalesced.
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_enumerate(Pool P)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
     __shared__ uint32_t stage[kBlock * 32];
-    const uint32_t w0 = blockIdx.x * kWordsPerBlock;
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_word, P);
+    const uint32_t w0 = blk * kWordsPerBlock;
     if (w0 >= P.W) return;
     uint32_t base = ones_before_word(P, w0);
     for (uint32_t it = 0; it < kWordsPerBlock; it += kBlock) {
@@ -328,8 +437,8 @@ __device__ __forceinline__ V3 world(const LodK& K, V3 v)
     return v;
 }
 
-// Projected base-edge length test without division (cbt_lod_params):
-// returns the decision code from the three world positions.
+// Projected base-edge length test without division: returns the decision
+// code from the three world positions.
 __device__ __forceinline__ uint32_t lod_decide(const LodK& K, V3 p0, V3 p1, V3 p2)
 {
     const V3 p[3] = {p0, p1, p2};
@@ -385,12 +494,16 @@ __device__ __forceinline__ void store_vertices(const Pool& P, uint32_t s, V3 a, 
 // positions, the depth and the parity, so no heap ID is read)
 // ---------------------------------------------------------------------------
 
-template <bool kInjected>
-__global__ void __launch_bounds__(kBlock) k_classify(Pool P, LodK K, const uint8_t* inj)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
+    Pool P;
+    LodK K;
+    const uint8_t* inj;
+    const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
     uint32_t r0, r1;
-    rank_range(P.ctr->L, &r0, &r1);
+    rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     const int maxd = 63 - P.k;
     uint32_t nsplit = 0, nmerge = 0, scost = 0, nlist = 0;
     for (uint32_t base = r0; base < r1; base += kBlock) {
@@ -403,7 +516,7 @@ __global__ void __launch_bounds__(kBlock) k_classify(Pool P, LodK K, const uint8
             const float4 w0 = w[0], w1 = w[1], w2 = w[2];
             const int d = __float_as_int(w0.w);
             uint32_t dec;
-            if (kInjected) {
+            if (inj) {
                 dec = inj[s];
                 if (dec > kMerge) {
                     raise_err(P, kErrDecision);
@@ -428,14 +541,14 @@ __global__ void __launch_bounds__(kBlock) k_classify(Pool P, LodK K, const uint8
                 cand = __float_as_int(w1.w) == 0;
             }
         }
-        list_append(P, r0, &nlist, cand, s, sh);
+        list_append(P, r0, &nlist, cand, make_uint2(s, 0), sh);
     }
     const uint32_t a = block_sum(nsplit, sh);
     const uint32_t b = block_sum(nmerge, sh);
     const uint32_t c = block_sum(scost, sh);
     if (threadIdx.x == 0) {
-        P.part[blockIdx.x] = make_uint2(0, c);
-        P.lcnt[blockIdx.x] = nlist;
+        P.part[blk] = make_uint2(0, c);
+        P.lcnt[blk] = nlist;
         if (a) atomicAdd(&P.ctr->stat[kStSplitReq], a);
         if (b) atomicAdd(&P.ctr->stat[kStMergeReq], b);
     }
@@ -451,7 +564,7 @@ __global__ void __launch_bounds__(kBlock) k_classify(Pool P, LodK K, const uint8
 // configuration is always an even member (c0 < c1), so configurations are
 // detected, once, from their even members.
 __device__ __forceinline__ int merge_config_even(const Pool& P, uint64_t id, int4 l1, int32_t* j2o, int32_t* j3o,
-                                                 int32_t* j4o)
+                                                 int32_t* j4o, uint64_t* id4o)
 {
     const int32_t j2 = l1.y, j3 = l1.z;
     if (j2 < 0) return 0;
@@ -465,56 +578,70 @@ __device__ __forceinline__ int merge_config_even(const Pool& P, uint64_t id, int
     const int32_t j4 = P.link[j3].z;
     if (j4 < 0) return 0;
     if (!slot_ok(P, j4)) { raise_err(P, kErrPointer); return 0; }
-    if ((P.id[j4] >> 1) != (id3 >> 1)) return 0;
+    const uint64_t id4 = P.id[j4];
+    if ((id4 >> 1) != (id3 >> 1)) return 0;
     *j3o = j3;
     *j4o = j4;
+    *id4o = id4;
     return 4;
 }
 
 // A configuration merges only if every member decided MERGE (unanimity);
-// its reservation, one block per parent, is charged to the smallest member.
-__global__ void __launch_bounds__(kBlock) k_vote(Pool P)
+// its reservation, one block per parent, is charged to the smallest member
+// (added to the partial of the rank workgroup that holds it).
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
-    uint32_t r0, r1;
-    rank_range(P.ctr->L, &r0, &r1);
-    const uint32_t n = P.lcnt[blockIdx.x];
-    uint32_t ncfg = 0, res = 0;
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
-        const uint32_t s = P.list[r0 + i];
+    __shared__ uint32_t base[kMaxRankGroups + 1];
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    const ListShare ls = list_share(P, blk, base, sh);
+    uint32_t ncfg = 0, res = 0, wres = 0xffffffffu;
+    for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
+        uint32_t w;
+        const uint32_t s = P.list[list_at(base, P.G, ls.chunk, i, &w)].x;
         const uint64_t id = P.id[s];
         int32_t j2 = -1, j3 = -1, j4 = -1;
-        const int m = merge_config_even(P, id, P.link[s], &j2, &j3, &j4);
-        if (!m || (m == 4 && P.id[j4] < id)) continue;   // not the smallest member
+        uint64_t id4 = 0;
+        const int m = merge_config_even(P, id, P.link[s], &j2, &j3, &j4, &id4);
+        if (!m || (m == 4 && id4 < id)) continue;   // not the smallest member
         bool ok = (P.cmd[j2] & kDecMask) == kMerge;
         if (m == 4) ok = ok && (P.cmd[j3] & kDecMask) == kMerge && (P.cmd[j4] & kDecMask) == kMerge;
         if (!ok) continue;
         P.cmd[s] |= kMCfg | kMMin | kMUnan | (m == 4 ? kMQuad : 0u);
         P.fwd[s] = make_uint4((uint32_t)j2, (uint32_t)j3, (uint32_t)j4, (uint32_t)m);
+        if (w != wres) {
+            if (res) atomicAdd(&P.part[wres].x, res);
+            wres = w;
+            res = 0;
+        }
         res += (uint32_t)m / 2;
         ++ncfg;
     }
-    const uint32_t t = block_sum(res, sh);
+    if (res) atomicAdd(&P.part[wres].x, res);
     const uint32_t u = block_sum(ncfg, sh);
-    if (threadIdx.x == 0) {
-        P.part[blockIdx.x].x = t;
-        if (u) atomicAdd(&P.ctr->stat[kStMergeCfg], u);
-    }
+    if (threadIdx.x == 0 && u) atomicAdd(&P.ctr->stat[kStMergeCfg], u);
 }
 
-// exclusive saturating scan of the per-workgroup partials (one workgroup of
-// 1024 threads, kRankGrid / 1024 partials each); mode 0: the totals are the
-// reservations, mode 1: the allocations
-__global__ void __launch_bounds__(1024) k_scan_parts(Pool P, int mode)
+// exclusive saturating scan of one instance's G per-workgroup partials (one
+// workgroup of 1024 threads per instance, two partials each); mode 0: the
+// totals are the reservations, mode 1: the allocations
+template <bool kB>
+__global__ void __launch_bounds__(1024) k_scan_parts(Batch B, Inst one, int mode)
 {
-    constexpr int E = kRankGrid / 1024;
+    constexpr int E = kMaxRankGroups / 1024;
     __shared__ uint2 sh[16];
+    Pool P;
+    pick_inst<kB>(B, one, P);
+    const uint32_t G = P.G;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint2 v[E];
     uint2 loc = make_uint2(0, 0);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        v[e] = P.part[threadIdx.x * E + e];
+        const uint32_t i = threadIdx.x * E + e;
+        v[e] = i < G ? P.part[i] : make_uint2(0, 0);
         loc = sat_add2(loc, v[e]);
     }
     const uint2 inc = wave_incl_scan_sat(loc);
@@ -530,7 +657,8 @@ __global__ void __launch_bounds__(1024) k_scan_parts(Pool P, int mode)
     uint2 run = lane ? sat_add2(pre, make_uint2(ex, ey)) : pre;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        P.part[threadIdx.x * E + e] = run;
+        const uint32_t i = threadIdx.x * E + e;
+        if (i < G) P.part[i] = run;
         run = sat_add2(run, v[e]);
     }
     if (threadIdx.x == 0) {
@@ -552,14 +680,17 @@ __global__ void __launch_bounds__(1024) k_scan_parts(Pool P, int mode)
 // inclusive merge prefix fits in F; the split reservation (3d + 4) when all
 // merge reservations plus the inclusive split prefix fit in F.  Accepted
 // initiators are listed for the chain walk.
-__global__ void __launch_bounds__(kBlock) k_budget(Pool P)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
 {
     __shared__ uint2 sh2[8];
     __shared__ uint32_t sh[8];
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
     uint32_t r0, r1;
-    rank_range(P.ctr->L, &r0, &r1);
+    rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     const uint32_t F = P.ctr->F, Tm = P.ctr->Tm;
-    uint2 carry = P.part[blockIdx.x];
+    uint2 carry = P.part[blk];
     uint32_t nm = 0, nlist = 0;
     for (uint32_t base = r0; base < r1; base += kBlock) {
         const uint32_t r = base + threadIdx.x;
@@ -577,12 +708,12 @@ __global__ void __launch_bounds__(kBlock) k_budget(Pool P)
             P.cmd[s] = c | kMAcc;
             ++nm;
         }
-        list_append(P, r0, &nlist, v.y && sat_add(Tm, inc.y) <= F, s, sh);
+        list_append(P, r0, &nlist, v.y && sat_add(Tm, inc.y) <= F, make_uint2(s, 0), sh);
         carry = sat_add2(carry, tot);
     }
     const uint32_t a = block_sum(nm, sh);
     if (threadIdx.x == 0) {
-        P.lcnt[blockIdx.x] = nlist;
+        P.lcnt[blk] = nlist;
         if (a) atomicAdd(&P.ctr->stat[kStMergeAcc], a);
         if (nlist) atomicAdd(&P.ctr->stat[kStSplitAcc], nlist);
     }
@@ -622,17 +753,23 @@ __device__ void walk_chain(const Pool& P, uint32_t s)
     raise_err(P, kErrChain);
 }
 
-__global__ void __launch_bounds__(kBlock) k_walk(Pool P)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_walk(Batch B, Inst one)
 {
-    uint32_t r0, r1;
-    rank_range(P.ctr->L, &r0, &r1);
-    const uint32_t n = P.lcnt[blockIdx.x];
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) walk_chain(P, P.list[r0 + i]);
+    __shared__ uint32_t sh[8];
+    __shared__ uint32_t base[kMaxRankGroups + 1];
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    const ListShare ls = list_share(P, blk, base, sh);
+    for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
+        uint32_t w;
+        walk_chain(P, P.list[list_at(base, P.G, ls.chunk, i, &w)].x);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // kernel: owners (split-marked bisectors, executing merges), their output
-// counts per workgroup, and the owner list
+// counts per workgroup, and the owner list with the command words
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint32_t split_outputs(uint32_t cmd)
@@ -640,47 +777,57 @@ __device__ __forceinline__ uint32_t split_outputs(uint32_t cmd)
     return 2u + ((cmd & kMarkN) ? 1u : 0u) + ((cmd & kMarkP) ? 1u : 0u);
 }
 
-__global__ void __launch_bounds__(kBlock) k_owners(Pool P)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
+    __shared__ uint2 sh2[8];
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
     uint32_t r0, r1;
-    rank_range(P.ctr->L, &r0, &r1);
-    uint32_t acc = 0, nexec = 0, nsc = 0, nfree = 0, nlist = 0;
+    rank_range(P.ctr->L, P.G, blk, &r0, &r1);
+    uint32_t nexec = 0, nsc = 0, nfree = 0;
+    uint2 run = make_uint2(0, 0);   // (owners, outputs) of earlier iterations
     for (uint32_t base = r0; base < r1; base += kBlock) {
         const uint32_t r = base + threadIdx.x;
-        uint32_t s = 0;
-        bool owner = false;
+        uint32_t s = 0, c = 0, k = 0;
         if (r < r1) {
             s = P.live[r];
-            const uint32_t c = P.cmd[s];
+            c = P.cmd[s];
             if (c & kMarks) {
-                acc += split_outputs(c);
+                k = split_outputs(c);
                 ++nsc;
                 ++nfree;
-                owner = true;
             } else if (c & kMAcc) {
                 // splits win: a configuration with a split-marked member stays
                 const uint4 m = P.fwd[s];
                 bool clean = !(P.cmd[m.x] & kMarks);
                 if (m.w == 4) clean = clean && !(P.cmd[m.y] & kMarks) && !(P.cmd[m.z] & kMarks);
                 if (clean) {
-                    P.cmd[s] = c | kMExec;
-                    acc += m.w / 2;
+                    c |= kMExec;
+                    k = m.w / 2;
                     ++nexec;
                     nfree += m.w;
-                    owner = true;
                 }
             }
         }
-        list_append(P, r0, &nlist, owner, s, sh);
+        // owners before this one in the workgroup, and their outputs
+        const uint2 v = make_uint2(k ? 1u : 0u, k);
+        uint2 tot;
+        const uint2 inc = block_incl_scan_sat(v, sh2, &tot);
+        if (k) {
+            const uint32_t at = r0 + run.x + inc.x - 1u;
+            P.list[at] = make_uint2(s, c);
+            P.lpre[at] = run.y + inc.y - k;
+        }
+        run = make_uint2(run.x + tot.x, run.y + tot.y);
     }
-    const uint32_t t = block_sum(acc, sh);
     const uint32_t a = block_sum(nexec, sh);
     const uint32_t b = block_sum(nsc, sh);
     const uint32_t c = block_sum(nfree, sh);
     if (threadIdx.x == 0) {
-        P.part[blockIdx.x] = make_uint2(t, 0);
-        P.lcnt[blockIdx.x] = nlist;
+        P.part[blk] = make_uint2(run.y, 0);
+        P.lcnt[blk] = run.x;
         if (a) atomicAdd(&P.ctr->stat[kStMergeExec], a);
         if (b) atomicAdd(&P.ctr->stat[kStSplitConsumed], b);
         if (c) atomicAdd(&P.ctr->stat[kStFrees], c);
@@ -692,12 +839,15 @@ __global__ void __launch_bounds__(kBlock) k_owners(Pool P)
 // tree, Alg. 8), marked occupied; staged in LDS for coalesced writes
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_freelist(Pool P)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
     __shared__ uint32_t stage[kBlock * 32];
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_word, P);
     const uint32_t N = P.ctr->N;
-    const uint32_t w0 = blockIdx.x * kWordsPerBlock;
+    const uint32_t w0 = blk * kWordsPerBlock;
     if (w0 >= P.W || N == 0) return;
     uint32_t zb = 32u * w0 - ones_before_word(P, w0);
     if (zb >= N) return;
@@ -726,9 +876,11 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Pool P)
 }
 
 // ---------------------------------------------------------------------------
-// kernel: fill (owner list) -- allocation offsets (exclusive scan of the
-// output counts in rank order), new heap IDs, vertex-cache records and the
-// forwarding records of consumed bisectors
+// kernel: fill (owner list) -- vertex-cache records of the outputs and the
+// forwarding records and fates of consumed bisectors.  An owner's first
+// output takes position (workgroup's output base) + (outputs of the
+// workgroup's earlier owners) of the free list: the exclusive scan of the
+// output counts in rank order.
 // ---------------------------------------------------------------------------
 
 // Forwarding record of a split bisector, by role:
@@ -737,11 +889,12 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Pool P)
 //   2: second child (2x+1), or its first child (4x+2) when the Next edge splits
 //   3: second child of the second child (4x+3), Next edge split only
 // Outputs take their blocks in ascending heap-ID order.  A merged member's
-// record holds its parent's block first; the owner's record also keeps the
-// other members (second, third, fourth fields) for the pointer pass.
+// record holds its parent's block first; the smallest member's record also
+// keeps the other members (second, third, fourth fields) for the pointer
+// pass.
 
-__device__ __forceinline__ void fill_split(const Pool& P, uint32_t s, uint32_t c, uint32_t base, uint32_t N,
-                                           const LodK& K)
+__device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_t s, uint32_t c, uint32_t base,
+                                           uint32_t N)
 {
     const bool hn = c & kMarkN, hp = c & kMarkP;
     const uint32_t cnt = 2u + (hn ? 1u : 0u) + (hp ? 1u : 0u);
@@ -749,7 +902,6 @@ __device__ __forceinline__ void fill_split(const Pool& P, uint32_t s, uint32_t c
     const uint32_t q0 = P.freel[base], q1 = P.freel[base + 1];
     const uint32_t q2 = cnt > 2 ? P.freel[base + 2] : 0u, q3 = cnt > 3 ? P.freel[base + 3] : 0u;
     if (q0 >= P.cap || q1 >= P.cap || q2 >= P.cap || q3 >= P.cap) { raise_err(P, kErrAlloc); return; }
-    const uint64_t x = P.id[s];
     const int d = depth_of_cmd(c);
     const float4* fv = P.vflat + 3 * (size_t)s;
     const float4* wv = P.vworld + 3 * (size_t)s;
@@ -769,33 +921,28 @@ __device__ __forceinline__ void fill_split(const Pool& P, uint32_t s, uint32_t c
     }
     // first child (v0, v2, m), or its children (v0, m, m0) and (m, v2, m0)
     if (!hp) {
-        P.id[r0q] = 2 * x;
         store_vertices(P, r0q, v0, v2, m, w0, w2, wm, d + 1, 0);
     } else {
         const V3 m0 = mid3(v0, v2);
         const V3 wm0 = world(K, m0);
-        P.id[r0q] = 4 * x;
-        P.id[r1q] = 4 * x + 1;
         store_vertices(P, r0q, v0, m, m0, w0, wm, wm0, d + 2, 0);
         store_vertices(P, r1q, m, v2, m0, wm, w2, wm0, d + 2, 1);
     }
     // second child (v2, v1, m), or its children (v2, m, m1) and (m, v1, m1)
     if (!hn) {
-        P.id[r2q] = 2 * x + 1;
         store_vertices(P, r2q, v2, v1, m, w2, w1, wm, d + 1, 1);
     } else {
         const V3 m1 = mid3(v2, v1);
         const V3 wm1 = world(K, m1);
-        P.id[r2q] = 4 * x + 2;
-        P.id[r3q] = 4 * x + 3;
         store_vertices(P, r2q, v2, m, m1, w2, wm, wm1, d + 2, 0);
         store_vertices(P, r3q, m, v1, m1, wm, w1, wm1, d + 2, 1);
     }
+    P.link[s].w = (int)c;
     P.fwd[s] = make_uint4(r0q, r1q, r2q, r3q);
 }
 
 // parent of the sibling pair (c0 even, c1 odd): vertices (c0.v0, c1.v1, c0.v1)
-__device__ __forceinline__ void fill_parent(const Pool& P, uint32_t q, int32_t c0, int32_t c1, int depth)
+__device__ __forceinline__ void fill_parent(const Pool& P, uint32_t q, int32_t c0, int32_t c1, int depth, int parity)
 {
     const float4* f0 = P.vflat + 3 * (size_t)c0;
     const float4* f1 = P.vflat + 3 * (size_t)c1;
@@ -803,72 +950,71 @@ __device__ __forceinline__ void fill_parent(const Pool& P, uint32_t q, int32_t c
     const float4* w1 = P.vworld + 3 * (size_t)c1;
     float4* fq = P.vflat + 3 * (size_t)q;
     float4* wq = P.vworld + 3 * (size_t)q;
-    const uint64_t id = P.id[c0] >> 1;
     fq[0] = f0[0];
     fq[1] = f1[1];
     fq[2] = f0[1];
     const float4 a = w0[0], b = w1[1], c = w0[1];
     wq[0] = make_float4(a.x, a.y, a.z, __int_as_float(depth));
-    wq[1] = make_float4(b.x, b.y, b.z, __int_as_float((int)(id & 1u)));
+    wq[1] = make_float4(b.x, b.y, b.z, __int_as_float(parity));
     wq[2] = make_float4(c.x, c.y, c.z, 0.0f);
-    P.id[q] = id;
 }
 
 __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c, uint32_t base, uint32_t N)
 {
     const uint4 m = P.fwd[s];   // (sibling, other odd, other even, members)
+    const uint64_t ida = P.id[s] >> 1;
     const bool quad = m.w == 4;
     if (base + (quad ? 2u : 1u) > N) { raise_err(P, kErrAlloc); return; }
     uint32_t qa = P.freel[base], qb = 0xffffffffu;
+    uint64_t idb = 0;
     if (quad) {
         const uint32_t q1 = P.freel[base + 1];
-        const bool a_first = (P.id[s] >> 1) < (P.id[m.z] >> 1);
+        idb = P.id[m.z] >> 1;
+        const bool a_first = ida < idb;
         qb = a_first ? q1 : qa;
         qa = a_first ? qa : q1;
     }
     if (qa >= P.cap || (quad && qb >= P.cap)) { raise_err(P, kErrAlloc); return; }
     const int dp = depth_of_cmd(c) - 1;
-    fill_parent(P, qa, (int32_t)s, (int32_t)m.x, dp);
+    fill_parent(P, qa, (int32_t)s, (int32_t)m.x, dp, (int)(ida & 1u));
+    P.link[s].w = (int)kMExec;
     P.fwd[s] = make_uint4(qa, m.x, m.y, m.z);
+    P.link[m.x].w = (int)kMExec;
     P.fwd[m.x] = make_uint4(qa, 0, 0, 0);
-    P.cmd[m.x] |= kMExec;
     if (quad) {
-        fill_parent(P, qb, (int32_t)m.z, (int32_t)m.y, dp);
+        fill_parent(P, qb, (int32_t)m.z, (int32_t)m.y, dp, (int)(idb & 1u));
+        P.link[m.y].w = (int)kMExec;
         P.fwd[m.y] = make_uint4(qb, 0, 0, 0);
+        P.link[m.z].w = (int)kMExec;
         P.fwd[m.z] = make_uint4(qb, 0, 0, 0);
-        P.cmd[m.y] |= kMExec;
-        P.cmd[m.z] |= kMExec;
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_fill(Pool P, LodK K)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
-    uint32_t r0, r1;
-    rank_range(P.ctr->L, &r0, &r1);
+    __shared__ uint32_t base[kMaxRankGroups + 1];
+    Pool P;
+    LodK K;
+    const uint8_t* inj;
+    const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
+    (void)inj;
+    const ListShare ls = list_share(P, blk, base, sh);
     const uint32_t N = P.ctr->N;
-    const uint32_t n = P.lcnt[blockIdx.x];
-    uint32_t carry = P.part[blockIdx.x].x;
-    for (uint32_t ib = 0; ib < n; ib += kBlock) {
-        const uint32_t i = ib + threadIdx.x;
-        uint32_t s = 0, c = 0, k = 0;
-        if (i < n) {
-            s = P.list[r0 + i];
-            c = P.cmd[s];
-            k = (c & kMarks) ? split_outputs(c) : ((c & kMQuad) ? 2u : 1u);
-        }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(k, sh, &tot);
-        if (i < n) {
-            if (c & kMarks) fill_split(P, s, c, carry + ex, N, K);
-            else fill_merge(P, s, c, carry + ex, N);
-        }
-        carry += tot;
+    for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
+        uint32_t w;
+        const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
+        const uint2 e = P.list[at];
+        const uint32_t off = P.part[w].x + P.lpre[at];
+        if (e.y & kMarks) fill_split(P, K, e.x, e.y, off, N);
+        else fill_merge(P, e.x, e.y, off, N);
     }
 }
 
 // ---------------------------------------------------------------------------
-// kernel: neighbour pointers (Table 1, Alg. 5/6 and their compositions)
+// kernel: heap IDs and neighbour pointers of the new bisectors (Table 1,
+// Alg. 5/6 and their compositions)
 // ---------------------------------------------------------------------------
 
 enum { kEdgeT = 0, kEdgeN = 1, kEdgeP = 2 };
@@ -898,9 +1044,9 @@ __device__ __forceinline__ uint32_t comp(uint4 v, int i)
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-// The old neighbour across one edge of a consumed bisector b, loaded once:
-// its block, which of its fields pointed to b, its command word and (when it
-// is consumed too) its forwarding record.
+// The old neighbour across one edge of a consumed bisector b, loaded once
+// (one record line): its block, which of its fields pointed to b, its fate
+// this frame (0 when untouched) and its forwarding record.
 struct Nb {
     int32_t n;
     int f;
@@ -928,8 +1074,8 @@ __device__ __forceinline__ Nb load_nb(const Pool& P, int32_t b, int32_t n)
         r.n = -1;
         return r;
     }
-    r.c = P.cmd[n];
-    if (r.c & (kMarks | kMExec)) r.fw = P.fwd[n];
+    r.c = (uint32_t)ln.w;
+    if (r.c) r.fw = P.fwd[n];
     return r;
 }
 
@@ -954,10 +1100,12 @@ __device__ __forceinline__ int32_t piece_target(const Pool& P, const Nb& nb, int
     return nb.n;
 }
 
-__device__ __forceinline__ void store_link(const Pool& P, uint32_t q, int32_t t, int32_t n, int32_t p)
+// a new bisector: heap ID, pointers, untouched fate
+__device__ __forceinline__ void store_new(const Pool& P, uint32_t q, uint64_t id, int32_t t, int32_t n, int32_t p)
 {
-    if (q < P.cap) P.link[q] = make_int4(t, n, p, 0);
-    else raise_err(P, kErrAlloc);
+    if (q >= P.cap) { raise_err(P, kErrAlloc); return; }
+    P.id[q] = id;
+    P.link[q] = make_int4(t, n, p, 0);
 }
 
 __device__ __forceinline__ void clear_bit(const Pool& P, uint32_t s)
@@ -969,57 +1117,69 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
 {
     const int db = depth_of_cmd(c);
     const bool hn = c & kMarkN, hp = c & kMarkP;
+    const uint64_t x = P.id[b];
     const int4 lb = P.link[b];
     const uint4 f = P.fwd[b];
     const Nb nT = load_nb(P, b, lb.x);
     const Nb nN = load_nb(P, b, lb.y);
     const Nb nP = load_nb(P, b, lb.z);
     if (!hp) {  // first child (v0, v2, m)
-        store_link(P, f.x, piece_target(P, nP, db, kWhole, f.x), (int32_t)f.z, piece_target(P, nT, db, kHalf0, f.x));
+        store_new(P, f.x, 2 * x, piece_target(P, nP, db, kWhole, f.x), (int32_t)f.z,
+                  piece_target(P, nT, db, kHalf0, f.x));
     } else {    // its two children
-        store_link(P, f.x, piece_target(P, nT, db, kHalf0, f.x), (int32_t)f.y, piece_target(P, nP, db, kHalf1, f.x));
-        store_link(P, f.y, (int32_t)f.z, piece_target(P, nP, db, kHalf0, f.y), (int32_t)f.x);
+        store_new(P, f.x, 4 * x, piece_target(P, nT, db, kHalf0, f.x), (int32_t)f.y,
+                  piece_target(P, nP, db, kHalf1, f.x));
+        store_new(P, f.y, 4 * x + 1, (int32_t)f.z, piece_target(P, nP, db, kHalf0, f.y), (int32_t)f.x);
     }
     if (!hn) {  // second child (v2, v1, m)
-        store_link(P, f.z, piece_target(P, nN, db, kWhole, f.z), piece_target(P, nT, db, kHalf1, f.z),
-                   (int32_t)(hp ? f.y : f.x));
+        store_new(P, f.z, 2 * x + 1, piece_target(P, nN, db, kWhole, f.z), piece_target(P, nT, db, kHalf1, f.z),
+                  (int32_t)(hp ? f.y : f.x));
     } else {    // its two children
-        store_link(P, f.z, (int32_t)(hp ? f.y : f.x), (int32_t)f.w, piece_target(P, nN, db, kHalf1, f.z));
-        store_link(P, f.w, piece_target(P, nT, db, kHalf1, f.w), piece_target(P, nN, db, kHalf0, f.w), (int32_t)f.z);
+        store_new(P, f.z, 4 * x + 2, (int32_t)(hp ? f.y : f.x), (int32_t)f.w, piece_target(P, nN, db, kHalf1, f.z));
+        store_new(P, f.w, 4 * x + 3, piece_target(P, nT, db, kHalf1, f.w), piece_target(P, nN, db, kHalf0, f.w),
+                  (int32_t)f.z);
     }
     clear_bit(P, (uint32_t)b);
 }
 
 // parent q of the sibling pair (c0, c1): Next edge = c1's base edge, Prev
 // edge = c0's base edge, Twin = the other parent (or the border)
-__device__ __forceinline__ void resolve_parent(const Pool& P, uint32_t q, int32_t twin, int32_t c0, int32_t c1, int d)
+__device__ __forceinline__ void resolve_parent(const Pool& P, uint32_t q, uint64_t id, int32_t twin, int32_t c0,
+                                               int32_t c1, int d)
 {
     const Nb n1 = load_nb(P, c1, P.link[c1].x);
     const Nb n0 = load_nb(P, c0, P.link[c0].x);
-    store_link(P, q, twin, piece_target(P, n1, d, kWhole, q), piece_target(P, n0, d, kWhole, q));
+    store_new(P, q, id, twin, piece_target(P, n1, d, kWhole, q), piece_target(P, n0, d, kWhole, q));
 }
 
-__global__ void __launch_bounds__(kBlock) k_resolve(Pool P)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
 {
-    uint32_t r0, r1;
-    rank_range(P.ctr->L, &r0, &r1);
-    const uint32_t n = P.lcnt[blockIdx.x];
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
-        const int32_t b = (int32_t)P.list[r0 + i];
-        const uint32_t c = P.cmd[b];
+    __shared__ uint32_t sh[8];
+    __shared__ uint32_t base[kMaxRankGroups + 1];
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    const ListShare ls = list_share(P, blk, base, sh);
+    for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
+        uint32_t w;
+        const uint2 e = P.list[list_at(base, P.G, ls.chunk, i, &w)];
+        const int32_t b = (int32_t)e.x;
+        const uint32_t c = e.y;
         if (c & kMarks) {
             resolve_split(P, b, c);
         } else {
             const uint4 f = P.fwd[b];   // (parent, sibling, other odd, other even)
+            const uint64_t ida = P.id[b] >> 1;
             const int d = depth_of_cmd(c);
             if (c & kMQuad) {
                 const uint32_t qb = P.fwd[f.w].x;
-                resolve_parent(P, f.x, (int32_t)qb, b, (int32_t)f.y, d);
-                resolve_parent(P, qb, (int32_t)f.x, (int32_t)f.w, (int32_t)f.z, d);
+                const uint64_t idb = P.id[f.w] >> 1;
+                resolve_parent(P, f.x, ida, (int32_t)qb, b, (int32_t)f.y, d);
+                resolve_parent(P, qb, idb, (int32_t)f.x, (int32_t)f.w, (int32_t)f.z, d);
                 clear_bit(P, f.z);
                 clear_bit(P, f.w);
             } else {
-                resolve_parent(P, f.x, -1, b, (int32_t)f.y, d);
+                resolve_parent(P, f.x, ida, -1, b, (int32_t)f.y, d);
             }
             clear_bit(P, (uint32_t)b);
             clear_bit(P, f.y);
@@ -1032,13 +1192,22 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Pool P)
 // word are popcounts of the bitfield and are never stored)
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_reduce_sub(Pool P)
+__device__ __forceinline__ int sub_levels(const Pool& P)
 {
-    __shared__ uint32_t buf[2][1 << kReduceSub];
     const int LW = P.D - 5;
-    const int SUB = LW < kReduceSub ? LW : kReduceSub;
+    return LW < P.sub ? LW : P.sub;
+}
+
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_reduce_sub(Batch B, Inst one)
+{
+    __shared__ uint32_t buf[2][1 << kMaxReduceSub];
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_red, P);
+    const int LW = P.D - 5;
+    const int SUB = sub_levels(P);
     const uint32_t wpb = 1u << SUB;
-    const uint32_t w0 = blockIdx.x * wpb;
+    const uint32_t w0 = blk * wpb;
     for (uint32_t i = threadIdx.x; i < wpb; i += kBlock) {
         const uint32_t c = __popc(P.bits[w0 + i]);
         buf[0][i] = c;
@@ -1051,17 +1220,20 @@ __global__ void __launch_bounds__(kBlock) k_reduce_sub(Pool P)
         for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
             const uint32_t v = buf[src][2 * i] + buf[src][2 * i + 1];
             buf[src ^ 1][i] = v;
-            P.tree[(1u << (LW - lvl)) + (blockIdx.x << (SUB - lvl)) + i] = v;
+            P.tree[(1u << (LW - lvl)) + (blk << (SUB - lvl)) + i] = v;
         }
         __syncthreads();
         src ^= 1;
     }
 }
 
-__global__ void __launch_bounds__(1024) k_reduce_top(Pool P)
+// the levels above the workgroup subtrees (one workgroup per instance)
+template <bool kB>
+__global__ void __launch_bounds__(1024) k_reduce_top(Batch B, Inst one)
 {
-    const int LW = P.D - 5;
-    const int top = LW - kReduceSub;   // levels [0, top) remain
+    Pool P;
+    pick_inst<kB>(B, one, P);
+    const int top = (P.D - 5) - sub_levels(P);   // levels [0, top) remain
     for (int lvl = top - 1; lvl >= 0; --lvl) {
         const uint32_t n = 1u << lvl;
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -1073,15 +1245,21 @@ __global__ void __launch_bounds__(1024) k_reduce_top(Pool P)
 }
 
 // ---------------------------------------------------------------------------
-// kernels: vertex-cache refresh, queries and restore
+// kernels: vertex-cache refresh, queries, snapshot and restore
 // ---------------------------------------------------------------------------
 
 // Rebuild the cache of every live block: flat vertices by the Alg. 2 decode
 // (when flat is set) and world positions from them.
-__global__ void __launch_bounds__(kBlock) k_refresh(Pool P, LodK K, int flat)
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one, int flat)
 {
+    Pool P;
+    LodK K;
+    const uint8_t* inj;
+    const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
+    (void)inj;
     const uint32_t L = P.ctr->L;
-    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < L; r += gridDim.x * kBlock) {
+    for (uint32_t r = blk * kBlock + threadIdx.x; r < L; r += P.G * kBlock) {
         const uint32_t s = P.live[r];
         const uint64_t id = P.id[s];
         V3 a = {0, 0, 0}, b = a, c = a;
@@ -1179,11 +1357,53 @@ __global__ void k_export_heap(Pool P, uint32_t* out)
     }
 }
 
+__global__ void k_export_records(Pool P, uint32_t b0, uint32_t n, uint32_t* out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t id = P.id[b0 + i];
+    const int4 l = P.link[b0 + i];
+    uint32_t* o = out + 5 * (size_t)i;
+    o[0] = (uint32_t)id;
+    o[1] = (uint32_t)(id >> 32);
+    o[2] = (uint32_t)l.x;
+    o[3] = (uint32_t)l.y;
+    o[4] = (uint32_t)l.z;
+}
+
+__global__ void k_import_records(Pool P, uint32_t b0, uint32_t n, const uint32_t* in)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t* v = in + 5 * (size_t)i;
+    P.id[b0 + i] = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+    P.link[b0 + i] = make_int4((int32_t)v[2], (int32_t)v[3], (int32_t)v[4], 0);
+    P.fwd[b0 + i] = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+}
+
+// counters of every instance of a batch, gathered into one array
+__global__ void k_gather_counters(Batch B, Counters* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B.n) return;
+    out[i] = *B.inst[i].P.ctr;
+}
+
 // ---------------------------------------------------------------------------
 // host-side launch sequences
 // ---------------------------------------------------------------------------
 
 static inline uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+uint32_t word_groups(const Pool& P) { return cdiv(P.W, kWordsPerBlock); }
+
+int reduce_levels(const Pool& P)
+{
+    const int LW = P.D - 5;
+    return LW < P.sub ? LW : P.sub;
+}
+
+uint32_t reduce_groups(const Pool& P) { return P.W >> reduce_levels(P); }
 
 size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
 {
@@ -1196,24 +1416,25 @@ size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
         off = (off + bytes + 255) & ~(size_t)255;
         return o;
     };
-    const size_t o_id = take(8 * cap), o_link = take(16 * cap), o_cmd = take(4 * cap), o_fwd = take(16 * cap);
-    const size_t o_flat = take(48 * cap), o_world = take(48 * cap);
+    const size_t o_id = take(8 * cap), o_link = take(16 * cap), o_fwd = take(16 * cap);
+    const size_t o_flat = take(48 * cap), o_world = take(48 * cap), o_cmd = take(4 * cap);
     const size_t o_bits = take(4 * W), o_tree = take(4 * TW), o_live = take(4 * cap);
-    const size_t o_free = take(4 * cap), o_list = take(4 * cap), o_lcnt = take(4 * (size_t)kRankGrid);
-    const size_t o_part = take(sizeof(uint2) * kRankGrid), o_ctr = take(sizeof(Counters));
+    const size_t o_free = take(4 * cap), o_list = take(8 * cap), o_lpre = take(4 * cap), o_lcnt = take(4 * (size_t)kMaxRankGroups);
+    const size_t o_part = take(sizeof(uint2) * kMaxRankGroups), o_ctr = take(sizeof(Counters));
     const size_t o_root = take(36 * (size_t)H);
     if (P) {
         P->id = reinterpret_cast<uint64_t*>(base + o_id);
         P->link = reinterpret_cast<int4*>(base + o_link);
-        P->cmd = reinterpret_cast<uint32_t*>(base + o_cmd);
         P->fwd = reinterpret_cast<uint4*>(base + o_fwd);
         P->vflat = reinterpret_cast<float4*>(base + o_flat);
         P->vworld = reinterpret_cast<float4*>(base + o_world);
+        P->cmd = reinterpret_cast<uint32_t*>(base + o_cmd);
         P->bits = reinterpret_cast<uint32_t*>(base + o_bits);
         P->tree = reinterpret_cast<uint32_t*>(base + o_tree);
         P->live = reinterpret_cast<uint32_t*>(base + o_live);
         P->freel = reinterpret_cast<uint32_t*>(base + o_free);
-        P->list = reinterpret_cast<uint32_t*>(base + o_list);
+        P->list = reinterpret_cast<uint2*>(base + o_list);
+        P->lpre = reinterpret_cast<uint32_t*>(base + o_lpre);
         P->lcnt = reinterpret_cast<uint32_t*>(base + o_lcnt);
         P->part = reinterpret_cast<uint2*>(base + o_part);
         P->ctr = reinterpret_cast<Counters*>(base + o_ctr);
@@ -1226,79 +1447,114 @@ size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
     return off;
 }
 
-hipError_t launch_reduce(const Pool& P, hipStream_t s)
+Launch single_launch(const Pool& P, const LodK& K, const uint8_t* inj)
 {
-    const int LW = P.D - 5;
-    const int SUB = LW < kReduceSub ? LW : kReduceSub;
-    const uint32_t blocks = P.W >> SUB;
-    hipLaunchKernelGGL(k_reduce_sub, dim3(blocks), dim3(kBlock), 0, s, P);
-    if (LW > kReduceSub) hipLaunchKernelGGL(k_reduce_top, dim3(1), dim3(1024), 0, s, P);
+    Launch X{};
+    X.batched = false;
+    X.one.P = P;
+    X.one.K = K;
+    X.one.inj = inj;
+    X.B.n = 0;
+    X.n_inst = 1;
+    X.grid_rank = P.G;
+    X.grid_word = word_groups(P);
+    X.grid_red = reduce_groups(P);
+    return X;
+}
+
+template <bool kB>
+static hipError_t reduce_seq(const Launch& X, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_sub<kB>, dim3(X.grid_red), dim3(kBlock), 0, s, X.B, X.one);
+    hipLaunchKernelGGL(k_reduce_top<kB>, dim3(X.n_inst), dim3(1024), 0, s, X.B, X.one);
     return hipGetLastError();
 }
 
-hipError_t launch_enumerate(const Pool& P, hipStream_t s)
+template <bool kB>
+static hipError_t enumerate_seq(const Launch& X, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, P);
-    hipLaunchKernelGGL(k_enumerate, dim3(cdiv(P.W, kWordsPerBlock)), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_begin<kB>, dim3(X.n_inst), dim3(64), 0, s, X.B, X.one);
+    hipLaunchKernelGGL(k_enumerate<kB>, dim3(X.grid_word), dim3(kBlock), 0, s, X.B, X.one);
     return hipGetLastError();
 }
 
-hipError_t launch_refresh(const Pool& P, const LodK& K, int flat, hipStream_t s)
+template <bool kB>
+static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* ev)
 {
-    hipError_t e = launch_enumerate(P, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_refresh, dim3(kRankGrid), dim3(kBlock), 0, s, P, K, flat);
-    return hipGetLastError();
-}
-
-hipError_t launch_frame(const Pool& P, const LodK& K, const uint8_t* decisions, hipStream_t s,
-                        const StageEvents* ev)
-{
-    const dim3 g(kRankGrid), b(kBlock);
-    const dim3 gw(cdiv(P.W, kWordsPerBlock));
+    const dim3 g(X.grid_rank), b(kBlock), gw(X.grid_word), gi(X.n_inst);
     auto mark = [&](int stage, bool begin) {
         if (ev && ev->stage == stage) (void)hipEventRecord(begin ? ev->begin : ev->end, s);
     };
     enum { kEnum = 1, kClass, kVote, kBudget, kChain, kOwners, kOffsets, kFree, kFill, kResolve, kReduce, kFrame };
     mark(kFrame, true);
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, P);
+    hipLaunchKernelGGL(k_begin<kB>, gi, dim3(64), 0, s, X.B, X.one);
     mark(kEnum, true);
-    hipLaunchKernelGGL(k_enumerate, gw, b, 0, s, P);
+    hipLaunchKernelGGL(k_enumerate<kB>, gw, b, 0, s, X.B, X.one);
     mark(kEnum, false);
     mark(kClass, true);
-    if (decisions) hipLaunchKernelGGL(k_classify<true>, g, b, 0, s, P, K, decisions);
-    else hipLaunchKernelGGL(k_classify<false>, g, b, 0, s, P, K, decisions);
+    hipLaunchKernelGGL(k_classify<kB>, g, b, 0, s, X.B, X.one);
     mark(kClass, false);
     mark(kVote, true);
-    hipLaunchKernelGGL(k_vote, g, b, 0, s, P);
+    hipLaunchKernelGGL(k_vote<kB>, g, b, 0, s, X.B, X.one);
     mark(kVote, false);
     mark(kBudget, true);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, P, 0);
-    hipLaunchKernelGGL(k_budget, g, b, 0, s, P);
+    hipLaunchKernelGGL(k_scan_parts<kB>, gi, dim3(1024), 0, s, X.B, X.one, 0);
+    hipLaunchKernelGGL(k_budget<kB>, g, b, 0, s, X.B, X.one);
     mark(kBudget, false);
     mark(kChain, true);
-    hipLaunchKernelGGL(k_walk, g, b, 0, s, P);
+    hipLaunchKernelGGL(k_walk<kB>, g, b, 0, s, X.B, X.one);
     mark(kChain, false);
     mark(kOwners, true);
-    hipLaunchKernelGGL(k_owners, g, b, 0, s, P);
+    hipLaunchKernelGGL(k_owners<kB>, g, b, 0, s, X.B, X.one);
     mark(kOwners, false);
     mark(kOffsets, true);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, P, 1);
+    hipLaunchKernelGGL(k_scan_parts<kB>, gi, dim3(1024), 0, s, X.B, X.one, 1);
     mark(kOffsets, false);
     mark(kFree, true);
-    hipLaunchKernelGGL(k_freelist, gw, b, 0, s, P);
+    hipLaunchKernelGGL(k_freelist<kB>, gw, b, 0, s, X.B, X.one);
     mark(kFree, false);
     mark(kFill, true);
-    hipLaunchKernelGGL(k_fill, g, b, 0, s, P, K);
+    hipLaunchKernelGGL(k_fill<kB>, g, b, 0, s, X.B, X.one);
     mark(kFill, false);
     mark(kResolve, true);
-    hipLaunchKernelGGL(k_resolve, g, b, 0, s, P);
+    hipLaunchKernelGGL(k_resolve<kB>, g, b, 0, s, X.B, X.one);
     mark(kResolve, false);
     mark(kReduce, true);
-    hipError_t e = launch_reduce(P, s);
+    hipError_t e = reduce_seq<kB>(X, s);
     mark(kReduce, false);
     mark(kFrame, false);
     return e;
+}
+
+hipError_t launch_frame(const Launch& X, hipStream_t s, const StageEvents* ev)
+{
+    return X.batched ? frame_seq<true>(X, s, ev) : frame_seq<false>(X, s, ev);
+}
+
+hipError_t launch_reduce(const Launch& X, hipStream_t s)
+{
+    return X.batched ? reduce_seq<true>(X, s) : reduce_seq<false>(X, s);
+}
+
+hipError_t launch_enumerate(const Launch& X, hipStream_t s)
+{
+    return X.batched ? enumerate_seq<true>(X, s) : enumerate_seq<false>(X, s);
+}
+
+hipError_t launch_refresh(const Launch& X, int flat, hipStream_t s)
+{
+    hipError_t e = launch_enumerate(X, s);
+    if (e != hipSuccess) return e;
+    if (X.batched) hipLaunchKernelGGL(k_refresh<true>, dim3(X.grid_rank), dim3(kBlock), 0, s, X.B, X.one, flat);
+    else hipLaunchKernelGGL(k_refresh<false>, dim3(X.grid_rank), dim3(kBlock), 0, s, X.B, X.one, flat);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_counters(const Launch& X, Counters* out, hipStream_t s)
+{
+    if (X.batched && X.n_inst)
+        hipLaunchKernelGGL(k_gather_counters, dim3(cdiv(X.n_inst, kBlock)), dim3(kBlock), 0, s, X.B, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s)
@@ -1335,6 +1591,18 @@ hipError_t launch_gather_decisions(const Pool& P, uint32_t L, uint8_t* out, hipS
 hipError_t launch_export_heap(const Pool& P, uint32_t* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_export_heap, dim3(2048), dim3(kBlock), 0, s, P, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_records(const Pool& P, uint32_t b0, uint32_t n, uint32_t* out5, hipStream_t s)
+{
+    if (n) hipLaunchKernelGGL(k_export_records, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, P, b0, n, out5);
+    return hipGetLastError();
+}
+
+hipError_t launch_import_records(const Pool& P, uint32_t b0, uint32_t n, const uint32_t* in5, hipStream_t s)
+{
+    if (n) hipLaunchKernelGGL(k_import_records, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, P, b0, n, in5);
     return hipGetLastError();
 }
 

@@ -1,0 +1,674 @@
+// Serving loop: tessellation-update requests (instance, camera) arrive at
+// any time; each instance keeps its state resident in device memory while it
+// fits, instances are admitted by their workspace footprint against a
+// memory budget and idle ones are evicted to host snapshots; requests are
+// batched continuously: whenever a launch slot is free, every instance with
+// a queued request and none in flight joins the next batched frame, which
+// runs on the slot's own stream, so batches of different instances overlap
+// on the device.  At most one request per instance is in flight, so each
+// instance sees its requests in arrival order and its result is the one it
+// gets alone.
+
+#include "cbt_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+using cbtk::Counters;
+using cbtk::Inst;
+using cbtk::LodK;
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+    uint64_t tag;
+    cbt_camera cam;
+    double t_arrive;
+};
+
+struct SInst {
+    int64_t id = 0;
+    std::vector<int32_t> twin, next, prev, vert;
+    std::vector<float> pos;
+    int32_t H = 0, V = 0, D = 0;
+    cbt_lod_params lod{};
+    int32_t groups = 0, levels = 0;   // schedule (0: library default)
+    cbt_handle h = nullptr;
+    size_t off = 0, bytes = 0;
+    bool has_snapshot = false;
+    std::vector<uint64_t> s_id;
+    std::vector<int32_t> s_twin, s_next, s_prev;
+    std::deque<Req> q;
+    int slot = -1;
+    double last_used = 0.0;
+    bool failed = false;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    Inst* d_inst = nullptr;
+    Counters* d_ctr = nullptr;
+    uint32_t* d_map = nullptr;
+    Inst* h_inst = nullptr;
+    uint32_t* h_map = nullptr;
+    Counters* h_ctr = nullptr;
+    std::vector<int64_t> ids;
+    std::vector<Req> reqs;
+    double t_launch = 0.0;
+    uint64_t seq = 0;
+};
+
+}  // namespace
+
+struct cbt_server_s {
+    cbt_server_config cfg{};
+    char* arena = nullptr;
+    size_t inst_base = 0, inst_bytes = 0, budget = 0, used = 0;
+    std::map<size_t, size_t> free_;    // offset -> length, within the instance area
+    hipStream_t aux = nullptr;         // admission, eviction and queries
+    std::vector<Slot> slots;
+    std::unordered_map<int64_t, SInst> inst;
+    int64_t next_id = 1;
+    uint64_t next_seq = 1;
+    std::deque<cbt_completion> done_q;
+    cbt_server_stats st{};
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bool arena_alloc(cbt_server s, size_t bytes, size_t* off)
+{
+    bytes = round_up(bytes);
+    if (s->used + bytes > s->budget) return false;
+    for (auto it = s->free_.begin(); it != s->free_.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t roff = it->first + bytes;
+            s->free_.erase(it);
+            if (rest) s->free_[roff] = rest;
+            s->used += bytes;
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(cbt_server s, size_t off, size_t bytes)
+{
+    bytes = round_up(bytes);
+    s->used -= bytes;
+    auto it = s->free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != s->free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        s->free_.erase(nx);
+    }
+    if (it != s->free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            s->free_.erase(it);
+        }
+    }
+}
+
+cbt_status evict(cbt_server s, SInst& I)
+{
+    if (!I.h) return CBT_OK;
+    const size_t cap = (size_t)1 << I.D;
+    I.s_id.resize(cap);
+    I.s_twin.resize(cap);
+    I.s_next.resize(cap);
+    I.s_prev.resize(cap);
+    cbt_status st = cbt_snapshot(I.h, I.s_id.data(), I.s_twin.data(), I.s_next.data(), I.s_prev.data());
+    if (st) {
+        I.failed = true;
+        return st;
+    }
+    I.has_snapshot = true;
+    cbt_destroy(I.h);
+    I.h = nullptr;
+    arena_free(s, I.off, I.bytes);
+    s->st.evictions++;
+    s->st.resident--;
+    s->st.bytes_resident = (int64_t)s->used;
+    return CBT_OK;
+}
+
+// Makes I resident: allocates its workspace (evicting idle instances, least
+// recently used first, when the budget is exhausted), initialises it and
+// restores its snapshot.  CBT_E_BUDGET: cannot fit now.
+cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
+{
+    if (I.h) return CBT_OK;
+    const size_t bytes = cbt_workspace_bytes(I.H, I.D);
+    if (!bytes) return cbth::fail(nullptr, CBT_E_DEPTH, "instance %lld: invalid depth", (long long)I.id);
+    if (round_up(bytes) > s->budget) {
+        I.failed = true;
+        return cbth::fail(nullptr, CBT_E_BUDGET, "instance %lld needs %zu bytes, budget %zu", (long long)I.id, bytes,
+                          s->budget);
+    }
+    size_t off = 0;
+    while (!arena_alloc(s, bytes, &off)) {
+        SInst* victim = nullptr;
+        for (auto& kv : s->inst) {
+            SInst& J = kv.second;
+            if (!J.h || J.slot >= 0 || &J == &I || !J.q.empty()) continue;
+            if (std::find(pinned.begin(), pinned.end(), J.id) != pinned.end()) continue;
+            if (!victim || J.last_used < victim->last_used) victim = &J;
+        }
+        if (!victim) return CBT_E_BUDGET;
+        cbt_status st = evict(s, *victim);
+        if (st) return st;
+    }
+    cbt_mesh m{I.H, I.twin.data(), I.next.data(), I.prev.data(), I.vert.data(), I.V, I.pos.data()};
+    cbt_handle h = nullptr;
+    cbt_status st = cbt_init(&m, I.D, s->arena + s->inst_base + off, bytes, s->aux, &h);
+    if (st) {
+        arena_free(s, off, bytes);
+        I.failed = true;
+        return st;
+    }
+    if (I.groups) {
+        st = cbt_set_schedule(h, I.groups, I.levels);
+        if (st) {
+            cbt_destroy(h);
+            arena_free(s, off, bytes);
+            I.failed = true;
+            return st;
+        }
+    }
+    if (I.has_snapshot) {
+        st = cbt_restore(h, I.s_id.data(), I.s_twin.data(), I.s_next.data(), I.s_prev.data());
+        if (st) {
+            cbt_destroy(h);
+            arena_free(s, off, bytes);
+            I.failed = true;
+            return st;
+        }
+        I.has_snapshot = false;
+        std::vector<uint64_t>().swap(I.s_id);
+        std::vector<int32_t>().swap(I.s_twin);
+        std::vector<int32_t>().swap(I.s_next);
+        std::vector<int32_t>().swap(I.s_prev);
+    }
+    I.h = h;
+    I.off = off;
+    I.bytes = bytes;
+    s->st.admissions++;
+    s->st.resident++;
+    s->st.bytes_resident = (int64_t)s->used;
+    return CBT_OK;
+}
+
+void complete(cbt_server s, SInst& I, const Req& r, cbt_status status, const Counters* c, double t_launch,
+              int32_t batch_size, double t_done)
+{
+    cbt_completion o{};
+    o.tag = r.tag;
+    o.instance = I.id;
+    o.status = status;
+    o.batch_size = batch_size;
+    o.latency_ms = (t_done - r.t_arrive) * 1e3;
+    o.queue_ms = (t_launch - r.t_arrive) * 1e3;
+    if (c) {
+        o.live_before = c->L;
+        o.live_after = (int64_t)c->L + c->N - c->stat[cbtk::kStFrees];
+    }
+    s->done_q.push_back(o);
+}
+
+// Collects a finished batch.
+void harvest(cbt_server s, Slot& S)
+{
+    const double t = now_s();
+    const int32_t n = (int32_t)S.ids.size();
+    for (int32_t i = 0; i < n; ++i) {
+        auto it = s->inst.find(S.ids[i]);
+        if (it == s->inst.end()) continue;
+        SInst& I = it->second;
+        const Counters& c = S.h_ctr[i];
+        cbt_status status = CBT_OK;
+        if (c.err) {
+            status = CBT_E_DEVICE;
+            I.failed = true;
+            if (I.h) I.h->failed = 1;
+        } else if (I.h) {
+            I.h->last_frame_valid = 1;
+        }
+        I.slot = -1;
+        I.last_used = t;
+        s->st.frames++;
+        s->st.bisector_updates += c.L;
+        complete(s, I, S.reqs[i], status, &c, S.t_launch, n, t);
+    }
+    S.ids.clear();
+    S.reqs.clear();
+    S.busy = false;
+    s->st.in_flight--;
+}
+
+cbt_status launch_slot(cbt_server s, Slot& S)
+{
+    // candidates: queued, idle, not failed; oldest request first
+    std::vector<SInst*> cand;
+    for (auto& kv : s->inst) {
+        SInst& I = kv.second;
+        if (I.q.empty() || I.slot >= 0) continue;
+        if (I.failed) {
+            while (!I.q.empty()) {
+                complete(s, I, I.q.front(), CBT_E_STATE, nullptr, now_s(), 0, now_s());
+                I.q.pop_front();
+            }
+            continue;
+        }
+        cand.push_back(&I);
+    }
+    if (cand.empty()) return CBT_OK;
+    std::sort(cand.begin(), cand.end(),
+              [](const SInst* a, const SInst* b) { return a->q.front().t_arrive < b->q.front().t_arrive; });
+    std::vector<SInst*> pick;
+    std::vector<int64_t> pinned;
+    uint64_t nr = 0, nw = 0, nd = 0;
+    for (SInst* I : cand) {
+        if ((int32_t)pick.size() >= s->cfg.max_batch) break;
+        cbt_status st = admit(s, *I, pinned);
+        if (st == CBT_E_BUDGET && !I->failed) continue;   // waits for memory
+        if (st) {
+            while (!I->q.empty()) {
+                complete(s, *I, I->q.front(), st, nullptr, now_s(), 0, now_s());
+                I->q.pop_front();
+            }
+            continue;
+        }
+        const cbtk::Pool& P = I->h->P;
+        const uint64_t r = P.G, w = cbtk::word_groups(P), d = cbtk::reduce_groups(P);
+        if ((nr + r) + (nw + w) + (nd + d) > (uint64_t)s->cfg.map_capacity) break;
+        nr += r;
+        nw += w;
+        nd += d;
+        pick.push_back(I);
+        pinned.push_back(I->id);
+    }
+    if (pick.empty()) return CBT_OK;
+    const int n = (int)pick.size();
+    uint32_t* mr = S.h_map;
+    uint32_t* mw = mr + nr;
+    uint32_t* md = mw + nw;
+    uint32_t ar = 0, aw = 0, ad = 0;
+    S.ids.clear();
+    S.reqs.clear();
+    for (int i = 0; i < n; ++i) {
+        SInst& I = *pick[i];
+        const Req r = I.q.front();
+        I.q.pop_front();
+        LodK K;
+        cbth::make_lodk(&r.cam, &I.lod, &K);
+        cbt_handle h = I.h;
+        if (cbth::world_changed(K, h->wk)) {
+            h->wk = K;
+            HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), 0, S.stream), "vertex cache");
+        }
+        S.h_inst[i].P = h->P;
+        S.h_inst[i].K = K;
+        S.h_inst[i].inj = nullptr;
+        const uint32_t tag = (uint32_t)i << cbtk::kMapShift;
+        for (uint32_t g = 0; g < h->P.G; ++g) mr[ar++] = tag | g;
+        for (uint32_t g = 0; g < cbtk::word_groups(h->P); ++g) mw[aw++] = tag | g;
+        for (uint32_t g = 0; g < cbtk::reduce_groups(h->P); ++g) md[ad++] = tag | g;
+        I.slot = (int)(&S - s->slots.data());
+        S.ids.push_back(I.id);
+        S.reqs.push_back(r);
+    }
+    cbtk::Launch X{};
+    X.batched = true;
+    X.B.n = n;
+    X.B.inst = S.d_inst;
+    X.B.map_rank = S.d_map;
+    X.B.map_word = S.d_map + nr;
+    X.B.map_red = S.d_map + nr + nw;
+    X.n_inst = (uint32_t)n;
+    X.grid_rank = (uint32_t)nr;
+    X.grid_word = (uint32_t)nw;
+    X.grid_red = (uint32_t)nd;
+    hipStream_t st = S.stream;
+    HIP_TRY(nullptr, hipMemcpyAsync(S.d_inst, S.h_inst, sizeof(Inst) * (size_t)n, hipMemcpyHostToDevice, st), "descriptors");
+    HIP_TRY(nullptr, hipMemcpyAsync(S.d_map, S.h_map, 4 * (size_t)(nr + nw + nd), hipMemcpyHostToDevice, st), "block maps");
+    HIP_TRY(nullptr, cbtk::launch_frame(X, st, nullptr), "batched frame");
+    HIP_TRY(nullptr, cbtk::launch_gather_counters(X, S.d_ctr, st), "gather counters");
+    HIP_TRY(nullptr, hipMemcpyAsync(S.h_ctr, S.d_ctr, sizeof(Counters) * (size_t)n, hipMemcpyDeviceToHost, st), "counters");
+    HIP_TRY(nullptr, hipEventRecord(S.done, st), "batch event");
+    S.busy = true;
+    S.t_launch = now_s();
+    S.seq = s->next_seq++;
+    s->st.batches++;
+    s->st.in_flight++;
+    return CBT_OK;
+}
+
+cbt_status progress(cbt_server s)
+{
+    for (Slot& S : s->slots) {
+        if (!S.busy) continue;
+        const hipError_t e = hipEventQuery(S.done);
+        if (e == hipSuccess) harvest(s, S);
+        else if (e != hipErrorNotReady) return cbth::hip_fail(nullptr, e, "batch event");
+    }
+    for (Slot& S : s->slots) {
+        if (S.busy) continue;
+        cbt_status st = launch_slot(s, S);
+        if (st) return st;
+    }
+    return CBT_OK;
+}
+
+Slot* oldest_busy(cbt_server s)
+{
+    Slot* o = nullptr;
+    for (Slot& S : s->slots)
+        if (S.busy && (!o || S.seq < o->seq)) o = &S;
+    return o;
+}
+
+// workgroups of the three batched grids one instance adds
+uint64_t grid_need(int32_t D, int32_t groups, int32_t levels)
+{
+    cbtk::Pool P{};
+    P.D = D;
+    P.W = (uint32_t)((1ull << D) / 32);
+    P.G = groups ? (uint32_t)groups : cbth::default_rank_groups(D);
+    P.sub = levels ? levels : cbtk::kMaxReduceSub;
+    return (uint64_t)P.G + cbtk::word_groups(P) + cbtk::reduce_groups(P);
+}
+
+size_t slot_bytes(const cbt_server_config& c)
+{
+    return round_up(sizeof(Inst) * (size_t)c.max_batch) + round_up(sizeof(Counters) * (size_t)c.max_batch) +
+           round_up(4 * (size_t)c.map_capacity);
+}
+
+void destroy_slots(cbt_server s)
+{
+    for (Slot& S : s->slots) {
+        if (S.stream) (void)hipStreamSynchronize(S.stream);
+        if (S.done) (void)hipEventDestroy(S.done);
+        if (S.stream) (void)hipStreamDestroy(S.stream);
+        if (S.h_inst) (void)hipHostFree(S.h_inst);
+        if (S.h_map) (void)hipHostFree(S.h_map);
+        if (S.h_ctr) (void)hipHostFree(S.h_ctr);
+    }
+    s->slots.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t cbt_server_overhead_bytes(const cbt_server_config* cfg)
+{
+    if (!cfg || cfg->max_batch < 1 || cfg->max_batch > cbtk::kMaxBatch || cfg->slots < 1 || cfg->slots > 8 ||
+        cfg->map_capacity < 1)
+        return 0;
+    return slot_bytes(*cfg) * (size_t)cfg->slots;
+}
+
+cbt_status cbt_server_create(const cbt_server_config* cfg, void* device_arena, size_t arena_bytes, cbt_server* out)
+{
+    if (!out) return cbth::fail(nullptr, CBT_E_ARG, "output server pointer is NULL");
+    *out = nullptr;
+    const size_t over = cbt_server_overhead_bytes(cfg);
+    if (!over) return cbth::fail(nullptr, CBT_E_ARG, "invalid server configuration");
+    if (!device_arena || (reinterpret_cast<uintptr_t>(device_arena) & (kAlign - 1)))
+        return cbth::fail(nullptr, CBT_E_ARG, "device arena must be non-NULL and 256-byte aligned");
+    if (arena_bytes < over + kAlign) return cbth::fail(nullptr, CBT_E_BUDGET, "arena smaller than the launch slots (%zu bytes)", over);
+    cbt_server s = new (std::nothrow) cbt_server_s();
+    if (!s) return cbth::fail(nullptr, CBT_E_ARG, "out of host memory");
+    s->cfg = *cfg;
+    s->arena = reinterpret_cast<char*>(device_arena);
+    s->inst_base = over;
+    s->inst_bytes = (arena_bytes - over) & ~(kAlign - 1);
+    s->budget = cfg->memory_budget > 0 && (size_t)cfg->memory_budget < s->inst_bytes ? (size_t)cfg->memory_budget
+                                                                                      : s->inst_bytes;
+    s->free_[0] = s->inst_bytes;
+    s->st.bytes_budget = (int64_t)s->budget;
+    bool ok = hipStreamCreate(&s->aux) == hipSuccess;
+    s->slots.resize(cfg->slots);
+    for (int i = 0; i < cfg->slots && ok; ++i) {
+        Slot& S = s->slots[i];
+        char* base = s->arena + slot_bytes(*cfg) * (size_t)i;
+        S.d_inst = reinterpret_cast<Inst*>(base);
+        S.d_ctr = reinterpret_cast<Counters*>(base + round_up(sizeof(Inst) * (size_t)cfg->max_batch));
+        S.d_map = reinterpret_cast<uint32_t*>(base + round_up(sizeof(Inst) * (size_t)cfg->max_batch) +
+                                              round_up(sizeof(Counters) * (size_t)cfg->max_batch));
+        ok = hipStreamCreate(&S.stream) == hipSuccess &&
+             hipEventCreateWithFlags(&S.done, hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void**>(&S.h_inst), sizeof(Inst) * (size_t)cfg->max_batch,
+                           hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void**>(&S.h_map), 4 * (size_t)cfg->map_capacity, hipHostMallocDefault) ==
+                 hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void**>(&S.h_ctr), sizeof(Counters) * (size_t)cfg->max_batch,
+                           hipHostMallocDefault) == hipSuccess;
+    }
+    if (!ok) {
+        destroy_slots(s);
+        if (s->aux) (void)hipStreamDestroy(s->aux);
+        delete s;
+        return cbth::fail(nullptr, CBT_E_DEVICE, "stream, event or pinned allocation failed");
+    }
+    *out = s;
+    return CBT_OK;
+}
+
+cbt_status cbt_server_open(cbt_server s, const cbt_mesh* mesh, int32_t D, const cbt_lod_params* lod,
+                           int64_t* instance_id)
+{
+    if (!s || !mesh || !lod || !instance_id) return cbth::fail(nullptr, CBT_E_ARG, "NULL argument");
+    cbt_status st = cbth::validate_mesh(mesh);
+    if (st) return st;
+    if (!cbt_workspace_bytes(mesh->H, D)) return cbth::fail(nullptr, CBT_E_DEPTH, "invalid H / depth");
+    if (grid_need(D, 0, 0) > (uint64_t)s->cfg.map_capacity)
+        return cbth::fail(nullptr, CBT_E_ARG, "depth %d needs more workgroups than the map capacity", D);
+    cbt_camera probe{{0, 0, 1}, {0, 0, -1}, {0, 1, 0}, 1.0f, 16, 16, 1e-3f};
+    st = cbth::check_lod(nullptr, &probe, lod);
+    if (st) return st;
+    SInst I;
+    I.id = s->next_id++;
+    I.H = mesh->H;
+    I.V = mesh->V;
+    I.D = D;
+    I.lod = *lod;
+    I.twin.assign(mesh->twin, mesh->twin + mesh->H);
+    I.next.assign(mesh->next, mesh->next + mesh->H);
+    I.prev.assign(mesh->prev, mesh->prev + mesh->H);
+    I.vert.assign(mesh->vert, mesh->vert + mesh->H);
+    I.pos.assign(mesh->pos, mesh->pos + 3 * (size_t)mesh->V);
+    I.last_used = now_s();
+    const int64_t id = I.id;
+    s->inst.emplace(id, std::move(I));
+    s->st.instances++;
+    // the mesh is validated now (and the instance admitted when it fits)
+    std::vector<int64_t> none;
+    st = admit(s, s->inst[id], none);
+    if (st && st != CBT_E_BUDGET) {
+        s->inst.erase(id);
+        s->st.instances--;
+        return st;
+    }
+    if (st == CBT_E_BUDGET && s->inst[id].failed) {
+        s->inst.erase(id);
+        s->st.instances--;
+        return cbth::fail(nullptr, CBT_E_BUDGET, "instance does not fit the memory budget");
+    }
+    *instance_id = id;
+    return CBT_OK;
+}
+
+cbt_status cbt_server_set_schedule(cbt_server s, int64_t instance_id, int32_t rank_groups, int32_t reduce_levels)
+{
+    if (!s) return cbth::fail(nullptr, CBT_E_ARG, "NULL server");
+    auto it = s->inst.find(instance_id);
+    if (it == s->inst.end()) return cbth::fail(nullptr, CBT_E_ARG, "unknown instance %lld", (long long)instance_id);
+    SInst& I = it->second;
+    if (I.slot >= 0) return cbth::fail(nullptr, CBT_E_STATE, "instance has a request in flight");
+    if (grid_need(I.D, rank_groups, reduce_levels) > (uint64_t)s->cfg.map_capacity)
+        return cbth::fail(nullptr, CBT_E_ARG, "schedule needs more workgroups than the map capacity");
+    if (I.h) {
+        cbt_status st = cbt_set_schedule(I.h, rank_groups, reduce_levels);
+        if (st) return st;
+    } else if (rank_groups < cbtk::kMinRankGroups || rank_groups > cbtk::kMaxRankGroups ||
+               reduce_levels < cbtk::kMinReduceSub || reduce_levels > cbtk::kMaxReduceSub) {
+        return cbth::fail(nullptr, CBT_E_ARG, "schedule out of range");
+    }
+    I.groups = rank_groups;
+    I.levels = reduce_levels;
+    return CBT_OK;
+}
+
+cbt_status cbt_server_submit(cbt_server s, int64_t instance_id, const cbt_camera* camera, uint64_t tag)
+{
+    if (!s || !camera) return cbth::fail(nullptr, CBT_E_ARG, "NULL argument");
+    auto it = s->inst.find(instance_id);
+    if (it == s->inst.end()) return cbth::fail(nullptr, CBT_E_ARG, "unknown instance %lld", (long long)instance_id);
+    SInst& I = it->second;
+    if (I.failed) return cbth::fail(nullptr, CBT_E_STATE, "instance %lld failed earlier", (long long)instance_id);
+    cbt_status st = cbth::check_lod(nullptr, camera, &I.lod);
+    if (st) return st;
+    I.q.push_back(Req{tag, *camera, now_s()});
+    s->st.requests++;
+    return CBT_OK;
+}
+
+cbt_status cbt_server_poll(cbt_server s, int32_t wait, cbt_completion* out, int32_t capacity, int32_t* count)
+{
+    if (!s || !count || (capacity > 0 && !out) || capacity < 0) return cbth::fail(nullptr, CBT_E_ARG, "invalid argument");
+    *count = 0;
+    cbt_status st = progress(s);
+    if (st) return st;
+    if (wait && s->done_q.empty()) {
+        Slot* o = oldest_busy(s);
+        if (o) {
+            HIP_TRY(nullptr, hipEventSynchronize(o->done), "batch wait");
+            st = progress(s);
+            if (st) return st;
+        }
+    }
+    int32_t n = 0;
+    while (n < capacity && !s->done_q.empty()) {
+        out[n++] = s->done_q.front();
+        s->done_q.pop_front();
+    }
+    *count = n;
+    return CBT_OK;
+}
+
+cbt_status cbt_server_drain(cbt_server s)
+{
+    if (!s) return cbth::fail(nullptr, CBT_E_ARG, "NULL server");
+    for (;;) {
+        cbt_status st = progress(s);
+        if (st) return st;
+        Slot* o = oldest_busy(s);
+        if (!o) {
+            bool queued = false;
+            for (auto& kv : s->inst) queued = queued || (!kv.second.q.empty() && !kv.second.failed);
+            if (!queued) return CBT_OK;
+            // queued requests that cannot be admitted with nothing in flight
+            // wait for memory that no completion will free
+            bool admissible = false;
+            for (auto& kv : s->inst) admissible = admissible || (!kv.second.q.empty() && kv.second.h);
+            if (!admissible) return cbth::fail(nullptr, CBT_E_BUDGET, "queued instances do not fit the memory budget");
+            continue;
+        }
+        HIP_TRY(nullptr, hipEventSynchronize(o->done), "batch wait");
+    }
+}
+
+cbt_status cbt_server_query(cbt_server s, int64_t instance_id, cbt_bisectors* out)
+{
+    if (!s || !out) return cbth::fail(nullptr, CBT_E_ARG, "NULL argument");
+    auto it = s->inst.find(instance_id);
+    if (it == s->inst.end()) return cbth::fail(nullptr, CBT_E_ARG, "unknown instance %lld", (long long)instance_id);
+    SInst& I = it->second;
+    if (I.slot >= 0) {
+        Slot& S = s->slots[I.slot];
+        HIP_TRY(nullptr, hipEventSynchronize(S.done), "batch wait");
+        harvest(s, S);
+    }
+    if (I.failed) return cbth::fail(nullptr, CBT_E_STATE, "instance %lld failed", (long long)instance_id);
+    std::vector<int64_t> none;
+    cbt_status st = admit(s, I, none);
+    if (st) return st;
+    I.last_used = now_s();
+    return cbt_query(I.h, out);
+}
+
+cbt_status cbt_server_close(cbt_server s, int64_t instance_id)
+{
+    if (!s) return cbth::fail(nullptr, CBT_E_ARG, "NULL server");
+    auto it = s->inst.find(instance_id);
+    if (it == s->inst.end()) return cbth::fail(nullptr, CBT_E_ARG, "unknown instance %lld", (long long)instance_id);
+    SInst& I = it->second;
+    if (I.slot >= 0) {
+        Slot& S = s->slots[I.slot];
+        HIP_TRY(nullptr, hipEventSynchronize(S.done), "batch wait");
+        harvest(s, S);
+    }
+    while (!I.q.empty()) {
+        complete(s, I, I.q.front(), CBT_E_STATE, nullptr, now_s(), 0, now_s());
+        I.q.pop_front();
+    }
+    if (I.h) {
+        cbt_destroy(I.h);
+        arena_free(s, I.off, I.bytes);
+        s->st.resident--;
+        s->st.bytes_resident = (int64_t)s->used;
+    }
+    s->inst.erase(it);
+    s->st.instances--;
+    return CBT_OK;
+}
+
+cbt_status cbt_server_get_stats(cbt_server s, cbt_server_stats* out)
+{
+    if (!s || !out) return cbth::fail(nullptr, CBT_E_ARG, "NULL argument");
+    int64_t queued = 0;
+    for (auto& kv : s->inst) queued += (int64_t)kv.second.q.size();
+    *out = s->st;
+    out->queued = queued;
+    return CBT_OK;
+}
+
+cbt_status cbt_server_destroy(cbt_server s)
+{
+    if (!s) return CBT_OK;
+    destroy_slots(s);
+    for (auto& kv : s->inst)
+        if (kv.second.h) cbt_destroy(kv.second.h);
+    if (s->aux) {
+        (void)hipStreamSynchronize(s->aux);
+        (void)hipStreamDestroy(s->aux);
+    }
+    delete s;
+    return CBT_OK;
+}
+
+}  // extern "C"

@@ -521,3 +521,25 @@ def workload(name: str, frames: int | None = None, table_res: int | None = None)
         cams = camera_path_terrain(frames or 512, seed=3, table=table, amplitude=amp)
         return Workload(name, mesh_grid(64), 24, LodParams(MODE_HEIGHTFIELD, 2.0, 1.0, table, amp), cams)
     raise KeyError(name)
+
+
+def batched_workloads(n: int, frames: int = 64, seed: int = 4, h_range=(24, 50000), d_range=(14, 22),
+                      table_res: int = 256) -> List[Workload]:
+    """Independent instances for the batched configuration: closed tri/quad
+    sphere meshes with a log-uniform halfedge count in h_range, CBT depth
+    uniform in d_range (raised to ceil(log2 H) where needed), sphere
+    projection with one shared seeded fBm cube map (amplitude 1e-3 radius),
+    and a seeded orbit camera path of its own per instance (4 -> 1.05 radii,
+    split above 4 px, merge below 2 px at 1920x1080)."""
+    rng = np.random.default_rng(seed)
+    table = fbm_cubemap(table_res, seed=seed + 101)
+    lod = LodParams(MODE_SPHERE, 4.0, 2.0, table, 1e-3)
+    out = []
+    lo, hi = math.log(h_range[0]), math.log(h_range[1])
+    for i in range(n):
+        target = int(round(math.exp(rng.uniform(lo, hi))))
+        mesh = random_mesh_of_size(max(24, target), int(rng.integers(1 << 30)))
+        D = depth_for(mesh.H, int(rng.integers(d_range[0], d_range[1] + 1)))
+        cams = camera_path_orbit(frames, int(rng.integers(1 << 30)))
+        out.append(Workload(f"batched-{i}", mesh, D, lod, cams))
+    return out

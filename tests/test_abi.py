@@ -81,21 +81,20 @@ def test_workspace_follows_paper_memory_model():
     """Per pool block the paper keeps three 32-bit pointers, a 64-bit index,
     a 32-bit command and four 32-bit allocation slots (40 bytes), plus two
     32-bit cached decode results; at D = 17 that, with a 2^18-entry CBT, is
-    7 MiB.  This library keeps the same 40-byte record (ID; twin, next,
-    prev; command; four forwarding slots) and the same 8 bytes of rank and
-    free lists, adds 4 bytes of padding (16-byte pointer records), a 96-byte
-    vertex cache and a 4-byte merge list, and stores the bitfield plus a
-    tree that stops at the word level instead of the 2^(D+1) heap."""
+    7 MiB.  This library keeps the same index (8), pointers (12, padded to
+    16 with the bisector's fate this frame), command (4) and four slots
+    (16), the same 8 bytes of rank and free lists, a 12-byte work list and a
+    96-byte vertex cache, and stores the bitfield plus a tree that stops at
+    the word level instead of the 2^(D+1) heap."""
     g = read_golden("we4_memory.txt")
     D = int(g["D"])
     paper = (1 << D) * (3 * 4 + 8 + 4 + 4 * 4) + (1 << D) * 8 + (1 << (D + 1)) * 4
     assert paper == int(g["total_mib"]) << 20
     ours = cbt.workspace_bytes(60, D)
-    record_and_lists = (1 << D) * (40 + 8)
-    additions = (1 << D) * (4 + 96 + 4)
+    per_block = (8 + 16 + 4 + 16) + 8 + 12 + 96
     cbt_bytes = (1 << D) // 8 + (1 << (D - 4)) * 4
-    assert ours >= record_and_lists + additions + cbt_bytes
-    assert ours <= record_and_lists + additions + cbt_bytes + 64 * 1024
+    assert ours >= (1 << D) * per_block + cbt_bytes
+    assert ours <= (1 << D) * per_block + cbt_bytes + 64 * 1024
     assert cbt_bytes < (1 << (D + 1)) * 4
 
 

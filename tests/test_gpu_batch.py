@@ -1,0 +1,88 @@
+"""Batched update (cbt_batch_*): many instances of uneven mesh size and
+depth advanced by shared launches, eagerly or from a captured HIP graph,
+must give every member exactly the state it gets alone (and the CPU
+reference's state)."""
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+from oracle import Oracle
+from paper_2407_02215_amd import cbt
+from paper_2407_02215_amd import inputs as I
+from tests.gpu_checks import assert_same_state, assert_same_tree, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _same_pool(a, b, label):
+    for name, x, y in zip(("heap_id", "twin", "next", "prev"), a.pool(), b.pool()):
+        bad = np.nonzero(x != y)[0]
+        assert bad.size == 0, f"{label} {name}: {bad.size} mismatches, first {bad[:5].tolist()}"
+    ta = a.query(tree=True)["tree"]
+    tb = b.query(tree=True)["tree"]
+    assert np.array_equal(ta, tb), f"{label}: trees differ"
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batched_matches_single_instances(graph):
+    ws = I.batched_workloads(10, frames=14, seed=5, h_range=(24, 4000), d_range=(12, 16), table_res=64)
+    log(f"[batch graph={graph}] H={[w.mesh.H for w in ws]} D={[w.depth for w in ws]}")
+    alone = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
+    members = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
+    # uneven schedules inside one batch: the smallest grid, and the default
+    for i, m in enumerate(members):
+        if i % 3 == 0:
+            m.set_schedule(16, 5)
+    batch = cbt.Batch(members, graph=graph)
+    for f in range(len(ws[0].cameras)):
+        for a, w in zip(alone, ws):
+            a.update(w.cameras[f])
+        batch.update([w.cameras[f] for w in ws])
+    batch.synchronize()
+    torch.cuda.synchronize()
+    grew = 0
+    for i, (a, m) in enumerate(zip(alone, members)):
+        _same_pool(a, m, f"member {i}")
+        grew += a.live_count() > ws[i].mesh.H
+    assert grew >= len(ws) // 2
+    batch.close()
+    for x in alone + members:
+        x.close()
+
+
+def test_batched_members_match_reference():
+    ws = I.batched_workloads(4, frames=10, seed=9, h_range=(24, 600), d_range=(12, 14), table_res=64)
+    members = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
+    orcs = [Oracle(w.mesh, w.depth, w.lod) for w in ws]
+    batch = cbt.Batch(members, graph=True)
+    for f in range(len(ws[0].cameras)):
+        stats = batch.update([w.cameras[f] for w in ws], stats=True)
+        for i, (o, w) in enumerate(zip(orcs, ws)):
+            st = o.frame(camera=w.cameras[f])
+            assert stats[i]["live_before"] == st.live_before
+            assert stats[i]["allocations"] == st.allocations, f"member {i} frame {f}"
+            assert stats[i]["frees"] == st.frees
+    for i, (m, o) in enumerate(zip(members, orcs)):
+        assert_same_state(m, o, f"member {i}")
+        assert_same_tree(m, o, f"member {i}")
+    batch.close()
+
+
+def test_batched_injected_decisions_match_reference():
+    meshes = [(I.mesh_cube(), 10), (I.mesh_icosahedron(), 12), (I.mesh_quad_sphere(3, 0.5, 11), 11),
+              (I.mesh_two_triangles(False), 8)]
+    members = [cbt.Instance(m, D) for m, D in meshes]
+    orcs = [Oracle(m, D) for m, D in meshes]
+    batch = cbt.Batch(members, graph=True)
+    rng = np.random.default_rng(21)
+    for f in range(12):
+        ps, pm = (0.5, 0.1) if f < 6 else (0.1, 0.6)
+        decs = [I.random_decisions(o.cap, int(rng.integers(1 << 30)), ps, pm) for o in orcs]
+        batch.update_with_decisions(decs)
+        for o, d in zip(orcs, decs):
+            o.frame(decisions=d)
+    batch.synchronize()
+    for i, (m, o) in enumerate(zip(members, orcs)):
+        assert_same_state(m, o, f"member {i}")
+        assert_same_tree(m, o, f"member {i}")
+    batch.close()

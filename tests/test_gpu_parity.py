@@ -229,3 +229,22 @@ def test_restore_from_reference_state():
         orc.frame(decisions=dec)
         assert_same_state(inst, orc, f"after restore frame {f}")
     inst.close()
+
+
+@pytest.mark.parametrize("groups,levels", [(16, 5), (64, 7), (2048, 10)])
+def test_schedule_does_not_change_results(groups, levels):
+    """Launch schedules (rank workgroups, reduction levels per workgroup)
+    change only how the work is cut: every schedule gives the reference's
+    state, including ragged last chunks and many empty workgroups."""
+    w = I.workload("planet", frames=256, table_res=64)
+    inst = cbt.Instance(w.mesh, w.depth, w.lod)
+    inst.set_schedule(groups, levels)
+    assert inst.schedule() == (groups, levels)
+    orc = Oracle(w.mesh, w.depth, w.lod)
+    log(f"[schedule] groups={groups} levels={levels}")
+    for f, cam in enumerate(w.cameras[:20]):
+        inst.update(cam)
+        orc.frame(camera=cam)
+    assert_same_state(inst, orc, f"schedule {groups}/{levels}")
+    assert_same_tree(inst, orc, f"schedule {groups}/{levels}")
+    inst.close()
