@@ -171,6 +171,25 @@ cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_para
 cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisions,
                                      cbt_frame_stats* stats);
 
+/* Multi-pass mode: the update repeated with the same camera until a pass
+ * changes nothing (no allocation, no release) or max_passes passes ran, for
+ * cold starts and camera cuts (the single pass per frame of Section 3.3
+ * refines at most one level per frame).  passes receives the passes run;
+ * last, if non-NULL, the last pass's counters.  Synchronises after every
+ * pass. */
+cbt_status cbt_update_converge(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod,
+                               int32_t max_passes, int32_t* passes, cbt_frame_stats* last);
+
+/* Triangle export, the step after the update (Section 4.1: the leaves are
+ * rasterised): the world positions of the three vertices (v0, v1, v2) of
+ * every live bisector, in ascending block order, 9 floats per triangle,
+ * written to the DEVICE array device_out of capacity triangles.  Shared
+ * edges have bit-identical endpoints (watertight).  count receives the live
+ * count; CBT_E_CAPACITY (nothing written) when it exceeds capacity.
+ * Synchronises once (to read the count); the export itself is
+ * asynchronous on the handle's stream. */
+cbt_status cbt_export_triangles(cbt_handle h, float* device_out, int64_t capacity, int64_t* count);
+
 /* Copies the live bisectors (and optionally vertices and the CBT heap) to
  * host arrays; synchronises the stream. */
 cbt_status cbt_query(cbt_handle h, cbt_bisectors* out);
@@ -214,7 +233,8 @@ enum {
     CBT_STAGE_FILL = 9,       /* new heap IDs, forwarding records              */
     CBT_STAGE_RESOLVE = 10,   /* neighbour pointers, bitfield clears           */
     CBT_STAGE_REDUCE = 11,    /* sum-reduction tree                            */
-    CBT_STAGE_FRAME = 12      /* the whole update                              */
+    CBT_STAGE_FRAME = 12,     /* the whole update                              */
+    CBT_STAGE_EXPORT = 13     /* cbt_export_triangles' kernel                  */
 };
 cbt_status cbt_time_stage(cbt_handle h, int32_t stage);
 cbt_status cbt_stage_time(cbt_handle h, int64_t* launches, double* total_ms);

@@ -24,10 +24,11 @@ EXPORTED = ["cbt_workspace_bytes", "cbt_init", "cbt_update", "cbt_update_with_de
             "cbt_query_decisions", "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count",
             "cbt_destroy", "cbt_status_string", "cbt_last_error", "cbt_time_stage", "cbt_stage_time",
             "cbt_set_schedule", "cbt_get_schedule", "cbt_stage_times", "cbt_batch_workspace_bytes", "cbt_batch_create",
-            "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy"]
+            "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
+            "cbt_export_triangles"]
 
 STAGES = {"enumerate": 1, "classify": 2, "vote": 3, "budget": 4, "chain": 5, "owners": 6, "offsets": 7,
-          "freelist": 8, "fill": 9, "resolve": 10, "reduce": 11, "frame": 12}
+          "freelist": 8, "fill": 9, "resolve": 10, "reduce": 11, "frame": 12, "export": 13}
 
 
 class CbtError(RuntimeError):
@@ -90,6 +91,9 @@ def load_library():
     lib.cbt_time_stage.argtypes = [vp, C.c_int32]
     lib.cbt_stage_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     lib.cbt_stage_times.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.cbt_update_converge.argtypes = [vp, C.POINTER(Camera), C.POINTER(LodParams), C.c_int32,
+                                        C.POINTER(C.c_int32), C.POINTER(FrameStats)]
+    lib.cbt_export_triangles.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.cbt_set_schedule.argtypes = [vp, C.c_int32, C.c_int32]
     lib.cbt_get_schedule.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.cbt_batch_workspace_bytes.argtypes = [vp, C.c_int32]
@@ -105,7 +109,8 @@ def load_library():
     for f in ("cbt_init", "cbt_update", "cbt_update_with_decisions", "cbt_query", "cbt_query_decisions",
               "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count", "cbt_destroy",
               "cbt_time_stage", "cbt_stage_time", "cbt_stage_times", "cbt_set_schedule", "cbt_get_schedule", "cbt_batch_create",
-              "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy"):
+              "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
+              "cbt_export_triangles"):
         getattr(lib, f).restype = C.c_int32
     _LIB = lib
     return lib
@@ -215,6 +220,31 @@ class Instance:
         st = FrameStats() if stats else None
         self._check(self.lib.cbt_update(self.h, C.byref(cam), C.byref(self._lodp), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
+
+    def update_converge(self, camera, max_passes: int = 64):
+        """Repeats the update with one camera until a pass changes nothing;
+        returns (passes, counters of the last pass)."""
+        if self.lod is None:
+            raise CbtError(-1, "no LOD parameters")
+        cam = make_camera(camera)
+        n = C.c_int32()
+        st = FrameStats()
+        self._check(self.lib.cbt_update_converge(self.h, C.byref(cam), C.byref(self._lodp), int(max_passes),
+                                                 C.byref(n), C.byref(st)))
+        return int(n.value), st.as_dict()
+
+    def export_triangles(self, out=None):
+        """World positions of every live bisector's vertices, in block order,
+        as a device tensor of shape (L, 3, 3)."""
+        torch = self._torch
+        n = C.c_int64()
+        if out is None:
+            st = self.lib.cbt_export_triangles(self.h, None, 0, C.byref(n))
+            if st not in (CBT_OK, -4):
+                self._check(st)
+            out = torch.empty((max(1, int(n.value)), 3, 3), dtype=torch.float32, device=self.device)
+        self._check(self.lib.cbt_export_triangles(self.h, C.c_void_p(out.data_ptr()), out.shape[0], C.byref(n)))
+        return out[:int(n.value)]
 
     def update_with_decisions(self, decisions, stats: bool = False):
         torch = self._torch

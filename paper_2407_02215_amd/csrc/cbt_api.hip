@@ -279,8 +279,8 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
 
     const Pool& P = h->P;
     hipStream_t s = h->stream;
-    // the flat-vertex region (48 bytes per block, cap >= H) stages the roots
-    uint32_t* staging = reinterpret_cast<uint32_t*>(P.vflat);
+    // the vertex-cache region (48 bytes per block, cap >= H) stages the roots
+    uint32_t* staging = reinterpret_cast<uint32_t*>(P.vworld);
     cbt_status rc = CBT_OK;
 #define INIT_TRY(expr, what)                      \
     do {                                          \
@@ -304,13 +304,12 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
     INIT_TRY(hipMemsetAsync(P.ctr, 0, sizeof(Counters), s), "clear counters");
     INIT_TRY(hipMemcpyAsync(staging, recs.data(), sizeof(uint32_t) * recs.size(), hipMemcpyHostToDevice, s), "upload roots");
     INIT_TRY(cbtk::launch_import_records(P, 0, (uint32_t)H, staging, s), "root records");
-    INIT_TRY(hipMemsetAsync(P.vflat, 0, sizeof(float4) * 3 * (size_t)P.cap, s), "clear vertex cache");
     INIT_TRY(hipMemsetAsync(P.vworld, 0, sizeof(float4) * 3 * (size_t)P.cap, s), "clear vertex cache");
     INIT_TRY(hipMemcpyAsync(P.bits, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice, s), "upload bits");
     INIT_TRY(hipMemcpyAsync(P.root, roots.data(), sizeof(float) * roots.size(), hipMemcpyHostToDevice, s), "upload root triangles");
     std::memset(&h->wk, 0, sizeof h->wk);   // flat world positions until LOD parameters arrive
     INIT_TRY(cbtk::launch_reduce(cbtk::single_launch(P, h->wk, nullptr), s), "sum reduction");
-    INIT_TRY(cbtk::launch_refresh(cbtk::single_launch(P, h->wk, nullptr), 1, s), "vertex cache");
+    INIT_TRY(cbtk::launch_refresh(cbtk::single_launch(P, h->wk, nullptr), s), "vertex cache");
     INIT_TRY(hipStreamSynchronize(s), "init synchronise");
 #undef INIT_TRY
     *out = h;
@@ -376,7 +375,7 @@ cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_para
     if (cbth::world_changed(K, h->wk)) {
         // new world-position parameters: recompute the cached world positions
         h->wk = K;
-        HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), 0, h->stream), "vertex cache");
+        HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), h->stream), "vertex cache");
     }
     HIP_TRY(h, cbtk::launch_frame(cbtk::single_launch(h->P, K, nullptr), h->stream, next_events(h)), "frame launch");
     return finish_frame(h, stats);
@@ -391,6 +390,42 @@ cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisio
     HIP_TRY(h, cbtk::launch_frame(cbtk::single_launch(h->P, h->wk, device_decisions), h->stream, next_events(h)),
             "frame launch");
     return finish_frame(h, stats);
+}
+
+cbt_status cbt_update_converge(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod, int32_t max_passes,
+                               int32_t* passes, cbt_frame_stats* last)
+{
+    if (!h || !passes) return fail(h, CBT_E_ARG, "NULL argument");
+    if (max_passes < 1) return fail(h, CBT_E_ARG, "max_passes %d < 1", max_passes);
+    *passes = 0;
+    cbt_frame_stats st;
+    for (int32_t p = 0; p < max_passes; ++p) {
+        cbt_status rc = cbt_update(h, camera, lod, &st);
+        if (rc) return rc;
+        *passes = p + 1;
+        if (st.allocations == 0 && st.frees == 0) break;
+    }
+    if (last) *last = st;
+    return CBT_OK;
+}
+
+cbt_status cbt_export_triangles(cbt_handle h, float* device_out, int64_t capacity, int64_t* count)
+{
+    if (!h || !count || capacity < 0 || (capacity > 0 && !device_out)) return fail(h, CBT_E_ARG, "invalid argument");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    const Pool& P = h->P;
+    h->last_frame_valid = 0;
+    HIP_TRY(h, cbtk::launch_enumerate(cbtk::single_launch(P, h->wk, nullptr), h->stream), "enumerate");
+    cbt_status st = read_counters(h);
+    if (st) return st;
+    const uint32_t L = h->hctr->L;
+    *count = L;
+    if (capacity < (int64_t)L) return fail(h, CBT_E_CAPACITY, "capacity %lld < %u live bisectors", (long long)capacity, L);
+    const cbtk::StageEvents* ev = h->timed_stage == CBT_STAGE_EXPORT ? next_events(h) : nullptr;
+    if (ev) HIP_TRY(h, hipEventRecord(ev->begin, h->stream), "event");
+    HIP_TRY(h, cbtk::launch_export_triangles(P, L, device_out, h->stream), "export triangles");
+    if (ev) HIP_TRY(h, hipEventRecord(ev->end, h->stream), "event");
+    return CBT_OK;
 }
 
 cbt_status cbt_set_schedule(cbt_handle h, int32_t rank_groups, int32_t reduce_levels)
@@ -416,7 +451,7 @@ cbt_status cbt_get_schedule(cbt_handle h, int32_t* rank_groups, int32_t* reduce_
 cbt_status cbt_time_stage(cbt_handle h, int32_t stage)
 {
     if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
-    if (stage < CBT_STAGE_NONE || stage > CBT_STAGE_FRAME) return fail(h, CBT_E_ARG, "unknown stage %d", stage);
+    if (stage < CBT_STAGE_NONE || stage > CBT_STAGE_EXPORT) return fail(h, CBT_E_ARG, "unknown stage %d", stage);
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
     h->timed_stage = stage;
     h->n_timed = 0;
@@ -599,7 +634,7 @@ cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twi
     const cbtk::Launch X = cbtk::single_launch(P, h->wk, nullptr);
     HIP_TRY(h, cbtk::launch_bits_from_ids(P, h->stream), "bitfield");
     HIP_TRY(h, cbtk::launch_reduce(X, h->stream), "sum reduction");
-    HIP_TRY(h, cbtk::launch_refresh(X, 1, h->stream), "vertex cache");
+    HIP_TRY(h, cbtk::launch_refresh(X, h->stream), "vertex cache");
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
     h->last_frame_valid = 0;
     return CBT_OK;

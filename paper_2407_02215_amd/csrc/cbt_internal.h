@@ -93,8 +93,7 @@ struct Pool {
                        //       merged member; on the smallest member of a
                        //       merge configuration first its other members,
                        //       then (parent, members)
-    float4* vflat;    // [3 cap] flat-domain vertices (xyz, w unused)
-    float4* vworld;    // [3 cap] their world positions; w of the first holds
+    float4* vworld;    // [3 cap] world positions of the three vertices; w of the first holds
                        //         the subdivision depth, of the second the
                        //         parity of the heap ID (as integers)
     uint32_t* cmd;     // [cap] command word, rewritten every frame
@@ -166,10 +165,13 @@ struct StageEvents {
 hipError_t launch_frame(const Launch& X, hipStream_t s, const StageEvents* ev);
 hipError_t launch_reduce(const Launch& X, hipStream_t s);
 hipError_t launch_enumerate(const Launch& X, hipStream_t s);
-// rebuild the vertex cache of every live block (flat != 0: decode the flat
-// vertices from the heap IDs first; otherwise recompute world positions
-// with the instance's K)
-hipError_t launch_refresh(const Launch& X, int flat, hipStream_t s);
+// rebuild the vertex cache of every live block: world positions (with the
+// instance's K) of the vertices decoded from its heap ID
+hipError_t launch_refresh(const Launch& X, hipStream_t s);
+
+// cached world positions of the L live bisectors in rank order (after an
+// enumeration) -> out9[9 L]
+hipError_t launch_export_triangles(const Pool& P, uint32_t L, float* out9, hipStream_t s);
 
 // the counters of every instance of a batch -> out[n_inst]
 hipError_t launch_gather_counters(const Launch& X, Counters* out, hipStream_t s);

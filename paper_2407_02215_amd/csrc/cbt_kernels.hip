@@ -38,11 +38,13 @@
 // writer per pointer field, the only atomics are order-free bitwise OR/AND
 // and counter additions.
 //
-// Vertex cache: every block keeps its bisector's flat-domain vertices (the
-// Alg. 2 decode) and their world positions.  Children are midpoints of the
-// parent's vertices and merged parents copy their children's vertices, so
-// the cache equals the decode bit for bit; the LOD test reads it instead of
-// decoding d levels and sampling the displacement table three times.
+// Vertex cache: every block keeps the world positions of its bisector's
+// vertices.  A split decodes the parent's flat-domain vertices from its heap
+// ID (Alg. 2, a few ALU operations per level), copies the parent's cached
+// world positions and evaluates only the new midpoints; merged parents copy
+// their children's.  The cache equals the world positions of the decode bit
+// for bit, and the LOD test reads it instead of decoding d levels and
+// sampling the displacement table three times.
 //
 // Floating point: IEEE binary32, no contraction (-ffp-contract=off),
 // correctly rounded division and square root.
@@ -474,16 +476,11 @@ __device__ __forceinline__ uint32_t lod_decide(const LodK& K, V3 p0, V3 p1, V3 p
     return kKeep;
 }
 
-// vertex-cache record of block s: flat vertices, world positions, depth and
-// heap-ID parity
-__device__ __forceinline__ void store_vertices(const Pool& P, uint32_t s, V3 a, V3 b, V3 c, V3 pa, V3 pb, V3 pc,
-                                               int depth, int parity)
+// vertex-cache record of block s: world positions of the three vertices,
+// the depth and the heap-ID parity
+__device__ __forceinline__ void store_world(const Pool& P, uint32_t s, V3 pa, V3 pb, V3 pc, int depth, int parity)
 {
-    float4* f = P.vflat + 3 * (size_t)s;
     float4* w = P.vworld + 3 * (size_t)s;
-    f[0] = st3(a, 0);
-    f[1] = st3(b, 0);
-    f[2] = st3(c, 0);
     w[0] = st3(pa, depth);
     w[1] = st3(pb, parity);
     w[2] = st3(pc, 0);
@@ -903,9 +900,11 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
     const uint32_t q2 = cnt > 2 ? P.freel[base + 2] : 0u, q3 = cnt > 3 ? P.freel[base + 3] : 0u;
     if (q0 >= P.cap || q1 >= P.cap || q2 >= P.cap || q3 >= P.cap) { raise_err(P, kErrAlloc); return; }
     const int d = depth_of_cmd(c);
-    const float4* fv = P.vflat + 3 * (size_t)s;
+    // flat vertices: the Alg. 2 decode of the heap ID (no memory beyond the
+    // ID and the root table); world positions: the cache
+    V3 v0, v1, v2;
+    decode(P, P.id[s], d, v0, v1, v2);
     const float4* wv = P.vworld + 3 * (size_t)s;
-    const V3 v0 = ld3(fv[0]), v1 = ld3(fv[1]), v2 = ld3(fv[2]);
     const V3 w0 = ld3(wv[0]), w1 = ld3(wv[1]), w2 = ld3(wv[2]);
     const V3 m = mid3(v0, v1);
     const V3 wm = world(K, m);
@@ -921,21 +920,21 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
     }
     // first child (v0, v2, m), or its children (v0, m, m0) and (m, v2, m0)
     if (!hp) {
-        store_vertices(P, r0q, v0, v2, m, w0, w2, wm, d + 1, 0);
+        store_world(P, r0q, w0, w2, wm, d + 1, 0);
     } else {
         const V3 m0 = mid3(v0, v2);
         const V3 wm0 = world(K, m0);
-        store_vertices(P, r0q, v0, m, m0, w0, wm, wm0, d + 2, 0);
-        store_vertices(P, r1q, m, v2, m0, wm, w2, wm0, d + 2, 1);
+        store_world(P, r0q, w0, wm, wm0, d + 2, 0);
+        store_world(P, r1q, wm, w2, wm0, d + 2, 1);
     }
     // second child (v2, v1, m), or its children (v2, m, m1) and (m, v1, m1)
     if (!hn) {
-        store_vertices(P, r2q, v2, v1, m, w2, w1, wm, d + 1, 1);
+        store_world(P, r2q, w2, w1, wm, d + 1, 1);
     } else {
         const V3 m1 = mid3(v2, v1);
         const V3 wm1 = world(K, m1);
-        store_vertices(P, r2q, v2, m, m1, w2, wm, wm1, d + 2, 0);
-        store_vertices(P, r3q, m, v1, m1, wm, w1, wm1, d + 2, 1);
+        store_world(P, r2q, w2, wm, wm1, d + 2, 0);
+        store_world(P, r3q, wm, w1, wm1, d + 2, 1);
     }
     P.link[s].w = (int)c;
     P.fwd[s] = make_uint4(r0q, r1q, r2q, r3q);
@@ -944,15 +943,9 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
 // parent of the sibling pair (c0 even, c1 odd): vertices (c0.v0, c1.v1, c0.v1)
 __device__ __forceinline__ void fill_parent(const Pool& P, uint32_t q, int32_t c0, int32_t c1, int depth, int parity)
 {
-    const float4* f0 = P.vflat + 3 * (size_t)c0;
-    const float4* f1 = P.vflat + 3 * (size_t)c1;
     const float4* w0 = P.vworld + 3 * (size_t)c0;
     const float4* w1 = P.vworld + 3 * (size_t)c1;
-    float4* fq = P.vflat + 3 * (size_t)q;
     float4* wq = P.vworld + 3 * (size_t)q;
-    fq[0] = f0[0];
-    fq[1] = f1[1];
-    fq[2] = f0[1];
     const float4 a = w0[0], b = w1[1], c = w0[1];
     wq[0] = make_float4(a.x, a.y, a.z, __int_as_float(depth));
     wq[1] = make_float4(b.x, b.y, b.z, __int_as_float(parity));
@@ -1248,10 +1241,10 @@ __global__ void __launch_bounds__(1024) k_reduce_top(Batch B, Inst one)
 // kernels: vertex-cache refresh, queries, snapshot and restore
 // ---------------------------------------------------------------------------
 
-// Rebuild the cache of every live block: flat vertices by the Alg. 2 decode
-// (when flat is set) and world positions from them.
+// Rebuild the cache of every live block: world positions of the Alg. 2
+// decode of its heap ID.
 template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one, int flat)
+__global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
 {
     Pool P;
     LodK K;
@@ -1266,17 +1259,11 @@ __global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one, int flat)
         int d = 0;
         if (valid_id(P, id)) {
             d = ilog2_64(id) - P.k;
-            if (flat) decode(P, id, d, a, b, c);
+            decode(P, id, d, a, b, c);
         } else {
             raise_err(P, kErrPointer);
         }
-        if (!flat) {
-            const float4* f = P.vflat + 3 * (size_t)s;
-            a = ld3(f[0]);
-            b = ld3(f[1]);
-            c = ld3(f[2]);
-        }
-        store_vertices(P, s, a, b, c, world(K, a), world(K, b), world(K, c), d, (int)(id & 1u));
+        store_world(P, s, world(K, a), world(K, b), world(K, c), d, (int)(id & 1u));
     }
 }
 
@@ -1307,18 +1294,20 @@ __global__ void k_gather_links(Pool P, uint32_t r0, uint32_t n, int32_t* out)
     out[3 * (size_t)i + 2] = l.z;
 }
 
-// flat-domain vertices from the vertex cache
+// flat-domain vertices: the Alg. 2 decode of the heap ID
 __global__ void k_gather_vertices(Pool P, uint32_t r0, uint32_t n, float* out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float4* f = P.vflat + 3 * (size_t)P.live[r0 + i];
+    const uint64_t id = P.id[P.live[r0 + i]];
+    V3 v[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (valid_id(P, id)) decode(P, id, ilog2_64(id) - P.k, v[0], v[1], v[2]);
+    else raise_err(P, kErrPointer);
     float* o = out + 9 * (size_t)i;
-    for (int v = 0; v < 3; ++v) {
-        const float4 x = f[v];
-        o[3 * v + 0] = x.x;
-        o[3 * v + 1] = x.y;
-        o[3 * v + 2] = x.z;
+    for (int j = 0; j < 3; ++j) {
+        o[3 * j + 0] = v[j].x;
+        o[3 * j + 1] = v[j].y;
+        o[3 * j + 2] = v[j].z;
     }
 }
 
@@ -1381,6 +1370,28 @@ __global__ void k_import_records(Pool P, uint32_t b0, uint32_t n, const uint32_t
     P.fwd[b0 + i] = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
 }
 
+// Triangle export: the cached world positions of every live bisector's
+// three vertices, in rank order, 9 floats per triangle.  Each workgroup
+// stages its 256 triangles in LDS and writes them as one contiguous run.
+__global__ void __launch_bounds__(kBlock) k_export_triangles(Pool P, uint32_t L, float* out)
+{
+    __shared__ float stage[kBlock * 9];
+    const uint32_t r0 = blockIdx.x * kBlock;
+    const uint32_t r = r0 + threadIdx.x;
+    if (r < L) {
+        const float4* w = P.vworld + 3 * (size_t)P.live[r];
+        const float4 a = w[0], b = w[1], c = w[2];
+        float* t = stage + 9 * threadIdx.x;
+        t[0] = a.x; t[1] = a.y; t[2] = a.z;
+        t[3] = b.x; t[4] = b.y; t[5] = b.z;
+        t[6] = c.x; t[7] = c.y; t[8] = c.z;
+    }
+    __syncthreads();
+    const uint32_t n = 9u * ((L - r0) < (uint32_t)kBlock ? (L - r0) : (uint32_t)kBlock);
+    float* o = out + 9 * (size_t)r0;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) o[i] = stage[i];
+}
+
 // counters of every instance of a batch, gathered into one array
 __global__ void k_gather_counters(Batch B, Counters* out)
 {
@@ -1417,7 +1428,7 @@ size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
         return o;
     };
     const size_t o_id = take(8 * cap), o_link = take(16 * cap), o_fwd = take(16 * cap);
-    const size_t o_flat = take(48 * cap), o_world = take(48 * cap), o_cmd = take(4 * cap);
+    const size_t o_world = take(48 * cap), o_cmd = take(4 * cap);
     const size_t o_bits = take(4 * W), o_tree = take(4 * TW), o_live = take(4 * cap);
     const size_t o_free = take(4 * cap), o_list = take(8 * cap), o_lpre = take(4 * cap), o_lcnt = take(4 * (size_t)kMaxRankGroups);
     const size_t o_part = take(sizeof(uint2) * kMaxRankGroups), o_ctr = take(sizeof(Counters));
@@ -1426,7 +1437,6 @@ size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
         P->id = reinterpret_cast<uint64_t*>(base + o_id);
         P->link = reinterpret_cast<int4*>(base + o_link);
         P->fwd = reinterpret_cast<uint4*>(base + o_fwd);
-        P->vflat = reinterpret_cast<float4*>(base + o_flat);
         P->vworld = reinterpret_cast<float4*>(base + o_world);
         P->cmd = reinterpret_cast<uint32_t*>(base + o_cmd);
         P->bits = reinterpret_cast<uint32_t*>(base + o_bits);
@@ -1541,12 +1551,18 @@ hipError_t launch_enumerate(const Launch& X, hipStream_t s)
     return X.batched ? enumerate_seq<true>(X, s) : enumerate_seq<false>(X, s);
 }
 
-hipError_t launch_refresh(const Launch& X, int flat, hipStream_t s)
+hipError_t launch_refresh(const Launch& X, hipStream_t s)
 {
     hipError_t e = launch_enumerate(X, s);
     if (e != hipSuccess) return e;
-    if (X.batched) hipLaunchKernelGGL(k_refresh<true>, dim3(X.grid_rank), dim3(kBlock), 0, s, X.B, X.one, flat);
-    else hipLaunchKernelGGL(k_refresh<false>, dim3(X.grid_rank), dim3(kBlock), 0, s, X.B, X.one, flat);
+    if (X.batched) hipLaunchKernelGGL(k_refresh<true>, dim3(X.grid_rank), dim3(kBlock), 0, s, X.B, X.one);
+    else hipLaunchKernelGGL(k_refresh<false>, dim3(X.grid_rank), dim3(kBlock), 0, s, X.B, X.one);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_triangles(const Pool& P, uint32_t L, float* out9, hipStream_t s)
+{
+    if (L) hipLaunchKernelGGL(k_export_triangles, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out9);
     return hipGetLastError();
 }
 

@@ -326,7 +326,7 @@ cbt_status launch_slot(cbt_server s, Slot& S)
         cbt_handle h = I.h;
         if (cbth::world_changed(K, h->wk)) {
             h->wk = K;
-            HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), 0, S.stream), "vertex cache");
+            HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), S.stream), "vertex cache");
         }
         S.h_inst[i].P = h->P;
         S.h_inst[i].K = K;

@@ -84,14 +84,14 @@ def test_workspace_follows_paper_memory_model():
     7 MiB.  This library keeps the same index (8), pointers (12, padded to
     16 with the bisector's fate this frame), command (4) and four slots
     (16), the same 8 bytes of rank and free lists, a 12-byte work list and a
-    96-byte vertex cache, and stores the bitfield plus a tree that stops at
-    the word level instead of the 2^(D+1) heap."""
+    48-byte cache of the vertices' world positions, and stores the bitfield
+    plus a tree that stops at the word level instead of the 2^(D+1) heap."""
     g = read_golden("we4_memory.txt")
     D = int(g["D"])
     paper = (1 << D) * (3 * 4 + 8 + 4 + 4 * 4) + (1 << D) * 8 + (1 << (D + 1)) * 4
     assert paper == int(g["total_mib"]) << 20
     ours = cbt.workspace_bytes(60, D)
-    per_block = (8 + 16 + 4 + 16) + 8 + 12 + 96
+    per_block = (8 + 16 + 4 + 16) + 8 + 12 + 48
     cbt_bytes = (1 << D) // 8 + (1 << (D - 4)) * 4
     assert ours >= (1 << D) * per_block + cbt_bytes
     assert ours <= (1 << D) * per_block + cbt_bytes + 64 * 1024

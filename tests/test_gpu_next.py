@@ -1,0 +1,80 @@
+"""Rows after the per-frame update: triangle export (world positions of
+every leaf, watertight) and the multi-pass convergence mode, each checked
+element by element against the CPU reference."""
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+from oracle import Oracle
+from paper_2407_02215_amd import cbt
+from paper_2407_02215_amd import inputs as I
+from tests.gpu_checks import assert_same_state, assert_same_tree, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _reference_triangles(orc):
+    """World positions of the oracle's decoded vertices, live blocks in
+    ascending order."""
+    ids = orc.pool()[0]
+    live = np.nonzero(ids)[0]
+    flat = orc.vertices()[live].reshape(-1, 3)
+    world = np.stack([orc.world_position(v) for v in flat])
+    return world.reshape(-1, 3, 3)
+
+
+@pytest.mark.parametrize("name,frames", [("cube", 8), ("planet", 24)])
+def test_export_triangles_match_reference(name, frames):
+    w = I.workload(name, frames=256 if name == "planet" else None, table_res=64 if name == "planet" else None)
+    inst = cbt.Instance(w.mesh, w.depth, w.lod)
+    orc = Oracle(w.mesh, w.depth, w.lod)
+    for cam in w.cameras[:frames]:
+        inst.update(cam)
+        orc.frame(camera=cam)
+    got = inst.export_triangles().cpu().numpy()
+    ref = _reference_triangles(orc)
+    log(f"[export] {name}: {got.shape[0]} triangles")
+    assert got.shape == ref.shape
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    # the export follows the state it was taken from: a frame later it changes
+    inst.update(w.cameras[0])
+    assert inst.export_triangles().shape[0] == inst.live_count()
+    inst.close()
+
+
+def test_export_capacity_error():
+    w = I.workload("cube")
+    inst = cbt.Instance(w.mesh, w.depth, w.lod)
+    out = torch.empty((4, 3, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(cbt.CbtError) as e:
+        inst.export_triangles(out)
+    assert e.value.status == -4
+    inst.close()
+
+
+@pytest.mark.parametrize("name,cam_index,depth", [("cube", 0, 20), ("planet", 20, 20)])
+def test_converge_matches_reference(name, cam_index, depth):
+    """From the base mesh to the fixpoint for one camera (17 passes for both
+    cases; a nearly full pool converges much more slowly, since each pass
+    accepts only the splits whose 3d+4 reservations fit the free blocks)."""
+    w = I.workload(name, frames=256 if name == "planet" else None, table_res=64 if name == "planet" else None)
+    cam = w.cameras[cam_index]
+    inst = cbt.Instance(w.mesh, depth, w.lod)
+    orc = Oracle(w.mesh, depth, w.lod)
+    passes, last = inst.update_converge(cam, max_passes=64)
+    ref_passes = 0
+    for _ in range(64):
+        st = orc.frame(camera=cam)
+        ref_passes += 1
+        if st.allocations == 0 and st.frees == 0:
+            break
+    log(f"[converge] {name}: {passes} passes, live {inst.live_count()}")
+    assert passes == ref_passes
+    assert last["allocations"] == 0 and last["frees"] == 0
+    assert passes > 2
+    assert_same_state(inst, orc, f"{name} converged")
+    assert_same_tree(inst, orc, f"{name} converged")
+    # a fixpoint: one more pass changes nothing
+    again = inst.update(cam, stats=True)
+    assert again["allocations"] == 0 and again["frees"] == 0
+    inst.close()
