@@ -37,6 +37,7 @@
 enum { DEC_KEEP = 0, DEC_SPLIT = 1, DEC_MERGE = 2 };
 enum { MARK_B = 1, MARK_N = 2, MARK_P = 4 };   /* split marks: base, Next, Prev edge */
 enum { MODE_FLAT = 0, MODE_SPHERE = 1, MODE_HEIGHTFIELD = 2 };
+enum { CRIT_EDGE = 0, CRIT_AREA = 1 };   /* projected base-edge length / triangle area */
 
 static char g_err[1024];
 
@@ -114,6 +115,7 @@ struct orc_state {
     int32_t *twin, *next, *prev;
     uint32_t* heap;           /* 2^(D+1)                                 */
     int32_t mode;
+    int32_t criterion;        /* CRIT_EDGE or CRIT_AREA                  */
     float split_px, merge_px, amp;
     float* table;
     int32_t res;
@@ -281,6 +283,13 @@ int32_t orc_set_lod(orc_state* s, int32_t mode, float split_px, float merge_px,
     return 0;
 }
 
+int32_t orc_set_criterion(orc_state* s, int32_t criterion)
+{
+    if (criterion != CRIT_EDGE && criterion != CRIT_AREA) return fail("unknown size criterion %d", criterion);
+    s->criterion = criterion;
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* bisector vertices (Eq. 1, Alg. 2)                                         */
 /* ------------------------------------------------------------------------ */
@@ -425,8 +434,14 @@ static void make_consts(const orc_state* s, const float* camera, lod_consts* K)
         K->fwd[i] = (float)fw[i];
     }
     K->f2 = (float)(focal * focal);
-    K->t2s = (float)((double)s->split_px * (double)s->split_px);
-    K->t2m = (float)((double)s->merge_px * (double)s->merge_px);
+    if (s->criterion == CRIT_AREA) {
+        /* thresholds are areas in pixels^2; the test compares twice the area */
+        K->t2s = (float)(2.0 * (double)s->split_px);
+        K->t2m = (float)(2.0 * (double)s->merge_px);
+    } else {
+        K->t2s = (float)((double)s->split_px * (double)s->split_px);
+        K->t2m = (float)((double)s->merge_px * (double)s->merge_px);
+    }
     K->tx = (float)(th * width / height);
     K->ty = (float)th;
     K->znear = (float)znear;
@@ -470,6 +485,30 @@ static int classify(const orc_state* s, const lod_consts* K, const float* v,
     }
     *oA = *oBs = *oBm = 0.0f;
     if (out_near | out_left | out_right | out_bottom | out_top) return DEC_MERGE;
+    if (s->criterion == CRIT_AREA) {
+        /* The paper's literal target (Section 3.3 kernel 4, Section 4.1): the
+         * projected area of the triangle in pixels^2.  With screen
+         * coordinates f x_i / z_i, f y_i / z_i, twice the area is
+         * f^2 |N| / (z0^2 z1 z2), N = (x1 z0 - x0 z1)(y2 z0 - y0 z2)
+         * - (x2 z0 - x0 z2)(y1 z0 - y0 z1), compared without a division.
+         * A vertex behind the near plane makes the area unbounded: split. */
+        if (vz[0] < K->znear || vz[1] < K->znear || vz[2] < K->znear) return DEC_SPLIT;
+        float ax = vx[1] * vz[0] - vx[0] * vz[1];
+        float ay = vy[1] * vz[0] - vy[0] * vz[1];
+        float bx = vx[2] * vz[0] - vx[0] * vz[2];
+        float by = vy[2] * vz[0] - vy[0] * vz[2];
+        float N = ax * by - bx * ay;
+        float A = K->f2 * fabsf(N);
+        float zq = (vz[0] * vz[0]) * (vz[1] * vz[2]);
+        float Bs = K->t2s * zq;
+        float Bm = K->t2m * zq;
+        *oA = A;
+        *oBs = Bs;
+        *oBm = Bm;
+        if (A > Bs) return DEC_SPLIT;
+        if (A < Bm) return DEC_MERGE;
+        return DEC_KEEP;
+    }
     if (vz[0] < K->znear || vz[1] < K->znear) return DEC_SPLIT;
     float ex = vx[1] * vz[0] - vx[0] * vz[1];
     float ey = vy[1] * vz[0] - vy[0] * vz[1];

@@ -51,6 +51,9 @@ orc_state* orc_create(int32_t H, const int32_t* twin, const int32_t* next,
 void    orc_destroy(orc_state* s);
 int32_t orc_set_lod(orc_state* s, int32_t mode, float split_px, float merge_px,
                     const float* table, int32_t res, float amplitude);
+/* size criterion: 0 projected base-edge length (thresholds in pixels, the
+ * default), 1 projected triangle area (thresholds in pixels^2) */
+int32_t orc_set_criterion(orc_state* s, int32_t criterion);
 /* camera: float[13] = pos[3], fwd[3], up[3], fovy, width, height, znear.
  * decisions: NULL, or one code per slot (0 keep, 1 split, 2 merge) that
  * replaces the LOD test. */

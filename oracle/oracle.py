@@ -64,6 +64,8 @@ def load():
     lib.orc_destroy.argtypes = [C.c_void_p]
     lib.orc_set_lod.argtypes = [C.c_void_p, C.c_int32, C.c_float, C.c_float, f32p, C.c_int32, C.c_float]
     lib.orc_set_lod.restype = C.c_int32
+    lib.orc_set_criterion.argtypes = [C.c_void_p, C.c_int32]
+    lib.orc_set_criterion.restype = C.c_int32
     lib.orc_frame.argtypes = [C.c_void_p, f32p, u8p, C.POINTER(_Stats)]
     lib.orc_frame.restype = C.c_int32
     lib.orc_depth.argtypes = [C.c_void_p]
@@ -147,6 +149,8 @@ class Oracle:
         rc = self._lib.orc_set_lod(self._h, int(lod.mode), float(lod.split_px), float(lod.merge_px),
                                    None if t is None else _p(t, C.c_float), lod.table_res, float(lod.amplitude))
         if rc:
+            raise _err(self._lib)
+        if self._lib.orc_set_criterion(self._h, int(getattr(lod, "criterion", 0))):
             raise _err(self._lib)
 
     def frame(self, camera=None, decisions=None) -> Stats:

@@ -27,6 +27,10 @@ MODE_HEIGHTFIELD = 2  # p = v + (0, 0, amp * grid(v.x, v.y))
 
 DEC_KEEP, DEC_SPLIT, DEC_MERGE = 0, 1, 2
 
+# size criteria of the screen-space test: projected base-edge length
+# (thresholds in pixels) or projected triangle area (thresholds in pixels^2)
+CRIT_EDGE, CRIT_AREA = 0, 1
+
 
 @dataclasses.dataclass
 class HalfedgeMesh:
@@ -372,6 +376,7 @@ class LodParams:
     merge_px: float
     table: np.ndarray | None = None  # float32, cube map (6,res,res) or grid (res,res)
     amplitude: float = 0.0
+    criterion: int = CRIT_EDGE
 
     @property
     def table_res(self) -> int:

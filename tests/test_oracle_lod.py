@@ -179,3 +179,89 @@ def test_heightfield_bilinear_reproduces_linear_table():
         p = o.world_position(v)
         assert p[0] == v[0] and p[1] == v[1]
         assert abs(p[2] - (0.25 + amp * h)) < 2e-6
+
+
+def _area_decide64(p, K, split_a, merge_a, tanx, tany, znear, f):
+    """Decision from the float64 shoelace area of the pinhole-projected
+    triangle (explicit division by depth)."""
+    q = p - K[0:3].astype(np.float64)
+    x = q @ K[3:6].astype(np.float64)
+    y = q @ K[6:9].astype(np.float64)
+    z = q @ K[9:12].astype(np.float64)
+    for cond in (z < znear, x > tanx * z, x < -tanx * z, y > tany * z, y < -tany * z):
+        if cond.all():
+            return I.DEC_MERGE, None
+    if (z < znear).any():
+        return I.DEC_SPLIT, None
+    sx, sy = f * x / z, f * y / z
+    area = 0.5 * abs((sx[1] - sx[0]) * (sy[2] - sy[0]) - (sx[2] - sx[0]) * (sy[1] - sy[0]))
+    margin = min(abs(area - split_a) / split_a, abs(area - merge_a) / merge_a)
+    if area > split_a:
+        return I.DEC_SPLIT, margin
+    if area < merge_a:
+        return I.DEC_MERGE, margin
+    return I.DEC_KEEP, margin
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_area_decisions_match_float64_projection(seed):
+    """The projected-area criterion (the paper's screen-space area target):
+    the division-free binary32 test agrees with the area of the projected
+    triangle computed in float64 outside a 1e-4 relative band."""
+    m = _flat_mesh_in_front(seed)
+    o = Oracle(m, 12, I.LodParams(I.MODE_FLAT, 400.0, 100.0, criterion=I.CRIT_AREA))
+    for _ in range(4):
+        o.frame(decisions=np.ones(o.cap, np.uint8))
+    cam = _cam(70.0, 640, 480, 0.05, pos=(0.1, -0.2, -0.5), fwd=(0.1, 0.05, 1.0), up=(0.0, 1.0, 0.1))
+    K = o.frame_constants(cam)
+    ids = o.pool()[0]
+    verts = o.vertices()
+    live = np.nonzero(ids)[0]
+    th = math.tan(0.5 * cam.fovy)
+    f = 0.5 * cam.height / th
+    areas = []
+    for s in live:
+        v = verts[s].reshape(3, 3).astype(np.float64)
+        q = v - K[0:3].astype(np.float64)
+        x, y, z = q @ K[3:6].astype(np.float64), q @ K[6:9].astype(np.float64), q @ K[9:12].astype(np.float64)
+        if (z > cam.znear).all():
+            sx, sy = f * x / z, f * y / z
+            areas.append(0.5 * abs((sx[1] - sx[0]) * (sy[2] - sy[0]) - (sx[2] - sx[0]) * (sy[1] - sy[0])))
+    split_a, merge_a = float(np.quantile(areas, 0.7)), float(np.quantile(areas, 0.3))
+    o.set_lod(I.LodParams(I.MODE_FLAT, split_a, merge_a, criterion=I.CRIT_AREA))
+    K2 = o.frame_constants(cam)
+    assert K2[13] == np.float32(2.0 * split_a) and K2[14] == np.float32(2.0 * merge_a)
+    o.frame(camera=cam)
+    dec = o.decisions()[0]
+    split_a, merge_a = float(np.float32(split_a)), float(np.float32(merge_a))
+    n_checked = 0
+    kinds = set()
+    for s in live:
+        v = verts[s].reshape(3, 3).astype(np.float64)
+        want, margin = _area_decide64(v, K, split_a, merge_a, th * cam.width / cam.height, th, cam.znear, f)
+        if margin is not None and margin < 1e-4:
+            continue
+        assert dec[s] == want, (s, dec[s], want)
+        kinds.add(want)
+        n_checked += 1
+    assert n_checked > 0.9 * live.size
+    assert kinds == {I.DEC_SPLIT, I.DEC_MERGE, I.DEC_KEEP}
+
+
+def test_area_criterion_closed_form():
+    """A triangle facing the camera at depth z with legs a, b has projected
+    area f^2 a b / (2 z^2); each of its three root bisectors (fanned around
+    the face centroid, Alg. 1) covers a third of it.  Just below and above a
+    threshold set from that closed form the root splits or keeps."""
+    pos = np.array([[0.0, 0.0, 2.0], [0.3, 0.0, 2.0], [0.0, 0.2, 2.0]], np.float32)
+    m = I.halfedge_from_faces([[0, 1, 2]], pos)
+    cam = _cam(60.0, 800, 600, 0.05, pos=(0.05, 0.05, 0.0), fwd=(0, 0, 1), up=(0, 1, 0))
+    f = 0.5 * 600 / math.tan(math.radians(30.0))
+    area = f * f * 0.3 * 0.2 / (2 * 2.0 * 2.0) / 3.0
+    for thr, want in ((area * 0.999, I.DEC_SPLIT), (area * 1.001, I.DEC_KEEP)):
+        o = Oracle(m, 4, I.LodParams(I.MODE_FLAT, thr, thr / 4, criterion=I.CRIT_AREA))
+        o.frame(camera=cam)
+        dec, A, Bs, _ = o.decisions()
+        # root 0 sits in block 0 (roots never merge; a split is not overridden)
+        assert dec[0] == want
+        assert abs(float(A[0]) / (2.0 * area * float(Bs[0]) / (2.0 * np.float32(thr))) - 1.0) < 1e-5
