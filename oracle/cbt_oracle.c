@@ -116,6 +116,8 @@ struct orc_state {
     uint32_t* heap;           /* 2^(D+1)                                 */
     int32_t mode;
     int32_t criterion;        /* CRIT_EDGE or CRIT_AREA                  */
+    int32_t prec;             /* 32 or 64: precision of vertices and LOD  */
+    double* root64;           /* H * 9, binary64 variant                 */
     float split_px, merge_px, amp;
     float* table;
     int32_t res;
@@ -247,6 +249,7 @@ orc_state* orc_create(int32_t H, const int32_t* twin, const int32_t* next,
     }
     orc_cbt_reduce(s->heap, D);
     s->mode = MODE_FLAT;
+    s->prec = 32;
     s->split_px = 8.0f;
     s->merge_px = 4.0f;
     return s;
@@ -258,7 +261,7 @@ void orc_destroy(orc_state* s)
     free(s->mtwin); free(s->mnext); free(s->mprev); free(s->mvert); free(s->mpos);
     free(s->root); free(s->id); free(s->twin); free(s->next); free(s->prev);
     free(s->heap); free(s->dec); free(s->mA); free(s->mBs); free(s->mBm);
-    free(s->table);
+    free(s->table); free(s->root64);
     free(s);
 }
 
@@ -526,6 +529,253 @@ static int classify(const orc_state* s, const lod_consts* K, const float* v,
 }
 
 /* ------------------------------------------------------------------------ */
+/* binary64 variant: the paper evaluates its planets' vertex positions in    */
+/* double precision (Section 4.2).  The same steps as above -- Alg. 1 roots, */
+/* the Eq. 1 / Alg. 2 decode, world position, frame constants (no rounding  */
+/* to binary32) and the size test -- in double.                              */
+/* ------------------------------------------------------------------------ */
+
+static void compute_root_triangle64(const orc_state* s, int32_t h, double* out)
+{
+    int32_t nx = s->mnext[h];
+    const float* a = s->mpos + 3 * s->mvert[h];
+    const float* b = s->mpos + 3 * s->mvert[nx];
+    int32_t hmin = h;
+    for (int32_t g = s->mnext[h]; g != h; g = s->mnext[g])
+        if (g < hmin) hmin = g;
+    double sum[3];
+    for (int c = 0; c < 3; ++c) sum[c] = s->mpos[3 * s->mvert[hmin] + c];
+    int n = 1;
+    for (int32_t g = s->mnext[hmin]; g != hmin; g = s->mnext[g]) {
+        for (int c = 0; c < 3; ++c) sum[c] = sum[c] + (double)s->mpos[3 * s->mvert[g] + c];
+        n++;
+    }
+    for (int c = 0; c < 3; ++c) {
+        out[c] = a[c];
+        out[3 + c] = b[c];
+        out[6 + c] = sum[c] / (double)n;
+    }
+}
+
+static void decode_vertices64(const orc_state* s, uint64_t id, double* v)
+{
+    int d = depth_of(s, id);
+    int64_t h = (int64_t)(id >> d) - ((int64_t)1 << s->k);
+    double v0[3], v1[3], v2[3];
+    for (int c = 0; c < 3; ++c) {
+        v0[c] = s->root64[9 * h + c];
+        v1[c] = s->root64[9 * h + 3 + c];
+        v2[c] = s->root64[9 * h + 6 + c];
+    }
+    for (int i = d - 1; i >= 0; --i) {
+        int b = (int)((id >> i) & 1u);
+        double m[3];
+        for (int c = 0; c < 3; ++c) m[c] = (v0[c] + v1[c]) * 0.5;
+        if (b == 0) {
+            for (int c = 0; c < 3; ++c) { v1[c] = v2[c]; v2[c] = m[c]; }
+        } else {
+            for (int c = 0; c < 3; ++c) { v0[c] = v2[c]; v2[c] = m[c]; }
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        v[c] = v0[c];
+        v[3 + c] = v1[c];
+        v[6 + c] = v2[c];
+    }
+}
+
+static double bilinear64(const float* T, int32_t res, double s, double t)
+{
+    double fs = floor(s), ft = floor(t);
+    double lim = (double)(res - 2);
+    if (fs < 0.0) fs = 0.0;
+    if (fs > lim) fs = lim;
+    if (ft < 0.0) ft = 0.0;
+    if (ft > lim) ft = lim;
+    int32_t i0 = (int32_t)fs, j0 = (int32_t)ft;
+    double fx = s - fs, fy = t - ft;
+    double a = T[(int64_t)j0 * res + i0];
+    double b = T[(int64_t)j0 * res + i0 + 1];
+    double c = T[(int64_t)(j0 + 1) * res + i0];
+    double e = T[(int64_t)(j0 + 1) * res + i0 + 1];
+    double top = a + fx * (b - a);
+    double bot = c + fx * (e - c);
+    return top + fy * (bot - top);
+}
+
+static double sample_cubemap64(const orc_state* s, double x, double y, double z)
+{
+    double ax = fabs(x), ay = fabs(y), az = fabs(z);
+    int f;
+    double u, v;
+    if (ax >= ay && ax >= az) {
+        f = x >= 0.0 ? 0 : 1;
+        u = y / ax;
+        v = z / ax;
+    } else if (ay >= az) {
+        f = y >= 0.0 ? 2 : 3;
+        u = x / ay;
+        v = z / ay;
+    } else {
+        f = z >= 0.0 ? 4 : 5;
+        u = x / az;
+        v = y / az;
+    }
+    double hr = 0.5 * (double)(s->res - 1);
+    return bilinear64(s->table + (int64_t)f * s->res * s->res, s->res, (u + 1.0) * hr, (v + 1.0) * hr);
+}
+
+static void world_position64(const orc_state* s, const double* v, double* p)
+{
+    if (s->mode == MODE_SPHERE) {
+        double len = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+        double n0 = v[0] / len, n1 = v[1] / len, n2 = v[2] / len;
+        double h = sample_cubemap64(s, n0, n1, n2);
+        double sc = 1.0 + (double)s->amp * h;
+        p[0] = n0 * sc;
+        p[1] = n1 * sc;
+        p[2] = n2 * sc;
+    } else if (s->mode == MODE_HEIGHTFIELD) {
+        double r1 = (double)(s->res - 1);
+        double h = bilinear64(s->table, s->res, v[0] * r1, v[1] * r1);
+        p[0] = v[0];
+        p[1] = v[1];
+        p[2] = v[2] + (double)s->amp * h;
+    } else {
+        p[0] = v[0];
+        p[1] = v[1];
+        p[2] = v[2];
+    }
+}
+
+typedef struct {
+    double cam[3], right[3], up[3], fwd[3];
+    double f2, t2s, t2m, tx, ty, znear;
+} lod_consts64;
+
+static void make_consts64(const orc_state* s, const float* camera, lod_consts64* K)
+{
+    double f[3] = {camera[3], camera[4], camera[5]};
+    double u[3] = {camera[6], camera[7], camera[8]};
+    double fovy = camera[9], width = camera[10], height = camera[11];
+    double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    double fw[3] = {f[0] / fl, f[1] / fl, f[2] / fl};
+    double r[3] = {fw[1] * u[2] - fw[2] * u[1], fw[2] * u[0] - fw[0] * u[2], fw[0] * u[1] - fw[1] * u[0]};
+    double rl = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    r[0] /= rl;
+    r[1] /= rl;
+    r[2] /= rl;
+    double up[3] = {r[1] * fw[2] - r[2] * fw[1], r[2] * fw[0] - r[0] * fw[2], r[0] * fw[1] - r[1] * fw[0]};
+    double th = tan(0.5 * fovy);
+    double focal = 0.5 * height / th;
+    for (int i = 0; i < 3; ++i) {
+        K->cam[i] = camera[i];
+        K->right[i] = r[i];
+        K->up[i] = up[i];
+        K->fwd[i] = fw[i];
+    }
+    K->f2 = focal * focal;
+    if (s->criterion == CRIT_AREA) {
+        K->t2s = 2.0 * (double)s->split_px;
+        K->t2m = 2.0 * (double)s->merge_px;
+    } else {
+        K->t2s = (double)s->split_px * (double)s->split_px;
+        K->t2m = (double)s->merge_px * (double)s->merge_px;
+    }
+    K->tx = th * width / height;
+    K->ty = th;
+    K->znear = camera[12];
+}
+
+static int classify64(const orc_state* s, const lod_consts64* K, const double* v, float* oA, float* oBs,
+                      float* oBm)
+{
+    double vx[3], vy[3], vz[3];
+    for (int i = 0; i < 3; ++i) {
+        double p[3];
+        world_position64(s, v + 3 * i, p);
+        double q0 = p[0] - K->cam[0], q1 = p[1] - K->cam[1], q2 = p[2] - K->cam[2];
+        vx[i] = (q0 * K->right[0] + q1 * K->right[1]) + q2 * K->right[2];
+        vy[i] = (q0 * K->up[0] + q1 * K->up[1]) + q2 * K->up[2];
+        vz[i] = (q0 * K->fwd[0] + q1 * K->fwd[1]) + q2 * K->fwd[2];
+    }
+    int out_near = 1, out_left = 1, out_right = 1, out_bottom = 1, out_top = 1;
+    for (int i = 0; i < 3; ++i) {
+        double zx = K->tx * vz[i], zy = K->ty * vz[i];
+        out_near &= vz[i] < K->znear;
+        out_right &= vx[i] > zx;
+        out_left &= vx[i] < -zx;
+        out_top &= vy[i] > zy;
+        out_bottom &= vy[i] < -zy;
+    }
+    *oA = *oBs = *oBm = 0.0f;
+    if (out_near | out_left | out_right | out_bottom | out_top) return DEC_MERGE;
+    double A, Bs, Bm;
+    if (s->criterion == CRIT_AREA) {
+        if (vz[0] < K->znear || vz[1] < K->znear || vz[2] < K->znear) return DEC_SPLIT;
+        double ax = vx[1] * vz[0] - vx[0] * vz[1];
+        double ay = vy[1] * vz[0] - vy[0] * vz[1];
+        double bx = vx[2] * vz[0] - vx[0] * vz[2];
+        double by = vy[2] * vz[0] - vy[0] * vz[2];
+        double N = ax * by - bx * ay;
+        A = K->f2 * fabs(N);
+        double zq = (vz[0] * vz[0]) * (vz[1] * vz[2]);
+        Bs = K->t2s * zq;
+        Bm = K->t2m * zq;
+    } else {
+        if (vz[0] < K->znear || vz[1] < K->znear) return DEC_SPLIT;
+        double ex = vx[1] * vz[0] - vx[0] * vz[1];
+        double ey = vy[1] * vz[0] - vy[0] * vz[1];
+        A = K->f2 * (ex * ex + ey * ey);
+        double zz = vz[0] * vz[1];
+        double z4 = zz * zz;
+        Bs = K->t2s * z4;
+        Bm = K->t2m * z4;
+    }
+    *oA = (float)A;
+    *oBs = (float)Bs;
+    *oBm = (float)Bm;
+    if (A > Bs) return DEC_SPLIT;
+    if (A < Bm) return DEC_MERGE;
+    return DEC_KEEP;
+}
+
+int32_t orc_set_precision(orc_state* s, int32_t bits)
+{
+    if (bits != 32 && bits != 64) return fail("precision must be 32 or 64 bits (got %d)", bits);
+    if (bits == 64 && !s->root64) {
+        s->root64 = (double*)malloc(sizeof(double) * 9 * s->H);
+        if (!s->root64) return fail("out of memory");
+        for (int32_t h = 0; h < s->H; ++h) compute_root_triangle64(s, h, s->root64 + 9 * h);
+    }
+    s->prec = bits;
+    return 0;
+}
+
+void orc_world_position64(const orc_state* s, const double* v, double* p) { world_position64(s, v, p); }
+
+int32_t orc_decode64(const orc_state* s, uint64_t id, double* out9)
+{
+    if (!s->root64) return fail("binary64 decode needs orc_set_precision(64)");
+    int d = depth_of(s, id);
+    if (d < 0 || d > 63 - s->k) return fail("ID %llu is not a bisector", (unsigned long long)id);
+    int64_t h = (int64_t)(id >> d) - ((int64_t)1 << s->k);
+    if (h < 0 || h >= s->H) return fail("ID %llu has no root halfedge", (unsigned long long)id);
+    decode_vertices64(s, id, out9);
+    return 0;
+}
+
+int32_t orc_get_vertices64(const orc_state* s, double* out)
+{
+    if (!s->root64) return fail("binary64 vertices need orc_set_precision(64)");
+    for (int64_t i = 0; i < s->cap; ++i) {
+        if (s->id[i]) decode_vertices64(s, s->id[i], out + 9 * i);
+        else memset(out + 9 * i, 0, sizeof(double) * 9);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* literal triangulation graph used for Alg. 3-6 and Table 1                 */
 /* ------------------------------------------------------------------------ */
 
@@ -788,7 +1038,13 @@ int32_t orc_frame(orc_state* s, const float* camera, const uint8_t* decisions, o
 
     /* (4) GenerateCommands: decision of every live bisector */
     lod_consts K;
-    if (camera) make_consts(s, camera, &K);
+    lod_consts64 K64;
+    memset(&K, 0, sizeof K);
+    memset(&K64, 0, sizeof K64);
+    if (camera) {
+        make_consts(s, camera, &K);
+        if (s->prec == 64) make_consts64(s, camera, &K64);
+    }
     for (int64_t r = 0; r < L; ++r) {
         int32_t b = live[r];
         int d = depth_of(s, s->id[b]);
@@ -796,6 +1052,11 @@ int32_t orc_frame(orc_state* s, const float* camera, const uint8_t* decisions, o
         if (decisions) {
             dc = decisions[b];
             if (dc > DEC_MERGE) { rc = fail("injected decision %d out of range", dc); goto done; }
+        } else if (s->prec == 64) {
+            if (!camera) { rc = fail("frame needs a camera or decisions"); goto done; }
+            double v[9];
+            decode_vertices64(s, s->id[b], v);
+            dc = classify64(s, &K64, v, &s->mA[b], &s->mBs[b], &s->mBm[b]);
         } else {
             if (!camera) { rc = fail("frame needs a camera or decisions"); goto done; }
             float v[9];

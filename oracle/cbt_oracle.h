@@ -54,6 +54,13 @@ int32_t orc_set_lod(orc_state* s, int32_t mode, float split_px, float merge_px,
 /* size criterion: 0 projected base-edge length (thresholds in pixels, the
  * default), 1 projected triangle area (thresholds in pixels^2) */
 int32_t orc_set_criterion(orc_state* s, int32_t criterion);
+/* precision of root triangles, decode, world position and the size test:
+ * 32 (binary32, the default) or 64 (binary64) */
+int32_t orc_set_precision(orc_state* s, int32_t bits);
+void    orc_world_position64(const orc_state* s, const double* v, double* p);
+int32_t orc_decode64(const orc_state* s, uint64_t id, double* out9);
+/* binary64 decode of every live block (9 doubles per block, 0 when free) */
+int32_t orc_get_vertices64(const orc_state* s, double* out);
 /* camera: float[13] = pos[3], fwd[3], up[3], fovy, width, height, znear.
  * decisions: NULL, or one code per slot (0 keep, 1 split, 2 merge) that
  * replaces the LOD test. */

@@ -66,6 +66,14 @@ def load():
     lib.orc_set_lod.restype = C.c_int32
     lib.orc_set_criterion.argtypes = [C.c_void_p, C.c_int32]
     lib.orc_set_criterion.restype = C.c_int32
+    f64p = C.POINTER(C.c_double)
+    lib.orc_set_precision.argtypes = [C.c_void_p, C.c_int32]
+    lib.orc_set_precision.restype = C.c_int32
+    lib.orc_world_position64.argtypes = [C.c_void_p, f64p, f64p]
+    lib.orc_get_vertices64.argtypes = [C.c_void_p, f64p]
+    lib.orc_get_vertices64.restype = C.c_int32
+    lib.orc_decode64.argtypes = [C.c_void_p, C.c_uint64, f64p]
+    lib.orc_decode64.restype = C.c_int32
     lib.orc_frame.argtypes = [C.c_void_p, f32p, u8p, C.POINTER(_Stats)]
     lib.orc_frame.restype = C.c_int32
     lib.orc_depth.argtypes = [C.c_void_p]
@@ -121,7 +129,7 @@ def zero_to_bit(heap: np.ndarray, D: int, i: int) -> int:
 class Oracle:
     """One bisection-update instance on the CPU."""
 
-    def __init__(self, mesh, depth: int, lod=None):
+    def __init__(self, mesh, depth: int, lod=None, precision: int = 32):
         lib = load()
         self._lib = lib
         self._keep = []
@@ -135,6 +143,9 @@ class Oracle:
         self.D = int(depth)
         self.cap = 1 << self.D
         self.k = int(lib.orc_root_bits(h))
+        self.precision = int(precision)
+        if lib.orc_set_precision(h, self.precision):
+            raise _err(lib)
         if lod is not None:
             self.set_lod(lod)
 
@@ -204,6 +215,24 @@ class Oracle:
         out = np.zeros(18, np.float32)
         self._lib.orc_frame_constants(self._h, _p(cam, C.c_float), _p(out, C.c_float))
         return out
+
+    def vertices64(self) -> np.ndarray:
+        v = np.zeros((self.cap, 9), np.float64)
+        if self._lib.orc_get_vertices64(self._h, _p(v, C.c_double)):
+            raise _err(self._lib)
+        return v
+
+    def decode64(self, hid: int) -> np.ndarray:
+        out = np.zeros(9, np.float64)
+        if self._lib.orc_decode64(self._h, C.c_uint64(hid), _p(out, C.c_double)):
+            raise _err(self._lib)
+        return out.reshape(3, 3)
+
+    def world_position64(self, v) -> np.ndarray:
+        v = np.ascontiguousarray(v, np.float64)
+        p = np.zeros(3, np.float64)
+        self._lib.orc_world_position64(self._h, _p(v, C.c_double), _p(p, C.c_double))
+        return p
 
     def world_position(self, v) -> np.ndarray:
         v = np.ascontiguousarray(v, np.float32)
