@@ -44,12 +44,13 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "bisector updates/s per frame (% HBM roofline); p50/p99 update latency"
 
 
-def algorithmic_bytes(stage: str, st: dict) -> float:
+def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
     """Bytes a stage must move per launch, from one frame's counters.
 
     L live bisectors, R merge requests, S bisectors consumed by splits,
     C merge configurations executed, M merged members, P parents (M / 2),
-    O split outputs (allocations - P)."""
+    O split outputs (allocations - P); vb is one vertex record (three world
+    positions with depth and parity: 48 bytes in binary32, 96 in binary64)."""
     L = st["live_before"]
     R = st["merge_requests"]
     S = st["split_consumed"]
@@ -58,17 +59,19 @@ def algorithmic_bytes(stage: str, st: dict) -> float:
     P = M // 2
     O = st["allocations"] - P
     if stage == "classify":
-        # rank -> block (4), cached world positions (48), command write (4);
-        # even merge requests are listed (8)
-        return 56.0 * L + 4.0 * R
+        # rank -> block (4), the vertex record (vb), command write (4); even
+        # merge requests are listed (8 for about half of them)
+        return (8.0 + vb) * L + 4.0 * R
     if stage == "fill":
-        # owner entries (8 + 4); a split bisector's vertex record read (96) and
-        # its fate + forwarding written (20); per split output a free-list
-        # entry (4) and a vertex record (96); a merge reads its members'
-        # forwarding (16) and IDs (8 per parent), per parent the children's
-        # vertex halves (96), a free-list entry (4) and the parent's record
-        # (96); every merged member's fate + forwarding (20)
-        return 12.0 * (S + C) + 116.0 * S + 100.0 * O + 16.0 * C + 204.0 * P + 20.0 * M
+        # owner entries (8 + 4); a split bisector's ID (8) and vertex record
+        # (vb) read, its fate + forwarding written (20); per split output a
+        # free-list entry (4) and a vertex record (vb); a merge reads its
+        # smallest member's forwarding (16), per parent a member's ID (8),
+        # three of the children's six world positions (vb), a free-list entry
+        # (4) and writes the parent's record (vb); every merged member's
+        # fate + forwarding (20).  Flat vertices are decoded from the IDs.
+        return (12.0 * (S + C) + (28.0 + vb) * S + (4.0 + vb) * O + 16.0 * C + (12.0 + 2.0 * vb) * P
+                + 20.0 * M)
     if stage == "resolve":
         # owner entries (8); a split bisector's ID, pointers, forwarding (40),
         # its three neighbours' pointers (48), its bit (4); per output ID +
@@ -77,10 +80,10 @@ def algorithmic_bytes(stage: str, st: dict) -> float:
         # neighbours' pointers (32), ID + pointers (24), two bits (8)
         return 8.0 * (S + C) + 92.0 * S + 24.0 * O + 120.0 * P
     if stage == "frame":
-        # every stage: rank passes over L (enumerate 4, classify 56, budget 8,
-        # owners 8), the fill and resolve bytes, and the bitfield + tree
-        # passes (3/8 byte per pool block, taken as L here)
-        return 76.0 * L + algorithmic_bytes("fill", st) + algorithmic_bytes("resolve", st)
+        # every stage: rank passes over L (enumerate 4, classify 8 + vb,
+        # budget 8, owners 8), the fill and resolve bytes, and the bitfield +
+        # tree passes (3/8 byte per pool block, taken as L here)
+        return (28.0 + vb) * L + algorithmic_bytes("fill", st, vb) + algorithmic_bytes("resolve", st, vb)
     raise KeyError(stage)
 
 
@@ -89,13 +92,13 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, np.float64), q)) if len(xs) else None
 
 
-def cpu_baseline(workload: str, budget_s: float) -> dict:
+def cpu_baseline(workload: str, budget_s: float, precision: int = 32) -> dict:
     """The CPU reference (single-threaded C) on the first frames of the same
     workload, timed frame by frame until about budget_s seconds of work."""
     from oracle import Oracle
     from paper_2407_02215_amd import inputs as I
     w = I.workload(workload, frames=64)
-    o = Oracle(w.mesh, w.depth, w.lod)
+    o = Oracle(w.mesh, w.depth, w.lod, precision=precision)
     total_l, total_t, frames = 0, 0.0, 0
     lo, hi = None, None
     for cam in w.cameras:
@@ -124,7 +127,7 @@ def run_single(args) -> dict:
     w = I.workload(args.workload, frames=max(frames, 8))
     if len(w.cameras) < frames:
         raise SystemExit(f"workload {args.workload} has {len(w.cameras)} frames, asked for {frames}")
-    inst = cbt.Instance(w.mesh, w.depth, w.lod, tuned=True)
+    inst = cbt.Instance(w.mesh, w.depth, w.lod, tuned=True, precision=args.precision)
     print(f"# warm-up {args.warmup} frames, schedule {inst.schedule()}", file=sys.stderr, flush=True)
     for cam in w.cameras[:args.warmup]:
         inst.update(cam)
@@ -157,7 +160,8 @@ def run_single(args) -> dict:
 
     updates = sum(s["live_before"] for s in stats)
     value = updates / elapsed
-    alg = sum(algorithmic_bytes(args.stage, s) for s in stats) / len(stats)
+    vb = 96 if args.precision == 64 else 48
+    alg = sum(algorithmic_bytes(args.stage, s, vb) for s in stats) / len(stats)
     mean_ms = stage_ms / max(1, launches)
     achieved = alg / (mean_ms * 1e-3) / 1e9
     out = {
@@ -171,7 +175,7 @@ def run_single(args) -> dict:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.precision == 64 else "f32",
         "data": "synthetic (seeded workload generator)",
         "config": {"workload": args.workload, "cbt_depth": w.depth, "halfedges": w.mesh.H,
                    "frames": f"{args.warmup}..{frames - 1}", "mean_live": updates / len(stats),
@@ -359,6 +363,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="terrain", choices=["terrain", "planet", "cube"])
+    ap.add_argument("--precision", type=int, default=32, choices=[32, 64],
+                    help="vertices, world positions and size test in binary32 or binary64 (single mode)")
     ap.add_argument("--stage", default="fill", choices=["classify", "fill", "resolve", "frame"])
     ap.add_argument("--traffic", type=float, default=None,
                     help="HBM bytes per launch of the profiled stage from the byte counters, if measured")
@@ -384,7 +390,7 @@ def main():
         print(json.dumps({"copy_bytes": a.numel(), "copies": 5}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build"}))
+        print(json.dumps({"error": "the update runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
     if args.mode == "single":
         args.steps = 200 if args.steps is None else args.steps
@@ -392,7 +398,7 @@ def main():
         out = run_single(args)
         if not args.no_cpu_baseline:
             print("# CPU reference baseline", file=sys.stderr, flush=True)
-            out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
+            out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, args.precision)
     elif args.mode == "batch":
         args.steps = 48 if args.steps is None else args.steps
         args.warmup = 16 if args.warmup is None else args.warmup

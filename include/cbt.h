@@ -91,11 +91,21 @@ enum {
     CBT_MODE_HEIGHTFIELD = 2  /* p = v + (0, 0, amplitude T_grid(v.x, v.y))        */
 };
 
-/* LOD parameters.  A live bisector is split when the projected length of
- * its base edge (v0,v1) exceeds split_px pixels and merged when it is below
- * merge_px; one whose vertices all lie outside one frustum plane is merged,
- * one whose base edge reaches behind the near plane is split (the paper's
- * screen-space size target of Section 3.3 kernel 4 and Section 4.1).
+/* Size criteria of the screen-space test (the paper's size target of
+ * Section 3.3 kernel 4 and Section 4.1). */
+enum {
+    CBT_CRIT_EDGE = 0,  /* projected length of the base edge, thresholds in pixels      */
+    CBT_CRIT_AREA = 1   /* projected area of the triangle, thresholds in pixels^2        */
+};
+
+/* LOD parameters.  With CBT_CRIT_EDGE a live bisector is split when the
+ * projected length of its base edge (v0,v1) exceeds split_px pixels and
+ * merged when it is below merge_px, and one whose base edge reaches behind
+ * the near plane is split; with CBT_CRIT_AREA the projected area of its
+ * triangle is compared with split_px and merge_px (pixels^2), and one with
+ * any vertex behind the near plane is split.  Either way one whose vertices
+ * all lie outside one frustum plane is merged; the comparisons are strict
+ * and division-free.
  * table is a DEVICE pointer (float32), caller-owned, that must stay valid
  * while updates run: 6 * table_res^2 texels for CBT_MODE_SPHERE (faces
  * +x,-x,+y,-y,+z,-z; texel (i,j) of a face at row j, column i) or
@@ -108,6 +118,7 @@ typedef struct {
     const float* table;
     int32_t table_res;
     float amplitude;
+    int32_t criterion;   /* CBT_CRIT_EDGE or CBT_CRIT_AREA */
 } cbt_lod_params;
 
 /* Per-frame counters (filled when a non-NULL pointer is passed). */
@@ -140,6 +151,9 @@ typedef struct {
     int32_t* prev;
     float* vertices;      /* out: 9 floats per bisector, flat-domain (Alg. 2)  */
     uint32_t* tree;       /* out: full CBT heap of 2^(D+1) counters, node 0 = 0 */
+    double* vertices64;   /* out: 9 doubles per bisector, flat-domain (Alg. 2),
+                             the binary64 decode of CBT_INIT_FP64 instances
+                             (binary32 instances: their decode, widened)   */
 } cbt_bisectors;
 
 /* Device workspace needed for a mesh of H halfedges and a pool of 2^D
@@ -153,6 +167,23 @@ size_t cbt_workspace_bytes(int32_t H, int32_t D);
  * workspace (CBT_E_BUDGET).  Synchronises the stream before returning. */
 cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace,
                     size_t workspace_bytes, void* hip_stream, cbt_handle* out);
+
+/* Instance flags of cbt_init_ex. */
+#define CBT_INIT_FP64 1u   /* vertices, world positions and the size test in
+                              binary64 (the paper evaluates planet vertices in
+                              double precision, Section 4.2): root triangles
+                              with the face mean in binary64, a 96-byte vertex
+                              record per block, the frame constants unrounded */
+
+/* Workspace of cbt_init_ex (0 when the arguments or flags are invalid). */
+size_t cbt_workspace_bytes_ex(int32_t H, int32_t D, uint32_t flags);
+
+/* cbt_init with instance flags (0 is cbt_init).  Unknown flags are
+ * CBT_E_ARG.  The pool logic is the same at either precision; only the
+ * decode, the world positions and the size test change width.  Binary64
+ * instances export triangles rounded once to float. */
+cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* device_workspace,
+                       size_t workspace_bytes, void* hip_stream, cbt_handle* out);
 
 /* One frame of the Section 3.3 pipeline: every live bisector decides by the
  * LOD test, splits propagate along compatibility chains (Alg. 3), merges
@@ -272,7 +303,7 @@ typedef struct cbt_batch_s* cbt_batch;
 #define CBT_BATCH_GRAPH 1
 
 /* 0 when the member list is invalid (NULL, repeated or failed handles,
- * n outside [1, 4096]). */
+ * members of both precisions, n outside [1, 4096]). */
 size_t cbt_batch_workspace_bytes(const cbt_handle* members, int32_t n);
 cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_workspace,
                             size_t workspace_bytes, void* hip_stream, int32_t flags,

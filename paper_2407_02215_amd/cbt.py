@@ -25,7 +25,9 @@ EXPORTED = ["cbt_workspace_bytes", "cbt_init", "cbt_update", "cbt_update_with_de
             "cbt_destroy", "cbt_status_string", "cbt_last_error", "cbt_time_stage", "cbt_stage_time",
             "cbt_set_schedule", "cbt_get_schedule", "cbt_stage_times", "cbt_batch_workspace_bytes", "cbt_batch_create",
             "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
-            "cbt_export_triangles"]
+            "cbt_export_triangles", "cbt_workspace_bytes_ex", "cbt_init_ex"]
+
+INIT_FP64 = 1
 
 STAGES = {"enumerate": 1, "classify": 2, "vote": 3, "budget": 4, "chain": 5, "owners": 6, "offsets": 7,
           "freelist": 8, "fill": 9, "resolve": 10, "reduce": 11, "frame": 12, "export": 13}
@@ -49,7 +51,7 @@ class Camera(C.Structure):
 
 class LodParams(C.Structure):
     _fields_ = [("mode", C.c_int32), ("split_px", C.c_float), ("merge_px", C.c_float), ("table", C.c_void_p),
-                ("table_res", C.c_int32), ("amplitude", C.c_float)]
+                ("table_res", C.c_int32), ("amplitude", C.c_float), ("criterion", C.c_int32)]
 
 
 class FrameStats(C.Structure):
@@ -64,7 +66,7 @@ class FrameStats(C.Structure):
 class Bisectors(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("count", C.c_int64), ("slot", C.c_void_p), ("heap_id", C.c_void_p),
                 ("twin", C.c_void_p), ("next", C.c_void_p), ("prev", C.c_void_p), ("vertices", C.c_void_p),
-                ("tree", C.c_void_p)]
+                ("tree", C.c_void_p), ("vertices64", C.c_void_p)]
 
 
 def load_library():
@@ -79,6 +81,9 @@ def load_library():
     lib.cbt_workspace_bytes.argtypes = [C.c_int32, C.c_int32]
     lib.cbt_workspace_bytes.restype = C.c_size_t
     lib.cbt_init.argtypes = [C.POINTER(Mesh), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.cbt_workspace_bytes_ex.argtypes = [C.c_int32, C.c_int32, C.c_uint32]
+    lib.cbt_workspace_bytes_ex.restype = C.c_size_t
+    lib.cbt_init_ex.argtypes = [C.POINTER(Mesh), C.c_int32, C.c_uint32, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.cbt_update.argtypes = [vp, C.POINTER(Camera), C.POINTER(LodParams), C.POINTER(FrameStats)]
     lib.cbt_update_with_decisions.argtypes = [vp, vp, C.POINTER(FrameStats)]
     lib.cbt_query.argtypes = [vp, C.POINTER(Bisectors)]
@@ -110,14 +115,15 @@ def load_library():
               "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count", "cbt_destroy",
               "cbt_time_stage", "cbt_stage_time", "cbt_stage_times", "cbt_set_schedule", "cbt_get_schedule", "cbt_batch_create",
               "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
-              "cbt_export_triangles"):
+              "cbt_export_triangles", "cbt_init_ex"):
         getattr(lib, f).restype = C.c_int32
     _LIB = lib
     return lib
 
 
-def workspace_bytes(H: int, D: int) -> int:
-    return int(load_library().cbt_workspace_bytes(H, D))
+def workspace_bytes(H: int, D: int, precision: int = 32) -> int:
+    flags = INIT_FP64 if precision == 64 else 0
+    return int(load_library().cbt_workspace_bytes_ex(H, D, flags))
 
 
 def _ptr(a: np.ndarray):
@@ -149,7 +155,8 @@ def canonical(heap_ids, k: int):
 class Instance:
     """One bisection-update instance resident on the GPU."""
 
-    def __init__(self, mesh, depth: int, lod=None, device: str = "cuda", stream=None, tuned: bool = False):
+    def __init__(self, mesh, depth: int, lod=None, device: str = "cuda", stream=None, tuned: bool = False,
+                 precision: int = 32):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -160,7 +167,10 @@ class Instance:
         self.cap = 1 << self.D
         self.H = int(mesh.H)
         self.k = (self.H - 1).bit_length()   # ceil(log2 H)
-        nbytes = workspace_bytes(self.H, self.D)
+        if precision not in (32, 64):
+            raise CbtError(-1, f"precision must be 32 or 64 bits, got {precision}")
+        self.precision = int(precision)
+        nbytes = workspace_bytes(self.H, self.D, self.precision)
         if nbytes == 0:
             raise CbtError(-3, f"invalid H={self.H} / D={self.D}")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -169,8 +179,9 @@ class Instance:
         pos = np.ascontiguousarray(mesh.pos, np.float32)
         m = Mesh(self.H, *(_ptr(a) for a in self._arrays), int(pos.shape[0]), _ptr(pos))
         h = C.c_void_p()
-        st = self.lib.cbt_init(C.byref(m), self.D, C.c_void_p(self.workspace.data_ptr()), nbytes,
-                               C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        flags = INIT_FP64 if self.precision == 64 else 0
+        st = self.lib.cbt_init_ex(C.byref(m), self.D, flags, C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if st != CBT_OK:
             raise CbtError(st, self.lib.cbt_last_error(None).decode())
         self.h = h
@@ -210,7 +221,7 @@ class Instance:
             self._table = None
         self._lodp = LodParams(int(lod.mode), float(lod.split_px), float(lod.merge_px),
                                C.c_void_p(self._table.data_ptr()) if self._table is not None else None,
-                               int(lod.table_res), float(lod.amplitude))
+                               int(lod.table_res), float(lod.amplitude), int(getattr(lod, "criterion", 0)))
 
     # -- frames -------------------------------------------------------------
     def update(self, camera, stats: bool = False):
@@ -265,7 +276,7 @@ class Instance:
         self._check(self.lib.cbt_live_count(self.h, C.byref(n)))
         return int(n.value)
 
-    def query(self, vertices: bool = False, tree: bool = False):
+    def query(self, vertices: bool = False, tree: bool = False, vertices64: bool = False):
         b = Bisectors()
         b.capacity = 0
         if tree:
@@ -280,14 +291,19 @@ class Instance:
         nx = np.zeros(L, np.int32)
         pv = np.zeros(L, np.int32)
         b2 = Bisectors(L, 0, _ptr(slot), _ptr(ids), _ptr(tw), _ptr(nx), _ptr(pv), None, None)
-        verts = None
+        verts = verts64 = None
         if vertices:
             verts = np.zeros((L, 9), np.float32)
             b2.vertices = _ptr(verts)
+        if vertices64:
+            verts64 = np.zeros((L, 9), np.float64)
+            b2.vertices64 = _ptr(verts64)
         self._check(self.lib.cbt_query(self.h, C.byref(b2)))
         out.update(slot=slot, heap_id=ids, twin=tw, next=nx, prev=pv)
         if vertices:
             out["vertices"] = verts
+        if vertices64:
+            out["vertices64"] = verts64
         if tree:
             out["tree"] = heap
         return out
@@ -527,7 +543,7 @@ class Server:
             table = self._tables[key][1]
         lp = LodParams(int(lod.mode), float(lod.split_px), float(lod.merge_px),
                        C.c_void_p(table.data_ptr()) if table is not None else None, int(lod.table_res),
-                       float(lod.amplitude))
+                       float(lod.amplitude), int(getattr(lod, "criterion", 0)))
         arrays = [np.ascontiguousarray(a, np.int32) for a in (mesh.twin, mesh.next, mesh.prev, mesh.vert)]
         pos = np.ascontiguousarray(mesh.pos, np.float32)
         m = Mesh(int(mesh.H), *(_ptr(a) for a in arrays), int(pos.shape[0]), _ptr(pos))

@@ -40,7 +40,8 @@ cbt_status hip_fail(cbt_handle h, hipError_t e, const char* what)
     return fail(h, CBT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Frame constants in double precision, each rounded once to float.
+// Frame constants in double precision.  Binary32 instances round each of
+// them once to float on the device; binary64 instances use them as is.
 void make_lodk(const cbt_camera* c, const cbt_lod_params* lp, LodK* K)
 {
     const double f[3] = {c->fwd[0], c->fwd[1], c->fwd[2]};
@@ -57,15 +58,21 @@ void make_lodk(const cbt_camera* c, const cbt_lod_params* lp, LodK* K)
     const double focal = 0.5 * (double)c->height / th;
     for (int i = 0; i < 3; ++i) {
         K->cam[i] = c->pos[i];
-        K->right[i] = (float)r[i];
-        K->up[i] = (float)up[i];
-        K->fwd[i] = (float)fw[i];
+        K->right[i] = r[i];
+        K->up[i] = up[i];
+        K->fwd[i] = fw[i];
     }
-    K->f2 = (float)(focal * focal);
-    K->t2s = (float)((double)lp->split_px * (double)lp->split_px);
-    K->t2m = (float)((double)lp->merge_px * (double)lp->merge_px);
-    K->tx = (float)(th * (double)c->width / (double)c->height);
-    K->ty = (float)th;
+    K->f2 = focal * focal;
+    if (lp->criterion == CBT_CRIT_AREA) {   // twice the target areas
+        K->t2s = 2.0 * (double)lp->split_px;
+        K->t2m = 2.0 * (double)lp->merge_px;
+    } else {                                // squared target lengths
+        K->t2s = (double)lp->split_px * (double)lp->split_px;
+        K->t2m = (double)lp->merge_px * (double)lp->merge_px;
+    }
+    K->crit = lp->criterion;
+    K->tx = th * (double)c->width / (double)c->height;
+    K->ty = th;
     K->znear = c->znear;
     K->table = lp->table;
     K->res = lp->table_res;
@@ -77,6 +84,8 @@ cbt_status check_lod(cbt_handle h, const cbt_camera* c, const cbt_lod_params* lp
 {
     if (!c || !lp) return fail(h, CBT_E_ARG, "camera and LOD parameters are required");
     if (lp->mode < CBT_MODE_FLAT || lp->mode > CBT_MODE_HEIGHTFIELD) return fail(h, CBT_E_ARG, "unknown LOD mode %d", lp->mode);
+    if (lp->criterion != CBT_CRIT_EDGE && lp->criterion != CBT_CRIT_AREA)
+        return fail(h, CBT_E_ARG, "unknown size criterion %d", lp->criterion);
     if (lp->mode != CBT_MODE_FLAT && (!lp->table || lp->table_res < 2))
         return fail(h, CBT_E_ARG, "LOD mode %d needs a device table of resolution >= 2", lp->mode);
     if (c->width <= 0 || c->height <= 0 || !(c->fovy > 0.0f && c->fovy < 3.14159f))
@@ -215,6 +224,32 @@ static void root_triangles(const cbt_mesh* m, std::vector<float>& out)
     }
 }
 
+// The same roots with the face mean accumulated and divided in binary64
+// (binary64 instances): corners are the binary32 mesh positions, exact in
+// binary64.
+static void root_triangles64(const cbt_mesh* m, std::vector<double>& out)
+{
+    const int32_t H = m->H;
+    out.assign(9 * (size_t)H, 0.0);
+    for (int32_t h = 0; h < H; ++h) {
+        int32_t mn = h;
+        for (int32_t g = m->next[h]; g != h; g = m->next[g]) mn = g < mn ? g : mn;
+        double sum[3] = {m->pos[3 * m->vert[mn] + 0], m->pos[3 * m->vert[mn] + 1], m->pos[3 * m->vert[mn] + 2]};
+        int n = 1;
+        for (int32_t g = m->next[mn]; g != mn; g = m->next[g]) {
+            for (int i = 0; i < 3; ++i) sum[i] = sum[i] + (double)m->pos[3 * m->vert[g] + i];
+            ++n;
+        }
+        const float* a = m->pos + 3 * m->vert[h];
+        const float* b = m->pos + 3 * m->vert[m->next[h]];
+        for (int i = 0; i < 3; ++i) {
+            out[9 * h + i] = a[i];
+            out[9 * h + 3 + i] = b[i];
+            out[9 * h + 6 + i] = sum[i] / (double)n;
+        }
+    }
+}
+
 // Device scratch that is free between frames: the work-list region
 // (8 bytes per pool block).
 static char* list_scratch(const Pool& P, size_t* bytes)
@@ -225,22 +260,32 @@ static char* list_scratch(const Pool& P, size_t* bytes)
 
 extern "C" {
 
-size_t cbt_workspace_bytes(int32_t H, int32_t D)
+size_t cbt_workspace_bytes_ex(int32_t H, int32_t D, uint32_t flags)
 {
-    if (H < 3 || D < 5 || D > 30 || D < ceil_log2(H)) return 0;
-    return cbtk::workspace_layout(H, D, nullptr, nullptr);
+    if (H < 3 || D < 5 || D > 30 || D < ceil_log2(H) || (flags & ~(uint32_t)CBT_INIT_FP64)) return 0;
+    return cbtk::workspace_layout(H, D, (flags & CBT_INIT_FP64) ? 1 : 0, nullptr, nullptr);
 }
+
+size_t cbt_workspace_bytes(int32_t H, int32_t D) { return cbt_workspace_bytes_ex(H, D, 0); }
 
 cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, size_t workspace_bytes,
                     void* hip_stream, cbt_handle* out)
 {
+    return cbt_init_ex(mesh, D, 0, device_workspace, workspace_bytes, hip_stream, out);
+}
+
+cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* device_workspace,
+                       size_t workspace_bytes, void* hip_stream, cbt_handle* out)
+{
     if (!out) return fail(nullptr, CBT_E_ARG, "output handle pointer is NULL");
     *out = nullptr;
+    if (flags & ~(uint32_t)CBT_INIT_FP64) return fail(nullptr, CBT_E_ARG, "unknown init flags 0x%x", flags);
+    const int32_t f64 = (flags & CBT_INIT_FP64) ? 1 : 0;
     cbt_status st = cbth::validate_mesh(mesh);
     if (st) return st;
     const int k = ceil_log2(mesh->H);
     if (D < 5 || D > 30 || D < k) return fail(nullptr, CBT_E_DEPTH, "depth %d outside [max(5, ceil(log2 H)=%d), 30]", D, k);
-    const size_t need = cbtk::workspace_layout(mesh->H, D, nullptr, nullptr);
+    const size_t need = cbtk::workspace_layout(mesh->H, D, f64, nullptr, nullptr);
     if (!device_workspace) return fail(nullptr, CBT_E_ARG, "device workspace is NULL");
     if (reinterpret_cast<uintptr_t>(device_workspace) & 255) return fail(nullptr, CBT_E_ARG, "workspace must be 256-byte aligned");
     if (workspace_bytes < need) return fail(nullptr, CBT_E_BUDGET, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
@@ -250,7 +295,7 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     h->ws = reinterpret_cast<char*>(device_workspace);
     h->ws_bytes = workspace_bytes;
-    cbtk::workspace_layout(mesh->H, D, &h->P, h->ws);
+    cbtk::workspace_layout(mesh->H, D, f64, &h->P, h->ws);
     h->P.k = k;
     h->P.G = cbth::default_rank_groups(D);
     h->P.sub = cbtk::kMaxReduceSub;
@@ -275,7 +320,9 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
     std::vector<uint32_t> words((H + 31) / 32, 0u);
     for (int32_t i = 0; i < H; ++i) words[i >> 5] |= 1u << (i & 31);
     std::vector<float> roots;
-    root_triangles(mesh, roots);
+    std::vector<double> roots64;
+    if (f64) root_triangles64(mesh, roots64);
+    else root_triangles(mesh, roots);
 
     const Pool& P = h->P;
     hipStream_t s = h->stream;
@@ -304,9 +351,15 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
     INIT_TRY(hipMemsetAsync(P.ctr, 0, sizeof(Counters), s), "clear counters");
     INIT_TRY(hipMemcpyAsync(staging, recs.data(), sizeof(uint32_t) * recs.size(), hipMemcpyHostToDevice, s), "upload roots");
     INIT_TRY(cbtk::launch_import_records(P, 0, (uint32_t)H, staging, s), "root records");
-    INIT_TRY(hipMemsetAsync(P.vworld, 0, sizeof(float4) * 3 * (size_t)P.cap, s), "clear vertex cache");
+    INIT_TRY(hipMemsetAsync(P.vworld, 0, (f64 ? sizeof(double4) : sizeof(float4)) * 3 * (size_t)P.cap, s),
+             "clear vertex cache");
     INIT_TRY(hipMemcpyAsync(P.bits, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice, s), "upload bits");
-    INIT_TRY(hipMemcpyAsync(P.root, roots.data(), sizeof(float) * roots.size(), hipMemcpyHostToDevice, s), "upload root triangles");
+    if (f64)
+        INIT_TRY(hipMemcpyAsync(P.root, roots64.data(), sizeof(double) * roots64.size(), hipMemcpyHostToDevice, s),
+                 "upload root triangles");
+    else
+        INIT_TRY(hipMemcpyAsync(P.root, roots.data(), sizeof(float) * roots.size(), hipMemcpyHostToDevice, s),
+                 "upload root triangles");
     std::memset(&h->wk, 0, sizeof h->wk);   // flat world positions until LOD parameters arrive
     INIT_TRY(cbtk::launch_reduce(cbtk::single_launch(P, h->wk, nullptr), s), "sum reduction");
     INIT_TRY(cbtk::launch_refresh(cbtk::single_launch(P, h->wk, nullptr), s), "vertex cache");
@@ -509,7 +562,7 @@ cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
     if (st) return st;
     const uint32_t L = h->hctr->L;
     out->count = L;
-    const bool per = out->slot || out->heap_id || out->twin || out->next || out->prev || out->vertices;
+    const bool per = out->slot || out->heap_id || out->twin || out->next || out->prev || out->vertices || out->vertices64;
     if (per && out->capacity < (int64_t)L) return fail(h, CBT_E_CAPACITY, "capacity %lld < %u live bisectors", (long long)out->capacity, L);
     size_t scratch_bytes;
     char* scratch = list_scratch(P, &scratch_bytes);
@@ -542,6 +595,16 @@ cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
             const uint32_t n = (L - r0) < chunk ? (L - r0) : chunk;
             HIP_TRY(h, cbtk::launch_gather_vertices(P, r0, n, reinterpret_cast<float*>(scratch), s), "gather vertices");
             HIP_TRY(h, hipMemcpyAsync(out->vertices + 9 * (size_t)r0, scratch, sizeof(float) * 9 * n, hipMemcpyDeviceToHost, s),
+                    "copy vertices");
+            HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+        }
+    }
+    if (out->vertices64 && L) {
+        const uint32_t chunk = (uint32_t)(scratch_bytes / (9 * sizeof(double)));
+        for (uint32_t r0 = 0; r0 < L; r0 += chunk) {
+            const uint32_t n = (L - r0) < chunk ? (L - r0) : chunk;
+            HIP_TRY(h, cbtk::launch_gather_vertices64(P, r0, n, reinterpret_cast<double*>(scratch), s), "gather vertices");
+            HIP_TRY(h, hipMemcpyAsync(out->vertices64 + 9 * (size_t)r0, scratch, sizeof(double) * 9 * n, hipMemcpyDeviceToHost, s),
                     "copy vertices");
             HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
         }
@@ -643,15 +706,15 @@ cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twi
 cbt_status cbt_frame_constants(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod, float* out18)
 {
     if (!out18) return fail(h, CBT_E_ARG, "NULL output");
-    cbt_lod_params lp = lod ? *lod : cbt_lod_params{CBT_MODE_FLAT, 1.0f, 1.0f, nullptr, 0, 0.0f};
+    cbt_lod_params lp = lod ? *lod : cbt_lod_params{CBT_MODE_FLAT, 1.0f, 1.0f, nullptr, 0, 0.0f, CBT_CRIT_EDGE};
     lp.mode = CBT_MODE_FLAT;   // the table is irrelevant for the constants
     cbt_status st = cbth::check_lod(h, camera, &lp);
     if (st) return st;
     LodK K;
     cbth::make_lodk(camera, &lp, &K);
-    const float v[18] = {K.cam[0], K.cam[1], K.cam[2], K.right[0], K.right[1], K.right[2], K.up[0], K.up[1], K.up[2],
-                         K.fwd[0], K.fwd[1], K.fwd[2], K.f2, K.t2s, K.t2m, K.tx, K.ty, K.znear};
-    std::memcpy(out18, v, sizeof v);
+    const double v[18] = {K.cam[0], K.cam[1], K.cam[2], K.right[0], K.right[1], K.right[2], K.up[0], K.up[1], K.up[2],
+                          K.fwd[0], K.fwd[1], K.fwd[2], K.f2, K.t2s, K.t2m, K.tx, K.ty, K.znear};
+    for (int i = 0; i < 18; ++i) out18[i] = (float)v[i];   // the binary32 path's constants
     return CBT_OK;
 }
 

@@ -71,6 +71,8 @@ cbt_status check_members(const cbt_handle* members, int32_t n)
         if (members[i]->failed) return cbth::fail(nullptr, CBT_E_STATE, "member %d failed earlier: %s", i, members[i]->err);
         for (int j = 0; j < i; ++j)
             if (members[j] == members[i]) return cbth::fail(nullptr, CBT_E_ARG, "member %d appears twice", i);
+        if (members[i]->P.f64 != members[0]->P.f64)
+            return cbth::fail(nullptr, CBT_E_ARG, "member %d: a batch holds instances of one precision", i);
     }
     return CBT_OK;
 }
@@ -260,6 +262,7 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
     cbtk::Launch& X = b->X;
     std::memset(&X, 0, sizeof X);
     X.batched = true;
+    X.f64 = members[0]->P.f64 != 0;
     X.B.n = n;
     X.B.inst = b->d_inst;
     X.B.map_rank = b->d_map_rank;

@@ -70,14 +70,17 @@ struct Counters {
     uint32_t stat[kStCount];
 };
 
-// Per-frame LOD constants (Section 3.3 kernel 4).
+// Per-frame LOD constants (Section 3.3 kernel 4), evaluated in double on
+// the host.  Binary32 instances use each value rounded once to float,
+// binary64 instances use it as is.
 struct LodK {
-    float cam[3], right[3], up[3], fwd[3];
-    float f2, t2s, t2m, tx, ty, znear;
+    double cam[3], right[3], up[3], fwd[3];
+    double f2, t2s, t2m, tx, ty, znear;   // t2s, t2m: squared pixel lengths, or twice the pixel areas
+    double amp;
     const float* table;
     int32_t res;
-    float amp;
     int32_t mode;
+    int32_t crit;                          // size criterion (CBT_CRIT_*)
 };
 
 // Device state of one instance, carved from its workspace.
@@ -93,9 +96,11 @@ struct Pool {
                        //       merged member; on the smallest member of a
                        //       merge configuration first its other members,
                        //       then (parent, members)
-    float4* vworld;    // [3 cap] world positions of the three vertices; w of the first holds
-                       //         the subdivision depth, of the second the
-                       //         parity of the heap ID (as integers)
+    float4* vworld;    // [3 cap] world positions of the three vertices; w of
+                       //         the first holds the subdivision depth, of the
+                       //         second the parity of the heap ID (as integers);
+                       //         binary64 instances: [3 cap] double4, depth and
+                       //         parity as exact doubles
     uint32_t* cmd;     // [cap] command word, rewritten every frame
     uint32_t* bits;    // [W]   occupancy bitfield, bit s&31 of word s>>5
     uint32_t* tree;    // [2^(D-4)] sum-reduction tree down to word level
@@ -110,11 +115,12 @@ struct Pool {
     uint32_t* lcnt;   // [kMaxRankGroups] entries in each workgroup's list
     uint2* part;       // [kMaxRankGroups] per-workgroup partial sums
     Counters* ctr;
-    float* root;       // [9H] root triangle vertices
+    float* root;       // [9H] root triangle vertices (binary64 instances: double)
     int32_t D, k, H;
     uint32_t cap, W;
     uint32_t G;        // rank workgroups (launch schedule)
     int32_t sub;       // tree levels per reduction workgroup (launch schedule)
+    int32_t f64;       // vertices, world positions and the size test in binary64
 };
 
 // One instance as the kernels see it: state, this frame's constants and the
@@ -140,6 +146,7 @@ struct Batch {
 // (batched = false) or a batch in device memory, and the grid sizes.
 struct Launch {
     bool batched;
+    bool f64;          // every instance of the launch in binary64
     Inst one;
     Batch B;
     uint32_t n_inst;
@@ -151,7 +158,7 @@ uint32_t word_groups(const Pool& P);
 uint32_t reduce_groups(const Pool& P);
 int reduce_levels(const Pool& P);
 
-size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base);
+size_t workspace_layout(int32_t H, int32_t D, int32_t f64, Pool* P, char* base);
 Launch single_launch(const Pool& P, const LodK& K, const uint8_t* inj);
 
 // Optional event pair recorded around the launches of one pipeline stage
@@ -181,6 +188,8 @@ hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s);
 hipError_t launch_gather_ids(const Pool& P, uint32_t r0, uint32_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_gather_links(const Pool& P, uint32_t r0, uint32_t n, int32_t* out3, hipStream_t s);
 hipError_t launch_gather_vertices(const Pool& P, uint32_t r0, uint32_t n, float* out9, hipStream_t s);
+// binary64 decode (binary32 instances: their decode, widened)
+hipError_t launch_gather_vertices64(const Pool& P, uint32_t r0, uint32_t n, double* out9, hipStream_t s);
 hipError_t launch_gather_decisions(const Pool& P, uint32_t L, uint8_t* out_per_slot, hipStream_t s);
 hipError_t launch_export_heap(const Pool& P, uint32_t* out, hipStream_t s);
 // blocks [b0, b0+n) <-> packed records (id low, id high, twin, next, prev)

@@ -55,6 +55,13 @@
 
 namespace cbtk {
 
+// Ranks each thread of a rank-order pass loads before it processes them
+// (all rows' loads in flight at once: these passes are bound by the latency
+// of the rank -> block -> command chain, not by bandwidth).
+constexpr int kClassRows = 2;   // LOD test: 48 bytes of vertices per rank
+constexpr int kRankRows = 8;    // budget: rank entry and command word
+constexpr int kOwnerRows = 4;   // owners: plus merge members
+
 // ---------------------------------------------------------------------------
 // wave64 / workgroup scan primitives
 // ---------------------------------------------------------------------------
@@ -315,15 +322,25 @@ __global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
     const uint32_t blk = pick<kB>(B, one, B.map_word, P);
     const uint32_t w0 = blk * kWordsPerBlock;
     if (w0 >= P.W) return;
+    // all of this workgroup's words in flight while the tree is descended
+    constexpr int kSteps = kWordsPerBlock / kBlock;
+    uint32_t words[kSteps];
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) {
+        const uint32_t w = w0 + j * kBlock + threadIdx.x;
+        words[j] = (w < P.W) ? P.bits[w] : 0u;
+    }
     uint32_t base = ones_before_word(P, w0);
-    for (uint32_t it = 0; it < kWordsPerBlock; it += kBlock) {
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) {
+        const uint32_t it = j * kBlock;
         const uint32_t w = w0 + it + threadIdx.x;
-        uint32_t word = (w < P.W) ? P.bits[w] : 0u;
+        uint32_t word = words[j];
         uint32_t tot;
         uint32_t o = block_excl_scan(__popc(word), sh, &tot);
         while (word) {
-            const int j = __ffs(word) - 1;
-            stage[o++] = w * 32u + (uint32_t)j;
+            const int bit = __ffs(word) - 1;
+            stage[o++] = w * 32u + (uint32_t)bit;
             word &= word - 1;
         }
         __syncthreads();
@@ -338,29 +355,69 @@ __global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
 // bisector geometry (Eq. 1 / Alg. 2), world position and the LOD test
 // ---------------------------------------------------------------------------
 
-struct V3 {
-    float x, y, z;
-};
+// Vertices, world positions and the size test are generic in the precision
+// R: binary32, or binary64 for instances created with the binary64 flag (the
+// paper's planets are evaluated in double, Section 4.2).  The binary32 path
+// uses every frame constant rounded once to float.
 
-__device__ __forceinline__ V3 mid3(V3 a, V3 b) { return {(a.x + b.x) * 0.5f, (a.y + b.y) * 0.5f, (a.z + b.z) * 0.5f}; }
-__device__ __forceinline__ V3 ld3(const float4& v) { return {v.x, v.y, v.z}; }
-__device__ __forceinline__ float4 st3(V3 v, int w) { return make_float4(v.x, v.y, v.z, __int_as_float(w)); }
+template <typename R>
+struct Vec3 {
+    R x, y, z;
+};
+using V3 = Vec3<float>;
+
+template <typename R> struct Store;
+template <> struct Store<float> { using T4 = float4; };
+template <> struct Store<double> { using T4 = double4; };
+template <typename R> using T4 = typename Store<R>::T4;
+
+__device__ __forceinline__ float floor_r(float x) { return floorf(x); }
+__device__ __forceinline__ double floor_r(double x) { return floor(x); }
+__device__ __forceinline__ float abs_r(float x) { return fabsf(x); }
+__device__ __forceinline__ double abs_r(double x) { return fabs(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return __builtin_sqrt(x); }
+
+// depth / parity ride in the w components: bit patterns in binary32,
+// exact values in binary64
+__device__ __forceinline__ float4 make4(Vec3<float> v, int w) { return make_float4(v.x, v.y, v.z, __int_as_float(w)); }
+__device__ __forceinline__ double4 make4(Vec3<double> v, int w) { return make_double4(v.x, v.y, v.z, (double)w); }
+__device__ __forceinline__ int w_int(float w) { return __float_as_int(w); }
+__device__ __forceinline__ int w_int(double w) { return (int)w; }
+
+template <typename R>
+__device__ __forceinline__ Vec3<R> ld3(const T4<R>& v) { return {v.x, v.y, v.z}; }
+
+template <typename R>
+__device__ __forceinline__ Vec3<R> mid3(Vec3<R> a, Vec3<R> b)
+{
+    const R h = (R)0.5;
+    return {(a.x + b.x) * h, (a.y + b.y) * h, (a.z + b.z) * h};
+}
+
+template <typename R>
+__device__ __forceinline__ T4<R>* world_rec(const Pool& P, uint32_t s)
+{
+    return reinterpret_cast<T4<R>*>(P.vworld) + 3 * (size_t)s;
+}
 
 // Splitting matrices applied from the root downwards, one path bit per
 // level, most significant first: M0 -> (v0, v2, m), M1 -> (v2, v1, m).
 // Scalar registers only (struct selects would be lowered through scratch).
-__device__ __forceinline__ void decode(const Pool& P, uint64_t id, int d, V3& A, V3& B, V3& C)
+template <typename R>
+__device__ __forceinline__ void decode(const Pool& P, uint64_t id, int d, Vec3<R>& A, Vec3<R>& B, Vec3<R>& C)
 {
     const int64_t h = (int64_t)(id >> d) - ((int64_t)1 << P.k);
-    const float* r = P.root + 9 * h;
-    float ax = r[0], ay = r[1], az = r[2];
-    float bx = r[3], by = r[4], bz = r[5];
-    float cx = r[6], cy = r[7], cz = r[8];
+    const R* r = reinterpret_cast<const R*>(P.root) + 9 * h;
+    R ax = r[0], ay = r[1], az = r[2];
+    R bx = r[3], by = r[4], bz = r[5];
+    R cx = r[6], cy = r[7], cz = r[8];
+    const R half = (R)0.5;
     for (int i = d - 1; i >= 0; --i) {
         const bool bit = (id >> i) & 1u;
-        const float mx = (ax + bx) * 0.5f, my = (ay + by) * 0.5f, mz = (az + bz) * 0.5f;
-        const float nax = bit ? cx : ax, nay = bit ? cy : ay, naz = bit ? cz : az;
-        const float nbx = bit ? bx : cx, nby = bit ? by : cy, nbz = bit ? bz : cz;
+        const R mx = (ax + bx) * half, my = (ay + by) * half, mz = (az + bz) * half;
+        const R nax = bit ? cx : ax, nay = bit ? cy : ay, naz = bit ? cz : az;
+        const R nbx = bit ? bx : cx, nby = bit ? by : cy, nbz = bit ? bz : cz;
         ax = nax; ay = nay; az = naz;
         bx = nbx; by = nby; bz = nbz;
         cx = mx; cy = my; cz = mz;
@@ -376,101 +433,128 @@ __device__ __forceinline__ bool valid_id(const Pool& P, uint64_t id)
     return id != 0 && d >= 0 && d <= 63 - P.k && (int64_t)(id >> d) - ((int64_t)1 << P.k) < P.H;
 }
 
-__device__ __forceinline__ float bilinear(const float* T, int res, float s, float t)
+template <typename R>
+__device__ __forceinline__ R bilinear(const float* T, int res, R s, R t)
 {
-    float fs = floorf(s), ft = floorf(t);
-    const float lim = (float)(res - 2);
-    fs = fs < 0.0f ? 0.0f : fs;
+    R fs = floor_r(s), ft = floor_r(t);
+    const R lim = (R)(res - 2);
+    fs = fs < (R)0 ? (R)0 : fs;
     fs = fs > lim ? lim : fs;
-    ft = ft < 0.0f ? 0.0f : ft;
+    ft = ft < (R)0 ? (R)0 : ft;
     ft = ft > lim ? lim : ft;
     int i0 = (int)fs, j0 = (int)ft;
     i0 = i0 < 0 ? 0 : (i0 > res - 2 ? res - 2 : i0);   // bounds guard (no-op unless NaN)
     j0 = j0 < 0 ? 0 : (j0 > res - 2 ? res - 2 : j0);
-    const float fx = s - fs, fy = t - ft;
+    const R fx = s - fs, fy = t - ft;
     const float* r0 = T + (size_t)j0 * res + i0;
     const float* r1 = r0 + res;
-    const float a = r0[0], b = r0[1], c = r1[0], e = r1[1];
-    const float top = a + fx * (b - a);
-    const float bot = c + fx * (e - c);
+    const R a = r0[0], b = r0[1], c = r1[0], e = r1[1];
+    const R top = a + fx * (b - a);
+    const R bot = c + fx * (e - c);
     return top + fy * (bot - top);
 }
 
 // cube-map face = axis of largest magnitude (ties x, y, z), face order
 // +x -x +y -y +z -z, (u, v) = the other two components over the major one
-__device__ __forceinline__ float sample_cube(const LodK& K, float x, float y, float z)
+template <typename R>
+__device__ __forceinline__ R sample_cube(const LodK& K, R x, R y, R z)
 {
-    const float ax = fabsf(x), ay = fabsf(y), az = fabsf(z);
+    const R ax = abs_r(x), ay = abs_r(y), az = abs_r(z);
     int f;
-    float u, v;
+    R u, v;
     if (ax >= ay && ax >= az) {
-        f = x >= 0.0f ? 0 : 1;
+        f = x >= (R)0 ? 0 : 1;
         u = y / ax;
         v = z / ax;
     } else if (ay >= az) {
-        f = y >= 0.0f ? 2 : 3;
+        f = y >= (R)0 ? 2 : 3;
         u = x / ay;
         v = z / ay;
     } else {
-        f = z >= 0.0f ? 4 : 5;
+        f = z >= (R)0 ? 4 : 5;
         u = x / az;
         v = y / az;
     }
-    const float hr = 0.5f * (float)(K.res - 1);
-    return bilinear(K.table + (size_t)f * K.res * K.res, K.res, (u + 1.0f) * hr, (v + 1.0f) * hr);
+    const R hr = (R)0.5 * (R)(K.res - 1);
+    return bilinear<R>(K.table + (size_t)f * K.res * K.res, K.res, (u + (R)1) * hr, (v + (R)1) * hr);
 }
 
 // world position of a flat-domain point (sphere projection + cube-map
 // displacement, or height-field displacement, or identity)
-__device__ __forceinline__ V3 world(const LodK& K, V3 v)
+template <typename R>
+__device__ __forceinline__ Vec3<R> world(const LodK& K, Vec3<R> v)
 {
     if (K.mode == 1) {
-        const float len = __builtin_sqrtf((v.x * v.x + v.y * v.y) + v.z * v.z);
-        const float nx = v.x / len, ny = v.y / len, nz = v.z / len;
-        const float h = sample_cube(K, nx, ny, nz);
-        const float sc = 1.0f + K.amp * h;
+        const R len = sqrt_r((v.x * v.x + v.y * v.y) + v.z * v.z);
+        const R nx = v.x / len, ny = v.y / len, nz = v.z / len;
+        const R h = sample_cube<R>(K, nx, ny, nz);
+        const R sc = (R)1 + (R)K.amp * h;
         return {nx * sc, ny * sc, nz * sc};
     }
     if (K.mode == 2) {
-        const float r1 = (float)(K.res - 1);
-        const float h = bilinear(K.table, K.res, v.x * r1, v.y * r1);
-        return {v.x, v.y, v.z + K.amp * h};
+        const R r1 = (R)(K.res - 1);
+        const R h = bilinear<R>(K.table, K.res, v.x * r1, v.y * r1);
+        return {v.x, v.y, v.z + (R)K.amp * h};
     }
     return v;
 }
 
-// Projected base-edge length test without division: returns the decision
-// code from the three world positions.
-__device__ __forceinline__ uint32_t lod_decide(const LodK& K, V3 p0, V3 p1, V3 p2)
+// Screen-space size test without division (projected base-edge length, or
+// projected triangle area): returns the decision code from the three world
+// positions.
+template <typename R>
+__device__ __forceinline__ uint32_t lod_decide(const LodK& K, Vec3<R> p0, Vec3<R> p1, Vec3<R> p2)
 {
-    const V3 p[3] = {p0, p1, p2};
-    float vx[3], vy[3], vz[3];
+    const Vec3<R> p[3] = {p0, p1, p2};
+    const R cam[3] = {(R)K.cam[0], (R)K.cam[1], (R)K.cam[2]};
+    const R rt[3] = {(R)K.right[0], (R)K.right[1], (R)K.right[2]};
+    const R up[3] = {(R)K.up[0], (R)K.up[1], (R)K.up[2]};
+    const R fw[3] = {(R)K.fwd[0], (R)K.fwd[1], (R)K.fwd[2]};
+    const R tx = (R)K.tx, ty = (R)K.ty, znear = (R)K.znear;
+    R vx[3], vy[3], vz[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const float q0 = p[i].x - K.cam[0], q1 = p[i].y - K.cam[1], q2 = p[i].z - K.cam[2];
-        vx[i] = (q0 * K.right[0] + q1 * K.right[1]) + q2 * K.right[2];
-        vy[i] = (q0 * K.up[0] + q1 * K.up[1]) + q2 * K.up[2];
-        vz[i] = (q0 * K.fwd[0] + q1 * K.fwd[1]) + q2 * K.fwd[2];
+        const R q0 = p[i].x - cam[0], q1 = p[i].y - cam[1], q2 = p[i].z - cam[2];
+        vx[i] = (q0 * rt[0] + q1 * rt[1]) + q2 * rt[2];
+        vy[i] = (q0 * up[0] + q1 * up[1]) + q2 * up[2];
+        vz[i] = (q0 * fw[0] + q1 * fw[1]) + q2 * fw[2];
     }
     bool on = true, ol = true, orr = true, ob = true, ot = true;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const float zx = K.tx * vz[i], zy = K.ty * vz[i];
-        on = on && (vz[i] < K.znear);
+        const R zx = tx * vz[i], zy = ty * vz[i];
+        on = on && (vz[i] < znear);
         orr = orr && (vx[i] > zx);
         ol = ol && (vx[i] < -zx);
         ot = ot && (vy[i] > zy);
         ob = ob && (vy[i] < -zy);
     }
     if (on || ol || orr || ob || ot) return kMerge;
-    if (vz[0] < K.znear || vz[1] < K.znear) return kSplit;
-    const float ex = vx[1] * vz[0] - vx[0] * vz[1];
-    const float ey = vy[1] * vz[0] - vy[0] * vz[1];
-    const float A = K.f2 * (ex * ex + ey * ey);
-    const float zz = vz[0] * vz[1];
-    const float z4 = zz * zz;
-    const float Bs = K.t2s * z4;
-    const float Bm = K.t2m * z4;
+    const R f2 = (R)K.f2, t2s = (R)K.t2s, t2m = (R)K.t2m;
+    if (K.crit == 1) {
+        // projected triangle area: twice the area in pixels^2 is
+        // f^2 |N| / (z0^2 z1 z2), N the cross product of the projected edges
+        // with the depths multiplied out
+        if (vz[0] < znear || vz[1] < znear || vz[2] < znear) return kSplit;
+        const R ax = vx[1] * vz[0] - vx[0] * vz[1];
+        const R ay = vy[1] * vz[0] - vy[0] * vz[1];
+        const R bx = vx[2] * vz[0] - vx[0] * vz[2];
+        const R by = vy[2] * vz[0] - vy[0] * vz[2];
+        const R N = ax * by - bx * ay;
+        const R A = f2 * abs_r(N);
+        const R zq = (vz[0] * vz[0]) * (vz[1] * vz[2]);
+        if (A > t2s * zq) return kSplit;
+        if (A < t2m * zq) return kMerge;
+        return kKeep;
+    }
+    if (vz[0] < znear || vz[1] < znear) return kSplit;
+    const R ex = vx[1] * vz[0] - vx[0] * vz[1];
+    const R ey = vy[1] * vz[0] - vy[0] * vz[1];
+    const R A = f2 * (ex * ex + ey * ey);
+    const R zz = vz[0] * vz[1];
+    const R z4 = zz * zz;
+    const R Bs = t2s * z4;
+    const R Bm = t2m * z4;
     if (A > Bs) return kSplit;
     if (A < Bm) return kMerge;
     return kKeep;
@@ -478,12 +562,14 @@ __device__ __forceinline__ uint32_t lod_decide(const LodK& K, V3 p0, V3 p1, V3 p
 
 // vertex-cache record of block s: world positions of the three vertices,
 // the depth and the heap-ID parity
-__device__ __forceinline__ void store_world(const Pool& P, uint32_t s, V3 pa, V3 pb, V3 pc, int depth, int parity)
+template <typename R>
+__device__ __forceinline__ void store_world(const Pool& P, uint32_t s, Vec3<R> pa, Vec3<R> pb, Vec3<R> pc, int depth,
+                                            int parity)
 {
-    float4* w = P.vworld + 3 * (size_t)s;
-    w[0] = st3(pa, depth);
-    w[1] = st3(pb, parity);
-    w[2] = st3(pc, 0);
+    T4<R>* w = world_rec<R>(P, s);
+    w[0] = make4(pa, depth);
+    w[1] = make4(pb, parity);
+    w[2] = make4(pc, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -491,7 +577,7 @@ __device__ __forceinline__ void store_world(const Pool& P, uint32_t s, V3 pa, V3
 // positions, the depth and the parity, so no heap ID is read)
 // ---------------------------------------------------------------------------
 
-template <bool kB>
+template <bool kB, typename R>
 __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
@@ -503,42 +589,59 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
     rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     const int maxd = 63 - P.k;
     uint32_t nsplit = 0, nmerge = 0, scost = 0, nlist = 0;
-    for (uint32_t base = r0; base < r1; base += kBlock) {
-        const uint32_t r = base + threadIdx.x;
-        bool cand = false;
-        uint32_t s = 0;
-        if (r < r1) {
-            s = P.live[r];
-            const float4* w = P.vworld + 3 * (size_t)s;
-            const float4 w0 = w[0], w1 = w[1], w2 = w[2];
-            const int d = __float_as_int(w0.w);
-            uint32_t dec;
-            if (inj) {
-                dec = inj[s];
-                if (dec > kMerge) {
-                    raise_err(P, kErrDecision);
+    for (uint32_t base = r0; base < r1; base += kBlock * kClassRows) {
+        // every row's loads in flight before the first row is processed
+        uint32_t sr[kClassRows];
+        T4<R> wa[kClassRows], wb[kClassRows], wc[kClassRows];
+#pragma unroll
+        for (int j = 0; j < kClassRows; ++j) {
+            const uint32_t r = base + j * kBlock + threadIdx.x;
+            sr[j] = r < r1 ? P.live[r] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kClassRows; ++j) {
+            // past the chunk sr[j] is block 0: an in-bounds load, unused
+            const T4<R>* w = world_rec<R>(P, sr[j]);
+            wa[j] = w[0];
+            wb[j] = w[1];
+            wc[j] = w[2];
+        }
+#pragma unroll
+        for (int j = 0; j < kClassRows; ++j) {
+            if (base + j * kBlock >= r1) continue;   // uniform: rows past the chunk
+            const uint32_t r = base + j * kBlock + threadIdx.x;
+            const uint32_t s = sr[j];
+            bool cand = false;
+            if (r < r1) {
+                const int d = w_int(wa[j].w);
+                uint32_t dec;
+                if (inj) {
+                    dec = inj[s];
+                    if (dec > kMerge) {
+                        raise_err(P, kErrDecision);
+                        dec = kKeep;
+                    }
+                } else {
+                    dec = lod_decide<R>(K, ld3<R>(wa[j]), ld3<R>(wb[j]), ld3<R>(wc[j]));
+                }
+                if (dec == kMerge && d == 0) dec = kKeep;       // roots never merge
+                if (dec == kSplit && d + 1 > maxd) dec = kKeep; // index width
+                if ((uint32_t)d > 63u) {
+                    raise_err(P, kErrPointer);
                     dec = kKeep;
                 }
-            } else {
-                dec = lod_decide(K, ld3(w0), ld3(w1), ld3(w2));
+                P.cmd[s] = dec | ((uint32_t)d << kDepthShift);
+                if (dec == kSplit) {
+                    ++nsplit;
+                    scost += 3u * (uint32_t)d + 4u;
+                } else if (dec == kMerge) {
+                    ++nmerge;
+                    // configurations are found from their even members (Alg. 4)
+                    cand = w_int(wb[j].w) == 0;
+                }
             }
-            if (dec == kMerge && d == 0) dec = kKeep;       // roots never merge
-            if (dec == kSplit && d + 1 > maxd) dec = kKeep; // index width
-            if ((uint32_t)d > 63u) {
-                raise_err(P, kErrPointer);
-                dec = kKeep;
-            }
-            P.cmd[s] = dec | ((uint32_t)d << kDepthShift);
-            if (dec == kSplit) {
-                ++nsplit;
-                scost += 3u * (uint32_t)d + 4u;
-            } else if (dec == kMerge) {
-                ++nmerge;
-                // configurations are found from their even members (Alg. 4)
-                cand = __float_as_int(w1.w) == 0;
-            }
+            list_append(P, r0, &nlist, cand, make_uint2(s, 0), sh);
         }
-        list_append(P, r0, &nlist, cand, make_uint2(s, 0), sh);
     }
     const uint32_t a = block_sum(nsplit, sh);
     const uint32_t b = block_sum(nmerge, sh);
@@ -560,26 +663,36 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
 // the same depth and j4 = Prev(j3) is j3's sibling.  The smallest ID of a
 // configuration is always an even member (c0 < c1), so configurations are
 // detected, once, from their even members.
+// The loads of each level (sibling and Prev neighbour, then the fourth
+// member) are issued together; c2..c4 receive the members' command words.
 __device__ __forceinline__ int merge_config_even(const Pool& P, uint64_t id, int4 l1, int32_t* j2o, int32_t* j3o,
-                                                 int32_t* j4o, uint64_t* id4o)
+                                                 int32_t* j4o, uint64_t* id4o, uint32_t* c2, uint32_t* c3,
+                                                 uint32_t* c4)
 {
     const int32_t j2 = l1.y, j3 = l1.z;
+    if ((j2 >= 0 && !slot_ok(P, j2)) || (j3 >= 0 && !slot_ok(P, j3))) { raise_err(P, kErrPointer); return 0; }
     if (j2 < 0) return 0;
-    if (!slot_ok(P, j2)) { raise_err(P, kErrPointer); return 0; }
-    if ((P.id[j2] >> 1) != (id >> 1)) return 0;
+    const uint32_t a3 = j3 >= 0 ? (uint32_t)j3 : 0u;   // in bounds either way
+    const uint64_t id2 = P.id[j2];
+    const uint32_t cm2 = P.cmd[j2];
+    const uint64_t id3 = P.id[a3];
+    const int32_t j4 = P.link[a3].z;
+    const uint32_t cm3 = P.cmd[a3];
+    if ((id2 >> 1) != (id >> 1)) return 0;
     *j2o = j2;
+    *c2 = cm2;
     if (j3 < 0) return 2;
-    if (!slot_ok(P, j3)) { raise_err(P, kErrPointer); return 0; }
-    const uint64_t id3 = P.id[j3];
     if (ilog2_64(id3) != ilog2_64(id)) return 0;
-    const int32_t j4 = P.link[j3].z;
     if (j4 < 0) return 0;
     if (!slot_ok(P, j4)) { raise_err(P, kErrPointer); return 0; }
     const uint64_t id4 = P.id[j4];
+    const uint32_t cm4 = P.cmd[j4];
     if ((id4 >> 1) != (id3 >> 1)) return 0;
     *j3o = j3;
     *j4o = j4;
     *id4o = id4;
+    *c3 = cm3;
+    *c4 = cm4;
     return 4;
 }
 
@@ -601,10 +714,11 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
         const uint64_t id = P.id[s];
         int32_t j2 = -1, j3 = -1, j4 = -1;
         uint64_t id4 = 0;
-        const int m = merge_config_even(P, id, P.link[s], &j2, &j3, &j4, &id4);
+        uint32_t c2 = 0, c3 = 0, c4 = 0;
+        const int m = merge_config_even(P, id, P.link[s], &j2, &j3, &j4, &id4, &c2, &c3, &c4);
         if (!m || (m == 4 && id4 < id)) continue;   // not the smallest member
-        bool ok = (P.cmd[j2] & kDecMask) == kMerge;
-        if (m == 4) ok = ok && (P.cmd[j3] & kDecMask) == kMerge && (P.cmd[j4] & kDecMask) == kMerge;
+        bool ok = (c2 & kDecMask) == kMerge;
+        if (m == 4) ok = ok && (c3 & kDecMask) == kMerge && (c4 & kDecMask) == kMerge;
         if (!ok) continue;
         P.cmd[s] |= kMCfg | kMMin | kMUnan | (m == 4 ? kMQuad : 0u);
         P.fwd[s] = make_uint4((uint32_t)j2, (uint32_t)j3, (uint32_t)j4, (uint32_t)m);
@@ -689,24 +803,34 @@ __global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
     const uint32_t F = P.ctr->F, Tm = P.ctr->Tm;
     uint2 carry = P.part[blk];
     uint32_t nm = 0, nlist = 0;
-    for (uint32_t base = r0; base < r1; base += kBlock) {
-        const uint32_t r = base + threadIdx.x;
-        uint2 v = make_uint2(0, 0);
-        uint32_t s = 0, c = 0;
-        if (r < r1) {
-            s = P.live[r];
-            c = P.cmd[s];
+    for (uint32_t base = r0; base < r1; base += kBlock * kRankRows) {
+        uint32_t sr[kRankRows], cr[kRankRows];
+#pragma unroll
+        for (int j = 0; j < kRankRows; ++j) {
+            const uint32_t r = base + j * kBlock + threadIdx.x;
+            sr[j] = r < r1 ? P.live[r] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kRankRows; ++j) {
+            const uint32_t r = base + j * kBlock + threadIdx.x;
+            cr[j] = r < r1 ? P.cmd[sr[j]] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kRankRows; ++j) {
+            if (base + j * kBlock >= r1) continue;   // uniform: rows past the chunk
+            const uint32_t s = sr[j], c = cr[j];
+            uint2 v = make_uint2(0, 0);
             if (c & kMUnan) v.x = (c & kMQuad) ? 2u : 1u;
             if ((c & kDecMask) == kSplit) v.y = 3u * (uint32_t)depth_of_cmd(c) + 4u;
+            uint2 tot;
+            const uint2 inc = sat_add2(carry, block_incl_scan_sat(v, sh2, &tot));
+            if (v.x && inc.x <= F) {
+                P.cmd[s] = c | kMAcc;
+                ++nm;
+            }
+            list_append(P, r0, &nlist, v.y && sat_add(Tm, inc.y) <= F, make_uint2(s, 0), sh);
+            carry = sat_add2(carry, tot);
         }
-        uint2 tot;
-        const uint2 inc = sat_add2(carry, block_incl_scan_sat(v, sh2, &tot));
-        if (v.x && inc.x <= F) {
-            P.cmd[s] = c | kMAcc;
-            ++nm;
-        }
-        list_append(P, r0, &nlist, v.y && sat_add(Tm, inc.y) <= F, make_uint2(s, 0), sh);
-        carry = sat_add2(carry, tot);
     }
     const uint32_t a = block_sum(nm, sh);
     if (threadIdx.x == 0) {
@@ -785,39 +909,63 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
     rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     uint32_t nexec = 0, nsc = 0, nfree = 0;
     uint2 run = make_uint2(0, 0);   // (owners, outputs) of earlier iterations
-    for (uint32_t base = r0; base < r1; base += kBlock) {
-        const uint32_t r = base + threadIdx.x;
-        uint32_t s = 0, c = 0, k = 0;
-        if (r < r1) {
-            s = P.live[r];
-            c = P.cmd[s];
+    for (uint32_t base = r0; base < r1; base += kBlock * kOwnerRows) {
+        // loads of every row in flight: rank entries, commands, then the
+        // members of accepted merges and their commands
+        uint32_t sr[kOwnerRows], cr[kOwnerRows];
+        uint4 mr[kOwnerRows];
+        bool marked[kOwnerRows];
+#pragma unroll
+        for (int j = 0; j < kOwnerRows; ++j) {
+            const uint32_t r = base + j * kBlock + threadIdx.x;
+            sr[j] = r < r1 ? P.live[r] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kOwnerRows; ++j) {
+            const uint32_t r = base + j * kBlock + threadIdx.x;
+            cr[j] = r < r1 ? P.cmd[sr[j]] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kOwnerRows; ++j) {
+            const bool acc = !(cr[j] & kMarks) && (cr[j] & kMAcc);
+            mr[j] = acc ? P.fwd[sr[j]] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < kOwnerRows; ++j) {
+            // splits win: a configuration with a split-marked member stays
+            bool any = false;
+            if (mr[j].w) {
+                any = (P.cmd[mr[j].x] & kMarks) != 0;
+                if (mr[j].w == 4) any = any || (P.cmd[mr[j].y] & kMarks) || (P.cmd[mr[j].z] & kMarks);
+            }
+            marked[j] = any;
+        }
+#pragma unroll
+        for (int j = 0; j < kOwnerRows; ++j) {
+            if (base + j * kBlock >= r1) continue;   // uniform: rows past the chunk
+            const uint32_t s = sr[j];
+            uint32_t c = cr[j], k = 0;
             if (c & kMarks) {
                 k = split_outputs(c);
                 ++nsc;
                 ++nfree;
-            } else if (c & kMAcc) {
-                // splits win: a configuration with a split-marked member stays
-                const uint4 m = P.fwd[s];
-                bool clean = !(P.cmd[m.x] & kMarks);
-                if (m.w == 4) clean = clean && !(P.cmd[m.y] & kMarks) && !(P.cmd[m.z] & kMarks);
-                if (clean) {
-                    c |= kMExec;
-                    k = m.w / 2;
-                    ++nexec;
-                    nfree += m.w;
-                }
+            } else if (mr[j].w && !marked[j]) {
+                c |= kMExec;
+                k = mr[j].w / 2;
+                ++nexec;
+                nfree += mr[j].w;
             }
+            // owners before this one in the workgroup, and their outputs
+            const uint2 v = make_uint2(k ? 1u : 0u, k);
+            uint2 tot;
+            const uint2 inc = block_incl_scan_sat(v, sh2, &tot);
+            if (k) {
+                const uint32_t at = r0 + run.x + inc.x - 1u;
+                P.list[at] = make_uint2(s, c);
+                P.lpre[at] = run.y + inc.y - k;
+            }
+            run = make_uint2(run.x + tot.x, run.y + tot.y);
         }
-        // owners before this one in the workgroup, and their outputs
-        const uint2 v = make_uint2(k ? 1u : 0u, k);
-        uint2 tot;
-        const uint2 inc = block_incl_scan_sat(v, sh2, &tot);
-        if (k) {
-            const uint32_t at = r0 + run.x + inc.x - 1u;
-            P.list[at] = make_uint2(s, c);
-            P.lpre[at] = run.y + inc.y - k;
-        }
-        run = make_uint2(run.x + tot.x, run.y + tot.y);
     }
     const uint32_t a = block_sum(nexec, sh);
     const uint32_t b = block_sum(nsc, sh);
@@ -890,9 +1038,11 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
 // keeps the other members (second, third, fourth fields) for the pointer
 // pass.
 
+template <typename R>
 __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_t s, uint32_t c, uint32_t base,
                                            uint32_t N)
 {
+    using V = Vec3<R>;
     const bool hn = c & kMarkN, hp = c & kMarkP;
     const uint32_t cnt = 2u + (hn ? 1u : 0u) + (hp ? 1u : 0u);
     if (base + cnt > N) { raise_err(P, kErrAlloc); return; }
@@ -902,12 +1052,12 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
     const int d = depth_of_cmd(c);
     // flat vertices: the Alg. 2 decode of the heap ID (no memory beyond the
     // ID and the root table); world positions: the cache
-    V3 v0, v1, v2;
-    decode(P, P.id[s], d, v0, v1, v2);
-    const float4* wv = P.vworld + 3 * (size_t)s;
-    const V3 w0 = ld3(wv[0]), w1 = ld3(wv[1]), w2 = ld3(wv[2]);
-    const V3 m = mid3(v0, v1);
-    const V3 wm = world(K, m);
+    V v0, v1, v2;
+    decode<R>(P, P.id[s], d, v0, v1, v2);
+    const T4<R>* wv = world_rec<R>(P, s);
+    const V w0 = ld3<R>(wv[0]), w1 = ld3<R>(wv[1]), w2 = ld3<R>(wv[2]);
+    const V m = mid3(v0, v1);
+    const V wm = world<R>(K, m);
     uint32_t r0q, r1q = 0xffffffffu, r2q, r3q = 0xffffffffu;
     if (!hn && !hp) {          // 2x, 2x+1
         r0q = q0; r2q = q1;
@@ -920,38 +1070,40 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
     }
     // first child (v0, v2, m), or its children (v0, m, m0) and (m, v2, m0)
     if (!hp) {
-        store_world(P, r0q, w0, w2, wm, d + 1, 0);
+        store_world<R>(P, r0q, w0, w2, wm, d + 1, 0);
     } else {
-        const V3 m0 = mid3(v0, v2);
-        const V3 wm0 = world(K, m0);
-        store_world(P, r0q, w0, wm, wm0, d + 2, 0);
-        store_world(P, r1q, wm, w2, wm0, d + 2, 1);
+        const V m0 = mid3(v0, v2);
+        const V wm0 = world<R>(K, m0);
+        store_world<R>(P, r0q, w0, wm, wm0, d + 2, 0);
+        store_world<R>(P, r1q, wm, w2, wm0, d + 2, 1);
     }
     // second child (v2, v1, m), or its children (v2, m, m1) and (m, v1, m1)
     if (!hn) {
-        store_world(P, r2q, w2, w1, wm, d + 1, 1);
+        store_world<R>(P, r2q, w2, w1, wm, d + 1, 1);
     } else {
-        const V3 m1 = mid3(v2, v1);
-        const V3 wm1 = world(K, m1);
-        store_world(P, r2q, w2, wm, wm1, d + 2, 0);
-        store_world(P, r3q, wm, w1, wm1, d + 2, 1);
+        const V m1 = mid3(v2, v1);
+        const V wm1 = world<R>(K, m1);
+        store_world<R>(P, r2q, w2, wm, wm1, d + 2, 0);
+        store_world<R>(P, r3q, wm, w1, wm1, d + 2, 1);
     }
     P.link[s].w = (int)c;
     P.fwd[s] = make_uint4(r0q, r1q, r2q, r3q);
 }
 
 // parent of the sibling pair (c0 even, c1 odd): vertices (c0.v0, c1.v1, c0.v1)
+template <typename R>
 __device__ __forceinline__ void fill_parent(const Pool& P, uint32_t q, int32_t c0, int32_t c1, int depth, int parity)
 {
-    const float4* w0 = P.vworld + 3 * (size_t)c0;
-    const float4* w1 = P.vworld + 3 * (size_t)c1;
-    float4* wq = P.vworld + 3 * (size_t)q;
-    const float4 a = w0[0], b = w1[1], c = w0[1];
-    wq[0] = make_float4(a.x, a.y, a.z, __int_as_float(depth));
-    wq[1] = make_float4(b.x, b.y, b.z, __int_as_float(parity));
-    wq[2] = make_float4(c.x, c.y, c.z, 0.0f);
+    const T4<R>* w0 = world_rec<R>(P, c0);
+    const T4<R>* w1 = world_rec<R>(P, c1);
+    T4<R>* wq = world_rec<R>(P, q);
+    const T4<R> a = w0[0], b = w1[1], c = w0[1];
+    wq[0] = make4(ld3<R>(a), depth);
+    wq[1] = make4(ld3<R>(b), parity);
+    wq[2] = make4(ld3<R>(c), 0);
 }
 
+template <typename R>
 __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c, uint32_t base, uint32_t N)
 {
     const uint4 m = P.fwd[s];   // (sibling, other odd, other even, members)
@@ -969,13 +1121,13 @@ __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c
     }
     if (qa >= P.cap || (quad && qb >= P.cap)) { raise_err(P, kErrAlloc); return; }
     const int dp = depth_of_cmd(c) - 1;
-    fill_parent(P, qa, (int32_t)s, (int32_t)m.x, dp, (int)(ida & 1u));
+    fill_parent<R>(P, qa, (int32_t)s, (int32_t)m.x, dp, (int)(ida & 1u));
     P.link[s].w = (int)kMExec;
     P.fwd[s] = make_uint4(qa, m.x, m.y, m.z);
     P.link[m.x].w = (int)kMExec;
     P.fwd[m.x] = make_uint4(qa, 0, 0, 0);
     if (quad) {
-        fill_parent(P, qb, (int32_t)m.z, (int32_t)m.y, dp, (int)(idb & 1u));
+        fill_parent<R>(P, qb, (int32_t)m.z, (int32_t)m.y, dp, (int)(idb & 1u));
         P.link[m.y].w = (int)kMExec;
         P.fwd[m.y] = make_uint4(qb, 0, 0, 0);
         P.link[m.z].w = (int)kMExec;
@@ -983,7 +1135,7 @@ __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c
     }
 }
 
-template <bool kB>
+template <bool kB, typename R>
 __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
@@ -1000,8 +1152,8 @@ __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
         const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
         const uint2 e = P.list[at];
         const uint32_t off = P.part[w].x + P.lpre[at];
-        if (e.y & kMarks) fill_split(P, K, e.x, e.y, off, N);
-        else fill_merge(P, e.x, e.y, off, N);
+        if (e.y & kMarks) fill_split<R>(P, K, e.x, e.y, off, N);
+        else fill_merge<R>(P, e.x, e.y, off, N);
     }
 }
 
@@ -1047,29 +1199,31 @@ struct Nb {
     uint4 fw;
 };
 
-__device__ __forceinline__ Nb load_nb(const Pool& P, int32_t b, int32_t n)
+// The neighbours n[i] of bisectors b[i] (-1: border), in two rounds of
+// loads: the pointer records of all of them, then the forwarding records of
+// those consumed this frame.  Unused slots load block 0 (in bounds, ignored).
+template <int N>
+__device__ __forceinline__ void load_nbs(const Pool& P, const int32_t (&b)[N], const int32_t (&n)[N], Nb (&r)[N])
 {
-    Nb r;
-    r.n = n;
-    r.f = -1;
-    r.c = 0;
-    r.fw = make_uint4(0, 0, 0, 0);
-    if (n < 0) return r;
-    if (!slot_ok(P, n)) {
-        raise_err(P, kErrPointer);
-        r.n = -1;
-        return r;
+    int4 ln[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const bool ok = slot_ok(P, n[i]);
+        if (n[i] >= 0 && !ok) raise_err(P, kErrPointer);
+        ln[i] = P.link[ok ? n[i] : 0];
     }
-    const int4 ln = P.link[n];
-    r.f = ln.x == b ? 0 : (ln.y == b ? 1 : (ln.z == b ? 2 : -1));
-    if (r.f < 0) {
-        raise_err(P, kErrPointer);
-        r.n = -1;
-        return r;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const bool ok = slot_ok(P, n[i]);
+        const int f = ln[i].x == b[i] ? 0 : (ln[i].y == b[i] ? 1 : (ln[i].z == b[i] ? 2 : -1));
+        if (ok && f < 0) raise_err(P, kErrPointer);
+        const bool use = ok && f >= 0;
+        r[i].n = use ? n[i] : -1;
+        r[i].f = f;
+        r[i].c = use ? (uint32_t)ln[i].w : 0u;
     }
-    r.c = (uint32_t)ln.w;
-    if (r.c) r.fw = P.fwd[n];
-    return r;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i].fw = P.fwd[r[i].c ? r[i].n : 0];
 }
 
 // New neighbour across (a piece of) an old edge, seen from output x: the
@@ -1113,9 +1267,13 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
     const uint64_t x = P.id[b];
     const int4 lb = P.link[b];
     const uint4 f = P.fwd[b];
-    const Nb nT = load_nb(P, b, lb.x);
-    const Nb nN = load_nb(P, b, lb.y);
-    const Nb nP = load_nb(P, b, lb.z);
+    const int32_t own[3] = {b, b, b};
+    const int32_t across[3] = {lb.x, lb.y, lb.z};
+    Nb nb[3];
+    load_nbs(P, own, across, nb);
+    const Nb& nT = nb[0];
+    const Nb& nN = nb[1];
+    const Nb& nP = nb[2];
     if (!hp) {  // first child (v0, v2, m)
         store_new(P, f.x, 2 * x, piece_target(P, nP, db, kWhole, f.x), (int32_t)f.z,
                   piece_target(P, nT, db, kHalf0, f.x));
@@ -1135,14 +1293,33 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
     clear_bit(P, (uint32_t)b);
 }
 
-// parent q of the sibling pair (c0, c1): Next edge = c1's base edge, Prev
-// edge = c0's base edge, Twin = the other parent (or the border)
-__device__ __forceinline__ void resolve_parent(const Pool& P, uint32_t q, uint64_t id, int32_t twin, int32_t c0,
-                                               int32_t c1, int d)
+// Parents of an executed merge (owner b, the smallest member): a parent q of
+// the sibling pair (c0 even, c1 odd) has Next edge = c1's base edge, Prev
+// edge = c0's base edge and Twin = the other parent (or the border).  The
+// members' pointer records, then their base-edge neighbours, are loaded in
+// one round each; a border pair loads its own members twice (unused).
+__device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t c)
 {
-    const Nb n1 = load_nb(P, c1, P.link[c1].x);
-    const Nb n0 = load_nb(P, c0, P.link[c0].x);
-    store_new(P, q, id, twin, piece_target(P, n1, d, kWhole, q), piece_target(P, n0, d, kWhole, q));
+    const uint4 f = P.fwd[b];   // (parent, sibling, other odd, other even)
+    const uint64_t ida = P.id[b] >> 1;
+    const int d = depth_of_cmd(c);
+    const bool quad = (c & kMQuad) != 0;
+    const uint32_t e2 = quad ? f.w : (uint32_t)b, o2 = quad ? f.z : f.y;
+    const uint32_t qb = P.fwd[e2].x;            // the second parent
+    const uint64_t idb = P.id[e2] >> 1;
+    const int32_t mem[4] = {(int32_t)f.y, b, (int32_t)o2, (int32_t)e2};
+    const int32_t twin[4] = {P.link[f.y].x, P.link[b].x, P.link[o2].x, P.link[e2].x};
+    Nb nb[4];
+    load_nbs(P, mem, twin, nb);
+    store_new(P, f.x, ida, quad ? (int32_t)qb : -1, piece_target(P, nb[0], d, kWhole, f.x),
+              piece_target(P, nb[1], d, kWhole, f.x));
+    if (quad) {
+        store_new(P, qb, idb, (int32_t)f.x, piece_target(P, nb[2], d, kWhole, qb), piece_target(P, nb[3], d, kWhole, qb));
+        clear_bit(P, f.z);
+        clear_bit(P, f.w);
+    }
+    clear_bit(P, (uint32_t)b);
+    clear_bit(P, f.y);
 }
 
 template <bool kB>
@@ -1158,25 +1335,8 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
         const uint2 e = P.list[list_at(base, P.G, ls.chunk, i, &w)];
         const int32_t b = (int32_t)e.x;
         const uint32_t c = e.y;
-        if (c & kMarks) {
-            resolve_split(P, b, c);
-        } else {
-            const uint4 f = P.fwd[b];   // (parent, sibling, other odd, other even)
-            const uint64_t ida = P.id[b] >> 1;
-            const int d = depth_of_cmd(c);
-            if (c & kMQuad) {
-                const uint32_t qb = P.fwd[f.w].x;
-                const uint64_t idb = P.id[f.w] >> 1;
-                resolve_parent(P, f.x, ida, (int32_t)qb, b, (int32_t)f.y, d);
-                resolve_parent(P, qb, idb, (int32_t)f.x, (int32_t)f.w, (int32_t)f.z, d);
-                clear_bit(P, f.z);
-                clear_bit(P, f.w);
-            } else {
-                resolve_parent(P, f.x, ida, -1, b, (int32_t)f.y, d);
-            }
-            clear_bit(P, (uint32_t)b);
-            clear_bit(P, f.y);
-        }
+        if (c & kMarks) resolve_split(P, b, c);
+        else resolve_merge(P, b, c);
     }
 }
 
@@ -1243,7 +1403,7 @@ __global__ void __launch_bounds__(1024) k_reduce_top(Batch B, Inst one)
 
 // Rebuild the cache of every live block: world positions of the Alg. 2
 // decode of its heap ID.
-template <bool kB>
+template <bool kB, typename R>
 __global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
 {
     Pool P;
@@ -1255,15 +1415,15 @@ __global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
     for (uint32_t r = blk * kBlock + threadIdx.x; r < L; r += P.G * kBlock) {
         const uint32_t s = P.live[r];
         const uint64_t id = P.id[s];
-        V3 a = {0, 0, 0}, b = a, c = a;
+        Vec3<R> a = {0, 0, 0}, b = a, c = a;
         int d = 0;
         if (valid_id(P, id)) {
             d = ilog2_64(id) - P.k;
-            decode(P, id, d, a, b, c);
+            decode<R>(P, id, d, a, b, c);
         } else {
             raise_err(P, kErrPointer);
         }
-        store_world(P, s, world(K, a), world(K, b), world(K, c), d, (int)(id & 1u));
+        store_world<R>(P, s, world<R>(K, a), world<R>(K, b), world<R>(K, c), d, (int)(id & 1u));
     }
 }
 
@@ -1294,20 +1454,22 @@ __global__ void k_gather_links(Pool P, uint32_t r0, uint32_t n, int32_t* out)
     out[3 * (size_t)i + 2] = l.z;
 }
 
-// flat-domain vertices: the Alg. 2 decode of the heap ID
-__global__ void k_gather_vertices(Pool P, uint32_t r0, uint32_t n, float* out)
+// flat-domain vertices: the Alg. 2 decode of the heap ID in the instance's
+// precision R, written as O (binary64 results rounded once when O is float)
+template <typename R, typename O>
+__global__ void k_gather_vertices(Pool P, uint32_t r0, uint32_t n, O* out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t id = P.id[P.live[r0 + i]];
-    V3 v[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    if (valid_id(P, id)) decode(P, id, ilog2_64(id) - P.k, v[0], v[1], v[2]);
+    Vec3<R> v[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (valid_id(P, id)) decode<R>(P, id, ilog2_64(id) - P.k, v[0], v[1], v[2]);
     else raise_err(P, kErrPointer);
-    float* o = out + 9 * (size_t)i;
+    O* o = out + 9 * (size_t)i;
     for (int j = 0; j < 3; ++j) {
-        o[3 * j + 0] = v[j].x;
-        o[3 * j + 1] = v[j].y;
-        o[3 * j + 2] = v[j].z;
+        o[3 * j + 0] = (O)v[j].x;
+        o[3 * j + 1] = (O)v[j].y;
+        o[3 * j + 2] = (O)v[j].z;
     }
 }
 
@@ -1373,18 +1535,19 @@ __global__ void k_import_records(Pool P, uint32_t b0, uint32_t n, const uint32_t
 // Triangle export: the cached world positions of every live bisector's
 // three vertices, in rank order, 9 floats per triangle.  Each workgroup
 // stages its 256 triangles in LDS and writes them as one contiguous run.
+template <typename R>
 __global__ void __launch_bounds__(kBlock) k_export_triangles(Pool P, uint32_t L, float* out)
 {
     __shared__ float stage[kBlock * 9];
     const uint32_t r0 = blockIdx.x * kBlock;
     const uint32_t r = r0 + threadIdx.x;
     if (r < L) {
-        const float4* w = P.vworld + 3 * (size_t)P.live[r];
-        const float4 a = w[0], b = w[1], c = w[2];
+        const T4<R>* w = world_rec<R>(P, P.live[r]);
+        const T4<R> a = w[0], b = w[1], c = w[2];
         float* t = stage + 9 * threadIdx.x;
-        t[0] = a.x; t[1] = a.y; t[2] = a.z;
-        t[3] = b.x; t[4] = b.y; t[5] = b.z;
-        t[6] = c.x; t[7] = c.y; t[8] = c.z;
+        t[0] = (float)a.x; t[1] = (float)a.y; t[2] = (float)a.z;
+        t[3] = (float)b.x; t[4] = (float)b.y; t[5] = (float)b.z;
+        t[6] = (float)c.x; t[7] = (float)c.y; t[8] = (float)c.z;
     }
     __syncthreads();
     const uint32_t n = 9u * ((L - r0) < (uint32_t)kBlock ? (L - r0) : (uint32_t)kBlock);
@@ -1416,7 +1579,7 @@ int reduce_levels(const Pool& P)
 
 uint32_t reduce_groups(const Pool& P) { return P.W >> reduce_levels(P); }
 
-size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
+size_t workspace_layout(int32_t H, int32_t D, int32_t f64, Pool* P, char* base)
 {
     const uint64_t cap = 1ull << D;
     const uint64_t W = cap / 32;
@@ -1428,11 +1591,12 @@ size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
         return o;
     };
     const size_t o_id = take(8 * cap), o_link = take(16 * cap), o_fwd = take(16 * cap);
-    const size_t o_world = take(48 * cap), o_cmd = take(4 * cap);
+    const size_t vrec = f64 ? 3 * sizeof(double4) : 3 * sizeof(float4);   // one vertex-cache record
+    const size_t o_world = take(vrec * cap), o_cmd = take(4 * cap);
     const size_t o_bits = take(4 * W), o_tree = take(4 * TW), o_live = take(4 * cap);
     const size_t o_free = take(4 * cap), o_list = take(8 * cap), o_lpre = take(4 * cap), o_lcnt = take(4 * (size_t)kMaxRankGroups);
     const size_t o_part = take(sizeof(uint2) * kMaxRankGroups), o_ctr = take(sizeof(Counters));
-    const size_t o_root = take(36 * (size_t)H);
+    const size_t o_root = take((f64 ? 72 : 36) * (size_t)H);
     if (P) {
         P->id = reinterpret_cast<uint64_t*>(base + o_id);
         P->link = reinterpret_cast<int4*>(base + o_link);
@@ -1453,6 +1617,7 @@ size_t workspace_layout(int32_t H, int32_t D, Pool* P, char* base)
         P->H = H;
         P->cap = (uint32_t)cap;
         P->W = (uint32_t)W;
+        P->f64 = f64 ? 1 : 0;
     }
     return off;
 }
@@ -1461,6 +1626,7 @@ Launch single_launch(const Pool& P, const LodK& K, const uint8_t* inj)
 {
     Launch X{};
     X.batched = false;
+    X.f64 = P.f64 != 0;
     X.one.P = P;
     X.one.K = K;
     X.one.inj = inj;
@@ -1488,7 +1654,7 @@ static hipError_t enumerate_seq(const Launch& X, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool kB>
+template <bool kB, typename R>
 static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* ev)
 {
     const dim3 g(X.grid_rank), b(kBlock), gw(X.grid_word), gi(X.n_inst);
@@ -1502,7 +1668,7 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL(k_enumerate<kB>, gw, b, 0, s, X.B, X.one);
     mark(kEnum, false);
     mark(kClass, true);
-    hipLaunchKernelGGL(k_classify<kB>, g, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL((k_classify<kB, R>), g, b, 0, s, X.B, X.one);
     mark(kClass, false);
     mark(kVote, true);
     hipLaunchKernelGGL(k_vote<kB>, g, b, 0, s, X.B, X.one);
@@ -1524,7 +1690,7 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL(k_freelist<kB>, gw, b, 0, s, X.B, X.one);
     mark(kFree, false);
     mark(kFill, true);
-    hipLaunchKernelGGL(k_fill<kB>, g, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL((k_fill<kB, R>), g, b, 0, s, X.B, X.one);
     mark(kFill, false);
     mark(kResolve, true);
     hipLaunchKernelGGL(k_resolve<kB>, g, b, 0, s, X.B, X.one);
@@ -1538,7 +1704,8 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
 
 hipError_t launch_frame(const Launch& X, hipStream_t s, const StageEvents* ev)
 {
-    return X.batched ? frame_seq<true>(X, s, ev) : frame_seq<false>(X, s, ev);
+    if (X.f64) return X.batched ? frame_seq<true, double>(X, s, ev) : frame_seq<false, double>(X, s, ev);
+    return X.batched ? frame_seq<true, float>(X, s, ev) : frame_seq<false, float>(X, s, ev);
 }
 
 hipError_t launch_reduce(const Launch& X, hipStream_t s)
@@ -1555,14 +1722,22 @@ hipError_t launch_refresh(const Launch& X, hipStream_t s)
 {
     hipError_t e = launch_enumerate(X, s);
     if (e != hipSuccess) return e;
-    if (X.batched) hipLaunchKernelGGL(k_refresh<true>, dim3(X.grid_rank), dim3(kBlock), 0, s, X.B, X.one);
-    else hipLaunchKernelGGL(k_refresh<false>, dim3(X.grid_rank), dim3(kBlock), 0, s, X.B, X.one);
+    const dim3 g(X.grid_rank), b(kBlock);
+    if (X.f64) {
+        if (X.batched) hipLaunchKernelGGL((k_refresh<true, double>), g, b, 0, s, X.B, X.one);
+        else hipLaunchKernelGGL((k_refresh<false, double>), g, b, 0, s, X.B, X.one);
+    } else {
+        if (X.batched) hipLaunchKernelGGL((k_refresh<true, float>), g, b, 0, s, X.B, X.one);
+        else hipLaunchKernelGGL((k_refresh<false, float>), g, b, 0, s, X.B, X.one);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_export_triangles(const Pool& P, uint32_t L, float* out9, hipStream_t s)
 {
-    if (L) hipLaunchKernelGGL(k_export_triangles, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out9);
+    if (!L) return hipGetLastError();
+    if (P.f64) hipLaunchKernelGGL(k_export_triangles<double>, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out9);
+    else hipLaunchKernelGGL(k_export_triangles<float>, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out9);
     return hipGetLastError();
 }
 
@@ -1593,7 +1768,19 @@ hipError_t launch_gather_links(const Pool& P, uint32_t r0, uint32_t n, int32_t* 
 
 hipError_t launch_gather_vertices(const Pool& P, uint32_t r0, uint32_t n, float* out9, hipStream_t s)
 {
-    if (n) hipLaunchKernelGGL(k_gather_vertices, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, P, r0, n, out9);
+    if (!n) return hipGetLastError();
+    const dim3 g(cdiv(n, kBlock)), b(kBlock);
+    if (P.f64) hipLaunchKernelGGL((k_gather_vertices<double, float>), g, b, 0, s, P, r0, n, out9);
+    else hipLaunchKernelGGL((k_gather_vertices<float, float>), g, b, 0, s, P, r0, n, out9);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_vertices64(const Pool& P, uint32_t r0, uint32_t n, double* out9, hipStream_t s)
+{
+    if (!n) return hipGetLastError();
+    const dim3 g(cdiv(n, kBlock)), b(kBlock);
+    if (P.f64) hipLaunchKernelGGL((k_gather_vertices<double, double>), g, b, 0, s, P, r0, n, out9);
+    else hipLaunchKernelGGL((k_gather_vertices<float, double>), g, b, 0, s, P, r0, n, out9);
     return hipGetLastError();
 }
 

@@ -96,6 +96,23 @@ def test_workspace_follows_paper_memory_model():
     assert ours >= (1 << D) * per_block + cbt_bytes
     assert ours <= (1 << D) * per_block + cbt_bytes + 64 * 1024
     assert cbt_bytes < (1 << (D + 1)) * 4
+    # binary64 instances: the vertex record doubles to 96 bytes and the root
+    # triangles to 72 bytes per halfedge
+    ours64 = cbt.workspace_bytes(60, D, precision=64)
+    assert (1 << D) * 48 + 60 * 36 - 256 <= ours64 - ours <= (1 << D) * 48 + 60 * 36 + 256
+
+
+def test_init_flags_checked():
+    lib = _lib()
+    assert lib.cbt_workspace_bytes_ex(12, 8, 0) == lib.cbt_workspace_bytes(12, 8)
+    assert lib.cbt_workspace_bytes_ex(12, 8, 2) == 0          # unknown flag
+    mesh = we1_mesh()
+    arrays = [np.ascontiguousarray(a, np.int32) for a in (mesh.twin, mesh.next, mesh.prev, mesh.vert)]
+    pos = np.ascontiguousarray(mesh.pos, np.float32)
+    m = cbt.Mesh(mesh.H, *(cbt._ptr(a) for a in arrays), int(pos.shape[0]), cbt._ptr(pos))
+    h = C.c_void_p()
+    st = lib.cbt_init_ex(C.byref(m), 8, 6, C.c_void_p(0x100000), 1 << 40, None, C.byref(h))
+    assert st == -1 and b"flags" in lib.cbt_last_error(None)
 
 
 def test_status_strings():

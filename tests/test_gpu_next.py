@@ -78,3 +78,30 @@ def test_converge_matches_reference(name, cam_index, depth):
     again = inst.update(cam, stats=True)
     assert again["allocations"] == 0 and again["frees"] == 0
     inst.close()
+
+
+def test_area_criterion_lockstep():
+    """The projected-area criterion (49 px^2 target, merge below a quarter
+    of it) frame by frame against the reference: states, trees, decisions
+    and the frame constants."""
+    import dataclasses
+    w = I.workload("planet", frames=256, table_res=64)
+    lod = dataclasses.replace(w.lod, split_px=49.0, merge_px=12.25, criterion=I.CRIT_AREA)
+    D = 18
+    inst = cbt.Instance(w.mesh, D, lod)
+    orc = Oracle(w.mesh, D, lod)
+    for f, cam in enumerate(w.cameras[:60:3]):
+        assert np.array_equal(inst.frame_constants(cam)[12:], orc.frame_constants(cam)[12:])
+        gst = inst.update(cam, stats=True)
+        ost = orc.frame(camera=cam)
+        gdec = inst.decisions()
+        odec = orc.decisions()[0]
+        was_live = gdec != 255
+        assert was_live.sum() == ost.live_before
+        assert np.array_equal(gdec[was_live], odec[was_live]), f"area frame {f}: decisions differ"
+        assert gst["allocations"] == ost.allocations and gst["live_after"] == ost.live_after
+        assert_same_state(inst, orc, f"area frame {f}")
+    assert_same_tree(inst, orc, "area")
+    log(f"[area] live {inst.live_count()}")
+    assert inst.live_count() > 10 * w.mesh.H
+    inst.close()
