@@ -160,6 +160,10 @@ def run_single(args) -> dict:
 
     updates = sum(s["live_before"] for s in stats)
     value = updates / elapsed
+    traffic = args.traffic
+    if traffic is None and args.precision == 32 and args.workload == "terrain":
+        from paper_2407_02215_amd import traffic as T
+        traffic = T.lookup(args.stage, args.warmup, args.steps)
     vb = 96 if args.precision == 64 else 48
     alg = sum(algorithmic_bytes(args.stage, s, vb) for s in stats) / len(stats)
     mean_ms = stage_ms / max(1, launches)
@@ -183,7 +187,7 @@ def run_single(args) -> dict:
         "latency_ms": {"p50": percentile(frame_ms, 50), "p99": percentile(frame_ms, 99),
                        "what": "GPU time of one whole update, HIP events"},
         "roofline": {"bound": "hbm", "kernel": args.stage, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": args.traffic,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
                      "mean_launch_ms": mean_ms, "alg_bytes_per_launch": alg},
     }
     inst.close()
@@ -367,7 +371,8 @@ def main():
                     help="vertices, world positions and size test in binary32 or binary64 (single mode)")
     ap.add_argument("--stage", default="fill", choices=["classify", "fill", "resolve", "frame"])
     ap.add_argument("--traffic", type=float, default=None,
-                    help="HBM bytes per launch of the profiled stage from the byte counters, if measured")
+                    help="HBM bytes per launch of the profiled stage from the byte counters; by default "
+                         "the value paper_2407_02215_amd/traffic.py recorded for this kernel source")
     ap.add_argument("--instances", type=int, default=None)
     ap.add_argument("--meshes", type=int, default=32)
     ap.add_argument("--rate", type=float, default=2000.0)

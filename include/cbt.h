@@ -240,6 +240,22 @@ cbt_status cbt_snapshot(cbt_handle h, uint64_t* heap_id, int32_t* twin, int32_t*
 cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twin,
                        const int32_t* next, const int32_t* prev);
 
+/* Compact state transfer: the live bisectors only, in rank order, as 6
+ * uint32 each (block, heap ID low, heap ID high, twin, next, prev), 24 bytes
+ * per live bisector instead of a 2^D-entry snapshot.  cbt_export_live
+ * writes them to the DEVICE array records of capacity entries (count
+ * receives the live count; CBT_E_CAPACITY, nothing written, when it
+ * exceeds capacity); it synchronises once to read the count, the copy
+ * itself is asynchronous on the handle's stream.  cbt_import_live replaces
+ * the handle's state by count records (a DEVICE array, or a HOST array when
+ * on_host is non-zero) exported from an instance of the same mesh and
+ * depth: the pool is cleared, the records scattered to their blocks, the
+ * bitfield, the sum-reduction tree and the vertex cache rebuilt.  A block
+ * or pointer out of range is reported as CBT_E_DEVICE (the handle is then
+ * failed).  Synchronises the stream. */
+cbt_status cbt_export_live(cbt_handle h, uint32_t* records, int64_t capacity, int64_t* count);
+cbt_status cbt_import_live(cbt_handle h, const uint32_t* records, int64_t count, int32_t on_host);
+
 /* LOD constants the device uses for a camera, evaluated once per frame in
  * double precision and rounded to float: cam[3] right[3] up[3] fwd[3] f^2
  * split_px^2 merge_px^2 tan_x tan_y znear (18 floats). */
@@ -332,8 +348,11 @@ cbt_status cbt_batch_destroy(cbt_batch b);
  *    workspaces (cbt_workspace_bytes each) are carved from the rest, up to
  *    memory_budget bytes.  An instance is admitted when its workspace fits;
  *    otherwise idle instances (none queued, none in flight) are evicted,
- *    least recently used first, to host snapshots and re-admitted (restored)
- *    when a request for them arrives.  The server creates its own streams
+ *    least recently used first: their live records (cbt_export_live, 24
+ *    bytes per live bisector) stay in the arena's top end and the workspace
+ *    is released; when even the records do not fit, the oldest records move
+ *    to host memory.  A request for an evicted instance re-admits it
+ *    (cbt_init + cbt_import_live).  The server creates its own streams
  *    (default priority) and pinned host staging.
  *  - Latency of a request: from cbt_server_submit to the poll that observes
  *    its batch finished (host steady clock); queue_ms up to its launch.
@@ -362,7 +381,8 @@ typedef struct {
     int64_t instances, resident, queued, in_flight;
     int64_t requests, admissions, evictions, batches, frames;
     int64_t bisector_updates;   /* sum of live counts over served frames */
-    int64_t bytes_resident, bytes_budget;
+    int64_t bytes_resident, bytes_budget;   /* arena bytes in use (workspaces and records) */
+    int64_t host_snapshots;                 /* evictions whose records went to host memory */
 } cbt_server_stats;
 
 size_t cbt_server_overhead_bytes(const cbt_server_config* cfg);   /* 0: invalid cfg */

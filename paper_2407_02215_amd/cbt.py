@@ -25,7 +25,7 @@ EXPORTED = ["cbt_workspace_bytes", "cbt_init", "cbt_update", "cbt_update_with_de
             "cbt_destroy", "cbt_status_string", "cbt_last_error", "cbt_time_stage", "cbt_stage_time",
             "cbt_set_schedule", "cbt_get_schedule", "cbt_stage_times", "cbt_batch_workspace_bytes", "cbt_batch_create",
             "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
-            "cbt_export_triangles", "cbt_workspace_bytes_ex", "cbt_init_ex"]
+            "cbt_export_triangles", "cbt_workspace_bytes_ex", "cbt_init_ex", "cbt_export_live", "cbt_import_live"]
 
 INIT_FP64 = 1
 
@@ -99,6 +99,8 @@ def load_library():
     lib.cbt_update_converge.argtypes = [vp, C.POINTER(Camera), C.POINTER(LodParams), C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(FrameStats)]
     lib.cbt_export_triangles.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.cbt_export_live.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.cbt_import_live.argtypes = [vp, vp, C.c_int64, C.c_int32]
     lib.cbt_set_schedule.argtypes = [vp, C.c_int32, C.c_int32]
     lib.cbt_get_schedule.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.cbt_batch_workspace_bytes.argtypes = [vp, C.c_int32]
@@ -115,7 +117,7 @@ def load_library():
               "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count", "cbt_destroy",
               "cbt_time_stage", "cbt_stage_time", "cbt_stage_times", "cbt_set_schedule", "cbt_get_schedule", "cbt_batch_create",
               "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
-              "cbt_export_triangles", "cbt_init_ex"):
+              "cbt_export_triangles", "cbt_init_ex", "cbt_export_live", "cbt_import_live"):
         getattr(lib, f).restype = C.c_int32
     _LIB = lib
     return lib
@@ -256,6 +258,28 @@ class Instance:
             out = torch.empty((max(1, int(n.value)), 3, 3), dtype=torch.float32, device=self.device)
         self._check(self.lib.cbt_export_triangles(self.h, C.c_void_p(out.data_ptr()), out.shape[0], C.byref(n)))
         return out[:int(n.value)]
+
+    def export_live(self):
+        """The live bisectors' records (block, id low, id high, twin, next,
+        prev) in rank order, as a device int32 tensor of shape (L, 6)."""
+        torch = self._torch
+        n = C.c_int64()
+        st = self.lib.cbt_export_live(self.h, None, 0, C.byref(n))
+        if st not in (CBT_OK, -4):
+            self._check(st)
+        out = torch.empty((max(1, int(n.value)), 6), dtype=torch.int32, device=self.device)
+        self._check(self.lib.cbt_export_live(self.h, C.c_void_p(out.data_ptr()), out.shape[0], C.byref(n)))
+        return out[:int(n.value)]
+
+    def import_live(self, records):
+        """Replaces the state by records from export_live (a device tensor,
+        or a host numpy array of shape (n, 6))."""
+        if isinstance(records, np.ndarray):
+            r = np.ascontiguousarray(records).view(np.uint32)
+            self._check(self.lib.cbt_import_live(self.h, _ptr(r), int(r.shape[0]), 1))
+        else:
+            r = records.contiguous()
+            self._check(self.lib.cbt_import_live(self.h, C.c_void_p(r.data_ptr()), int(r.shape[0]), 0))
 
     def update_with_decisions(self, decisions, stats: bool = False):
         torch = self._torch
@@ -462,7 +486,7 @@ class Completion(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "instances", "resident", "queued", "in_flight", "requests", "admissions", "evictions", "batches", "frames",
-        "bisector_updates", "bytes_resident", "bytes_budget")]
+        "bisector_updates", "bytes_resident", "bytes_budget", "host_snapshots")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -703,6 +703,54 @@ cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twi
     return CBT_OK;
 }
 
+cbt_status cbt_export_live(cbt_handle h, uint32_t* records, int64_t capacity, int64_t* count)
+{
+    if (!h || !count) return fail(h, CBT_E_ARG, "NULL argument");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    const Pool& P = h->P;
+    HIP_TRY(h, cbtk::launch_enumerate(cbtk::single_launch(P, h->wk, nullptr), h->stream), "enumerate");
+    cbt_status st = read_counters(h);
+    if (st) return st;
+    const uint32_t L = h->hctr->L;
+    *count = L;
+    if (capacity < (int64_t)L) return fail(h, CBT_E_CAPACITY, "capacity %lld < %u live bisectors", (long long)capacity, L);
+    if (!records) return fail(h, CBT_E_ARG, "NULL records");
+    HIP_TRY(h, cbtk::launch_export_live(P, L, records, h->stream), "export live records");
+    return CBT_OK;
+}
+
+cbt_status cbt_import_live(cbt_handle h, const uint32_t* records, int64_t count, int32_t on_host)
+{
+    if (!h || !records) return fail(h, CBT_E_ARG, "NULL argument");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    const Pool& P = h->P;
+    if (count < 1 || count > (int64_t)P.cap) return fail(h, CBT_E_ARG, "record count %lld outside [1, 2^D]", (long long)count);
+    hipStream_t s = h->stream;
+    HIP_TRY(h, hipMemsetAsync(P.id, 0, sizeof(uint64_t) * P.cap, s), "clear IDs");
+    HIP_TRY(h, hipMemsetAsync(P.link, 0, sizeof(int4) * P.cap, s), "clear pointers");
+    HIP_TRY(h, hipMemsetAsync(P.fwd, 0xff, sizeof(uint4) * P.cap, s), "clear forwarding");
+    if (on_host) {
+        size_t scratch_bytes;
+        uint32_t* scratch = reinterpret_cast<uint32_t*>(list_scratch(P, &scratch_bytes));
+        const uint32_t chunk = (uint32_t)(scratch_bytes / (6 * sizeof(uint32_t)));
+        for (int64_t r0 = 0; r0 < count; r0 += chunk) {
+            const uint32_t n = (uint32_t)((count - r0) < chunk ? (count - r0) : chunk);
+            HIP_TRY(h, hipMemcpyAsync(scratch, records + 6 * r0, sizeof(uint32_t) * 6 * n, hipMemcpyHostToDevice, s),
+                    "upload records");
+            HIP_TRY(h, cbtk::launch_import_live(P, n, scratch, s), "import live records");
+            HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+        }
+    } else {
+        HIP_TRY(h, cbtk::launch_import_live(P, (uint32_t)count, records, s), "import live records");
+    }
+    const cbtk::Launch X = cbtk::single_launch(P, h->wk, nullptr);
+    HIP_TRY(h, cbtk::launch_bits_from_ids(P, s), "bitfield");
+    HIP_TRY(h, cbtk::launch_reduce(X, s), "sum reduction");
+    HIP_TRY(h, cbtk::launch_refresh(X, s), "vertex cache");
+    h->last_frame_valid = 0;
+    return read_counters(h);
+}
+
 cbt_status cbt_frame_constants(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod, float* out18)
 {
     if (!out18) return fail(h, CBT_E_ARG, "NULL output");

@@ -192,6 +192,11 @@ hipError_t launch_gather_vertices(const Pool& P, uint32_t r0, uint32_t n, float*
 hipError_t launch_gather_vertices64(const Pool& P, uint32_t r0, uint32_t n, double* out9, hipStream_t s);
 hipError_t launch_gather_decisions(const Pool& P, uint32_t L, uint8_t* out_per_slot, hipStream_t s);
 hipError_t launch_export_heap(const Pool& P, uint32_t* out, hipStream_t s);
+// live bisectors in rank order (after an enumeration) <-> packed records
+// (block, id low, id high, twin, next, prev); the import scatters into a
+// cleared pool and flags blocks or pointers out of range
+hipError_t launch_export_live(const Pool& P, uint32_t L, uint32_t* out6, hipStream_t s);
+hipError_t launch_import_live(const Pool& P, uint32_t n, const uint32_t* in6, hipStream_t s);
 // blocks [b0, b0+n) <-> packed records (id low, id high, twin, next, prev)
 hipError_t launch_export_records(const Pool& P, uint32_t b0, uint32_t n, uint32_t* out5, hipStream_t s);
 hipError_t launch_import_records(const Pool& P, uint32_t b0, uint32_t n, const uint32_t* in5, hipStream_t s);

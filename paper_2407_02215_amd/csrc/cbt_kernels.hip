@@ -59,8 +59,11 @@ namespace cbtk {
 // (all rows' loads in flight at once: these passes are bound by the latency
 // of the rank -> block -> command chain, not by bandwidth).
 constexpr int kClassRows = 2;   // LOD test: 48 bytes of vertices per rank
-constexpr int kRankRows = 8;    // budget: rank entry and command word
-constexpr int kOwnerRows = 4;   // owners: plus merge members
+// The rank-order scans (budget, owners) give each thread kSeg consecutive
+// ranks: one workgroup scan per kBlock * kSeg ranks, and the segment of
+// rank-list entries is one pair of 16-byte loads.  Rank chunks are whole
+// segments.
+constexpr int kSeg = 8;
 
 // ---------------------------------------------------------------------------
 // wave64 / workgroup scan primitives
@@ -138,6 +141,57 @@ __device__ __forceinline__ uint2 block_incl_scan_sat(uint2 v, uint2* sh, uint2* 
     return sat_add2(pre, inc);
 }
 
+// exclusive saturating scan of pairs; sh holds >= 4 uint2
+__device__ __forceinline__ uint2 block_excl_scan_sat(uint2 v, uint2* sh, uint2* total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint2 inc = wave_incl_scan_sat(v);
+    if (lane == 63) sh[w] = inc;
+    uint2 ex = make_uint2(__shfl_up(inc.x, 1, 64), __shfl_up(inc.y, 1, 64));
+    if (lane == 0) ex = make_uint2(0, 0);
+    __syncthreads();
+    uint2 pre = make_uint2(0, 0), tot = make_uint2(0, 0);
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+        const uint2 t = sh[i];
+        if (i < w) pre = sat_add2(pre, t);
+        tot = sat_add2(tot, t);
+    }
+    __syncthreads();
+    *total = tot;
+    return sat_add2(pre, ex);
+}
+
+// exclusive scan of pairs (plain sums); sh holds >= 4 uint2
+__device__ __forceinline__ uint2 block_excl_scan2(uint2 v, uint2* sh, uint2* total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint2 inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t tx = __shfl_up(inc.x, o, 64), ty = __shfl_up(inc.y, o, 64);
+        if (lane >= o) inc = make_uint2(inc.x + tx, inc.y + ty);
+    }
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    uint2 pre = make_uint2(0, 0), tot = make_uint2(0, 0);
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+        const uint2 t = sh[i];
+        if (i < w) pre = make_uint2(pre.x + t.x, pre.y + t.y);
+        tot = make_uint2(tot.x + t.x, tot.y + t.y);
+    }
+    __syncthreads();
+    *total = tot;
+    return make_uint2(pre.x + inc.x - v.x, pre.y + inc.y - v.y);
+}
+
+// set lanes of a wave mask below this lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* sh)
 {
     uint32_t t;
@@ -191,25 +245,21 @@ __device__ __forceinline__ void pick_inst(const Batch& B, const Inst& one, Pool&
     else P = one.P;
 }
 
-// ranks of workgroup blk: a contiguous chunk of ceil(L / G)
+// ranks per rank workgroup: ceil(L / G) rounded up to whole segments
+__device__ __forceinline__ uint32_t rank_chunk(uint32_t L, uint32_t G)
+{
+    const uint32_t c = (L + G - 1) / G;
+    return (c + kSeg - 1) / kSeg * kSeg;
+}
+
+// ranks of workgroup blk: a contiguous chunk
 __device__ __forceinline__ void rank_range(uint32_t L, uint32_t G, uint32_t blk, uint32_t* r0, uint32_t* r1)
 {
-    const uint32_t chunk = (L + G - 1) / G;
+    const uint32_t chunk = rank_chunk(L, G);
     const uint64_t a = (uint64_t)blk * chunk;
     const uint64_t b = a + chunk;
     *r0 = (uint32_t)(a < L ? a : L);
     *r1 = (uint32_t)(b < L ? b : L);
-}
-
-// Appends the flagged lanes' values to this workgroup's list (rank order
-// kept); n is the running length, updated for the whole workgroup.
-__device__ __forceinline__ void list_append(const Pool& P, uint32_t r0, uint32_t* n, bool flag, uint2 value,
-                                            uint32_t* sh)
-{
-    uint32_t tot;
-    const uint32_t at = block_excl_scan(flag ? 1u : 0u, sh, &tot);
-    if (flag) P.list[r0 + *n + at] = value;
-    *n += tot;
 }
 
 // The lists of all rank workgroups form one list in rank order.  Consumers
@@ -248,7 +298,7 @@ __device__ __forceinline__ ListShare list_share(const Pool& P, uint32_t blk, uin
     ListShare s;
     s.i0 = (uint32_t)(a < tot ? a : tot);
     s.i1 = (uint32_t)(b < tot ? b : tot);
-    s.chunk = (P.ctr->L + G - 1) / G;
+    s.chunk = rank_chunk(P.ctr->L, G);
     return s;
 }
 
@@ -265,6 +315,23 @@ __device__ __forceinline__ uint32_t list_at(const uint32_t* base, uint32_t G, ui
     }
     *w = lo;
     return lo * chunk + (i - base[lo]);
+}
+
+// block numbers of ranks [t0, t0 + kSeg); t0 is a multiple of kSeg below
+// the pool size, so the two 16-byte loads stay inside the rank list; ranks
+// from r1 on read as block 0 (in bounds, unused)
+__device__ __forceinline__ void load_seg(const Pool& P, uint32_t t0, uint32_t r1, uint32_t (&s)[kSeg])
+{
+    static_assert(kSeg == 8, "two 16-byte loads per segment");
+    uint4 a = make_uint4(0, 0, 0, 0), b = a;
+    if (t0 < r1) {
+        const uint4* p = reinterpret_cast<const uint4*>(P.live + t0);
+        a = p[0];
+        b = p[1];
+    }
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) s[j] = t0 + j < r1 ? v[j] : 0u;
 }
 
 __device__ __forceinline__ int ilog2_64(uint64_t x) { return 63 - __clzll((long long)x); }
@@ -378,12 +445,33 @@ __device__ __forceinline__ double abs_r(double x) { return fabs(x); }
 __device__ __forceinline__ float sqrt_r(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return __builtin_sqrt(x); }
 
-// depth / parity ride in the w components: bit patterns in binary32,
-// exact values in binary64
-__device__ __forceinline__ float4 make4(Vec3<float> v, int w) { return make_float4(v.x, v.y, v.z, __int_as_float(w)); }
-__device__ __forceinline__ double4 make4(Vec3<double> v, int w) { return make_double4(v.x, v.y, v.z, (double)w); }
+// The w components of a vertex record carry the subdivision depth (first
+// vertex) and the heap ID (binary32: low and high words in the second and
+// third vertices; binary64: the whole ID in the second), as raw bits that
+// are only ever moved, never computed with.
+__device__ __forceinline__ float4 make4(Vec3<float> v, uint32_t w) { return make_float4(v.x, v.y, v.z, __uint_as_float(w)); }
+__device__ __forceinline__ double4 make4(Vec3<double> v, uint64_t w)
+{
+    return make_double4(v.x, v.y, v.z, __longlong_as_double((long long)w));
+}
 __device__ __forceinline__ int w_int(float w) { return __float_as_int(w); }
-__device__ __forceinline__ int w_int(double w) { return (int)w; }
+__device__ __forceinline__ int w_int(double w) { return (int)__double_as_longlong(w); }
+
+template <typename R> struct RecId;
+template <> struct RecId<float> {
+    static __device__ __forceinline__ uint64_t get(const float4& b, const float4& c)
+    {
+        return (uint64_t)__float_as_uint(b.w) | ((uint64_t)__float_as_uint(c.w) << 32);
+    }
+    static __device__ __forceinline__ uint32_t low(const float4& b) { return __float_as_uint(b.w); }
+};
+template <> struct RecId<double> {
+    static __device__ __forceinline__ uint64_t get(const double4& b, const double4&)
+    {
+        return (uint64_t)__double_as_longlong(b.w);
+    }
+    static __device__ __forceinline__ uint32_t low(const double4& b) { return (uint32_t)__double_as_longlong(b.w); }
+};
 
 template <typename R>
 __device__ __forceinline__ Vec3<R> ld3(const T4<R>& v) { return {v.x, v.y, v.z}; }
@@ -561,15 +649,28 @@ __device__ __forceinline__ uint32_t lod_decide(const LodK& K, Vec3<R> p0, Vec3<R
 }
 
 // vertex-cache record of block s: world positions of the three vertices,
-// the depth and the heap-ID parity
+// the depth and the heap ID
+__device__ __forceinline__ void store_rec(float4* w, Vec3<float> pa, Vec3<float> pb, Vec3<float> pc, int depth,
+                                          uint64_t id)
+{
+    w[0] = make4(pa, (uint32_t)depth);
+    w[1] = make4(pb, (uint32_t)id);
+    w[2] = make4(pc, (uint32_t)(id >> 32));
+}
+
+__device__ __forceinline__ void store_rec(double4* w, Vec3<double> pa, Vec3<double> pb, Vec3<double> pc, int depth,
+                                          uint64_t id)
+{
+    w[0] = make4(pa, (uint64_t)depth);
+    w[1] = make4(pb, id);
+    w[2] = make4(pc, (uint64_t)0);
+}
+
 template <typename R>
 __device__ __forceinline__ void store_world(const Pool& P, uint32_t s, Vec3<R> pa, Vec3<R> pb, Vec3<R> pc, int depth,
-                                            int parity)
+                                            uint64_t id)
 {
-    T4<R>* w = world_rec<R>(P, s);
-    w[0] = make4(pa, depth);
-    w[1] = make4(pb, parity);
-    w[2] = make4(pc, 0);
+    store_rec(world_rec<R>(P, s), pa, pb, pc, depth, id);
 }
 
 // ---------------------------------------------------------------------------
@@ -577,10 +678,15 @@ __device__ __forceinline__ void store_world(const Pool& P, uint32_t s, Vec3<R> p
 // positions, the depth and the parity, so no heap ID is read)
 // ---------------------------------------------------------------------------
 
+// The even MERGE members are listed (block, depth) per workgroup in (tile,
+// wave, row, lane) order: wave ballots place them, one barrier per tile
+// exchanges the waves' counts (the vote does not depend on the order within
+// the list).
 template <bool kB, typename R>
 __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
+    __shared__ uint32_t wcnt[2][kBlock / 64];
     Pool P;
     LodK K;
     const uint8_t* inj;
@@ -588,11 +694,13 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
     uint32_t r0, r1;
     rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     const int maxd = 63 - P.k;
-    uint32_t nsplit = 0, nmerge = 0, scost = 0, nlist = 0;
-    for (uint32_t base = r0; base < r1; base += kBlock * kClassRows) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t nsplit = 0, nmerge = 0, scost = 0, nlist = 0, tile = 0;
+    for (uint32_t base = r0; base < r1; base += kBlock * kClassRows, ++tile) {
         // every row's loads in flight before the first row is processed
-        uint32_t sr[kClassRows];
+        uint32_t sr[kClassRows], dr[kClassRows];
         T4<R> wa[kClassRows], wb[kClassRows], wc[kClassRows];
+        bool cand[kClassRows];
 #pragma unroll
         for (int j = 0; j < kClassRows; ++j) {
             const uint32_t r = base + j * kBlock + threadIdx.x;
@@ -608,40 +716,61 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
         }
 #pragma unroll
         for (int j = 0; j < kClassRows; ++j) {
-            if (base + j * kBlock >= r1) continue;   // uniform: rows past the chunk
+            cand[j] = false;
+            dr[j] = 0;
             const uint32_t r = base + j * kBlock + threadIdx.x;
+            if (r >= r1) continue;
             const uint32_t s = sr[j];
-            bool cand = false;
-            if (r < r1) {
-                const int d = w_int(wa[j].w);
-                uint32_t dec;
-                if (inj) {
-                    dec = inj[s];
-                    if (dec > kMerge) {
-                        raise_err(P, kErrDecision);
-                        dec = kKeep;
-                    }
-                } else {
-                    dec = lod_decide<R>(K, ld3<R>(wa[j]), ld3<R>(wb[j]), ld3<R>(wc[j]));
-                }
-                if (dec == kMerge && d == 0) dec = kKeep;       // roots never merge
-                if (dec == kSplit && d + 1 > maxd) dec = kKeep; // index width
-                if ((uint32_t)d > 63u) {
-                    raise_err(P, kErrPointer);
+            const int d = w_int(wa[j].w);
+            dr[j] = (uint32_t)d;
+            uint32_t dec;
+            if (inj) {
+                dec = inj[s];
+                if (dec > kMerge) {
+                    raise_err(P, kErrDecision);
                     dec = kKeep;
                 }
-                P.cmd[s] = dec | ((uint32_t)d << kDepthShift);
-                if (dec == kSplit) {
-                    ++nsplit;
-                    scost += 3u * (uint32_t)d + 4u;
-                } else if (dec == kMerge) {
-                    ++nmerge;
-                    // configurations are found from their even members (Alg. 4)
-                    cand = w_int(wb[j].w) == 0;
-                }
+            } else {
+                dec = lod_decide<R>(K, ld3<R>(wa[j]), ld3<R>(wb[j]), ld3<R>(wc[j]));
             }
-            list_append(P, r0, &nlist, cand, make_uint2(s, 0), sh);
+            if (dec == kMerge && d == 0) dec = kKeep;       // roots never merge
+            if (dec == kSplit && d + 1 > maxd) dec = kKeep; // index width
+            if ((uint32_t)d > 63u) {
+                raise_err(P, kErrPointer);
+                dec = kKeep;
+            }
+            P.cmd[s] = dec | ((uint32_t)d << kDepthShift);
+            if (dec == kSplit) {
+                ++nsplit;
+                scost += 3u * (uint32_t)d + 4u;
+            } else if (dec == kMerge) {
+                ++nmerge;
+                // configurations are found from their even members (Alg. 4)
+                cand[j] = (RecId<R>::low(wb[j]) & 1u) == 0;
+            }
         }
+        uint64_t m[kClassRows];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kClassRows; ++j) {
+            m[j] = __ballot(cand[j]);
+            cnt += (uint32_t)__popcll(m[j]);
+        }
+        if (lane == 0) wcnt[tile & 1][wv] = cnt;
+        __syncthreads();
+        uint32_t at = r0 + nlist, ttot = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) {
+            const uint32_t t = wcnt[tile & 1][i];
+            at += i < wv ? t : 0u;
+            ttot += t;
+        }
+#pragma unroll
+        for (int j = 0; j < kClassRows; ++j) {
+            if (cand[j]) P.list[at + lanes_below(m[j])] = make_uint2(sr[j], dr[j]);
+            at += (uint32_t)__popcll(m[j]);
+        }
+        nlist += ttot;
     }
     const uint32_t a = block_sum(nsplit, sh);
     const uint32_t b = block_sum(nmerge, sh);
@@ -658,39 +787,38 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
 // kernel: merge configurations (list of even MERGE members)
 // ---------------------------------------------------------------------------
 
-// Alg. 4 seen from an even member c0 (depth >= 1): j2 = Next (its sibling),
-// j3 = Prev; a border pair when Prev is null, a cycle of four when j3 has
-// the same depth and j4 = Prev(j3) is j3's sibling.  The smallest ID of a
+// Alg. 4 seen from an even member c0 of depth d >= 1: j2 = Next (its
+// sibling), j3 = Prev; a border pair when Prev is null, a cycle of four when
+// j3 has depth d and j4 = Prev(j3) is j3's sibling.  Next of an even child
+// and Prev of an odd child cross their parent's interior edge, so in a
+// conforming triangulation a bisector of the same depth across them is the
+// sibling, and one of depth d across Prev of c0 (half of the parent's base
+// edge) is the odd child of the parent's twin: the depths in the members'
+// command words decide, without their heap IDs.  The smallest ID of a
 // configuration is always an even member (c0 < c1), so configurations are
-// detected, once, from their even members.
-// The loads of each level (sibling and Prev neighbour, then the fourth
-// member) are issued together; c2..c4 receive the members' command words.
-__device__ __forceinline__ int merge_config_even(const Pool& P, uint64_t id, int4 l1, int32_t* j2o, int32_t* j3o,
-                                                 int32_t* j4o, uint64_t* id4o, uint32_t* c2, uint32_t* c3,
-                                                 uint32_t* c4)
+// detected, once, from their even members.  The loads of each level are
+// issued together; c2..c4 receive the members' command words.
+__device__ __forceinline__ int merge_config_even(const Pool& P, int d, int4 l1, int32_t* j2o, int32_t* j3o,
+                                                 int32_t* j4o, uint32_t* c2, uint32_t* c3, uint32_t* c4)
 {
     const int32_t j2 = l1.y, j3 = l1.z;
     if ((j2 >= 0 && !slot_ok(P, j2)) || (j3 >= 0 && !slot_ok(P, j3))) { raise_err(P, kErrPointer); return 0; }
     if (j2 < 0) return 0;
     const uint32_t a3 = j3 >= 0 ? (uint32_t)j3 : 0u;   // in bounds either way
-    const uint64_t id2 = P.id[j2];
     const uint32_t cm2 = P.cmd[j2];
-    const uint64_t id3 = P.id[a3];
     const int32_t j4 = P.link[a3].z;
     const uint32_t cm3 = P.cmd[a3];
-    if ((id2 >> 1) != (id >> 1)) return 0;
+    if (depth_of_cmd(cm2) != d) return 0;
     *j2o = j2;
     *c2 = cm2;
     if (j3 < 0) return 2;
-    if (ilog2_64(id3) != ilog2_64(id)) return 0;
+    if (depth_of_cmd(cm3) != d) return 0;
     if (j4 < 0) return 0;
     if (!slot_ok(P, j4)) { raise_err(P, kErrPointer); return 0; }
-    const uint64_t id4 = P.id[j4];
     const uint32_t cm4 = P.cmd[j4];
-    if ((id4 >> 1) != (id3 >> 1)) return 0;
+    if (depth_of_cmd(cm4) != d) return 0;
     *j3o = j3;
     *j4o = j4;
-    *id4o = id4;
     *c3 = cm3;
     *c4 = cm4;
     return 4;
@@ -710,13 +838,12 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
     uint32_t ncfg = 0, res = 0, wres = 0xffffffffu;
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
         uint32_t w;
-        const uint32_t s = P.list[list_at(base, P.G, ls.chunk, i, &w)].x;
-        const uint64_t id = P.id[s];
+        const uint2 e = P.list[list_at(base, P.G, ls.chunk, i, &w)];   // (block, depth)
+        const uint32_t s = e.x;
         int32_t j2 = -1, j3 = -1, j4 = -1;
-        uint64_t id4 = 0;
         uint32_t c2 = 0, c3 = 0, c4 = 0;
-        const int m = merge_config_even(P, id, P.link[s], &j2, &j3, &j4, &id4, &c2, &c3, &c4);
-        if (!m || (m == 4 && id4 < id)) continue;   // not the smallest member
+        const int m = merge_config_even(P, (int)e.y, P.link[s], &j2, &j3, &j4, &c2, &c3, &c4);
+        if (!m || (m == 4 && P.id[j4] < P.id[s])) continue;   // not the smallest member
         bool ok = (c2 & kDecMask) == kMerge;
         if (m == 4) ok = ok && (c3 & kDecMask) == kMerge && (c4 & kDecMask) == kMerge;
         if (!ok) continue;
@@ -803,34 +930,41 @@ __global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
     const uint32_t F = P.ctr->F, Tm = P.ctr->Tm;
     uint2 carry = P.part[blk];
     uint32_t nm = 0, nlist = 0;
-    for (uint32_t base = r0; base < r1; base += kBlock * kRankRows) {
-        uint32_t sr[kRankRows], cr[kRankRows];
+    for (uint32_t base = r0; base < r1; base += kBlock * kSeg) {
+        const uint32_t t0 = base + threadIdx.x * kSeg;
+        uint32_t sr[kSeg], cr[kSeg];
+        load_seg(P, t0, r1, sr);
 #pragma unroll
-        for (int j = 0; j < kRankRows; ++j) {
-            const uint32_t r = base + j * kBlock + threadIdx.x;
-            sr[j] = r < r1 ? P.live[r] : 0u;
+        for (int j = 0; j < kSeg; ++j) cr[j] = t0 + j < r1 ? P.cmd[sr[j]] : 0u;
+        // reservations: (merge blocks, split blocks 3d + 4) per rank
+        uint2 v[kSeg];
+        uint2 loc = make_uint2(0, 0);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            const uint32_t c = cr[j];
+            v[j] = make_uint2((c & kMUnan) ? ((c & kMQuad) ? 2u : 1u) : 0u,
+                              (c & kDecMask) == kSplit ? 3u * (uint32_t)depth_of_cmd(c) + 4u : 0u);
+            loc = sat_add2(loc, v[j]);
         }
+        uint2 tot;
+        uint2 run = sat_add2(carry, block_excl_scan_sat(loc, sh2, &tot));
+        uint32_t acc = 0;   // bit j: the split reservation of rank t0 + j fits
 #pragma unroll
-        for (int j = 0; j < kRankRows; ++j) {
-            const uint32_t r = base + j * kBlock + threadIdx.x;
-            cr[j] = r < r1 ? P.cmd[sr[j]] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < kRankRows; ++j) {
-            if (base + j * kBlock >= r1) continue;   // uniform: rows past the chunk
-            const uint32_t s = sr[j], c = cr[j];
-            uint2 v = make_uint2(0, 0);
-            if (c & kMUnan) v.x = (c & kMQuad) ? 2u : 1u;
-            if ((c & kDecMask) == kSplit) v.y = 3u * (uint32_t)depth_of_cmd(c) + 4u;
-            uint2 tot;
-            const uint2 inc = sat_add2(carry, block_incl_scan_sat(v, sh2, &tot));
-            if (v.x && inc.x <= F) {
-                P.cmd[s] = c | kMAcc;
+        for (int j = 0; j < kSeg; ++j) {
+            run = sat_add2(run, v[j]);   // inclusive prefix at this rank
+            if (v[j].x && run.x <= F) {
+                P.cmd[sr[j]] = cr[j] | kMAcc;
                 ++nm;
             }
-            list_append(P, r0, &nlist, v.y && sat_add(Tm, inc.y) <= F, make_uint2(s, 0), sh);
-            carry = sat_add2(carry, tot);
+            if (v[j].y && sat_add(Tm, run.y) <= F) acc |= 1u << j;
         }
+        uint32_t ltot;
+        uint32_t at = r0 + nlist + block_excl_scan((uint32_t)__popc(acc), sh, &ltot);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j)
+            if ((acc >> j) & 1u) P.list[at++] = make_uint2(sr[j], 0);
+        nlist += ltot;
+        carry = sat_add2(carry, tot);
     }
     const uint32_t a = block_sum(nm, sh);
     if (threadIdx.x == 0) {
@@ -908,64 +1042,58 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
     uint32_t r0, r1;
     rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     uint32_t nexec = 0, nsc = 0, nfree = 0;
-    uint2 run = make_uint2(0, 0);   // (owners, outputs) of earlier iterations
-    for (uint32_t base = r0; base < r1; base += kBlock * kOwnerRows) {
-        // loads of every row in flight: rank entries, commands, then the
-        // members of accepted merges and their commands
-        uint32_t sr[kOwnerRows], cr[kOwnerRows];
-        uint4 mr[kOwnerRows];
-        bool marked[kOwnerRows];
+    uint2 run = make_uint2(0, 0);   // (owners, outputs) of earlier tiles
+    for (uint32_t base = r0; base < r1; base += kBlock * kSeg) {
+        const uint32_t t0 = base + threadIdx.x * kSeg;
+        // loads of the whole segment in flight together: rank entries,
+        // commands, then the members of accepted merges and their commands
+        uint32_t sr[kSeg], cr[kSeg];
+        uint4 mr[kSeg];
+        load_seg(P, t0, r1, sr);
 #pragma unroll
-        for (int j = 0; j < kOwnerRows; ++j) {
-            const uint32_t r = base + j * kBlock + threadIdx.x;
-            sr[j] = r < r1 ? P.live[r] : 0u;
-        }
+        for (int j = 0; j < kSeg; ++j) cr[j] = t0 + j < r1 ? P.cmd[sr[j]] : 0u;
 #pragma unroll
-        for (int j = 0; j < kOwnerRows; ++j) {
-            const uint32_t r = base + j * kBlock + threadIdx.x;
-            cr[j] = r < r1 ? P.cmd[sr[j]] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < kOwnerRows; ++j) {
+        for (int j = 0; j < kSeg; ++j) {
             const bool acc = !(cr[j] & kMarks) && (cr[j] & kMAcc);
             mr[j] = acc ? P.fwd[sr[j]] : make_uint4(0, 0, 0, 0);
         }
+        uint2 loc = make_uint2(0, 0);   // (owners, outputs) of this segment
 #pragma unroll
-        for (int j = 0; j < kOwnerRows; ++j) {
-            // splits win: a configuration with a split-marked member stays
-            bool any = false;
-            if (mr[j].w) {
-                any = (P.cmd[mr[j].x] & kMarks) != 0;
-                if (mr[j].w == 4) any = any || (P.cmd[mr[j].y] & kMarks) || (P.cmd[mr[j].z] & kMarks);
-            }
-            marked[j] = any;
-        }
-#pragma unroll
-        for (int j = 0; j < kOwnerRows; ++j) {
-            if (base + j * kBlock >= r1) continue;   // uniform: rows past the chunk
-            const uint32_t s = sr[j];
+        for (int j = 0; j < kSeg; ++j) {
             uint32_t c = cr[j], k = 0;
             if (c & kMarks) {
                 k = split_outputs(c);
                 ++nsc;
                 ++nfree;
-            } else if (mr[j].w && !marked[j]) {
-                c |= kMExec;
-                k = mr[j].w / 2;
-                ++nexec;
-                nfree += mr[j].w;
+            } else if (mr[j].w) {
+                // splits win: a configuration with a split-marked member stays
+                bool any = (P.cmd[mr[j].x] & kMarks) != 0;
+                if (mr[j].w == 4) any = any || (P.cmd[mr[j].y] & kMarks) || (P.cmd[mr[j].z] & kMarks);
+                if (!any) {
+                    c |= kMExec;
+                    k = mr[j].w / 2;
+                    ++nexec;
+                    nfree += mr[j].w;
+                }
             }
-            // owners before this one in the workgroup, and their outputs
-            const uint2 v = make_uint2(k ? 1u : 0u, k);
-            uint2 tot;
-            const uint2 inc = block_incl_scan_sat(v, sh2, &tot);
-            if (k) {
-                const uint32_t at = r0 + run.x + inc.x - 1u;
-                P.list[at] = make_uint2(s, c);
-                P.lpre[at] = run.y + inc.y - k;
-            }
-            run = make_uint2(run.x + tot.x, run.y + tot.y);
+            cr[j] = c;
+            mr[j].w = k;   // outputs of rank t0 + j
+            loc = make_uint2(loc.x + (k ? 1u : 0u), loc.y + k);
         }
+        uint2 tot;
+        const uint2 pre = block_excl_scan2(loc, sh2, &tot);
+        uint32_t at = r0 + run.x + pre.x, outs = run.y + pre.y;
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            const uint32_t k = mr[j].w;
+            if (k) {
+                P.list[at] = make_uint2(sr[j], cr[j]);
+                P.lpre[at] = outs;
+                ++at;
+                outs += k;
+            }
+        }
+        run = make_uint2(run.x + tot.x, run.y + tot.y);
     }
     const uint32_t a = block_sum(nexec, sh);
     const uint32_t b = block_sum(nsc, sh);
@@ -1038,96 +1166,108 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
 // keeps the other members (second, third, fourth fields) for the pointer
 // pass.
 
+// Blocks of a split bisector's outputs by role, from its command word and
+// its first position base in the free list (N blocks allocated); the
+// unused roles hold 0xffffffff.  False (and the allocation flag raised)
+// when the allocation does not hold them.
+__device__ __forceinline__ bool split_targets(const Pool& P, uint32_t c, uint32_t base, uint32_t N, uint4* f)
+{
+    const bool hn = c & kMarkN, hp = c & kMarkP;
+    const uint32_t cnt = 2u + (hn ? 1u : 0u) + (hp ? 1u : 0u);
+    if (base + cnt > N) { raise_err(P, kErrAlloc); return false; }
+    const uint32_t q0 = P.freel[base], q1 = P.freel[base + 1];
+    const uint32_t q2 = cnt > 2 ? P.freel[base + 2] : 0u, q3 = cnt > 3 ? P.freel[base + 3] : 0u;
+    if (q0 >= P.cap || q1 >= P.cap || q2 >= P.cap || q3 >= P.cap) { raise_err(P, kErrAlloc); return false; }
+    const uint32_t no = 0xffffffffu;
+    if (!hn && !hp) *f = make_uint4(q0, no, q1, no);          // 2x, 2x+1
+    else if (hn && !hp) *f = make_uint4(q0, no, q1, q2);      // 2x, 4x+2, 4x+3
+    else if (!hn && hp) *f = make_uint4(q1, q2, q0, no);      // 2x+1, 4x, 4x+1
+    else *f = make_uint4(q0, q1, q2, q3);                     // 4x .. 4x+3
+    return true;
+}
+
 template <typename R>
 __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_t s, uint32_t c, uint32_t base,
                                            uint32_t N)
 {
     using V = Vec3<R>;
     const bool hn = c & kMarkN, hp = c & kMarkP;
-    const uint32_t cnt = 2u + (hn ? 1u : 0u) + (hp ? 1u : 0u);
-    if (base + cnt > N) { raise_err(P, kErrAlloc); return; }
-    const uint32_t q0 = P.freel[base], q1 = P.freel[base + 1];
-    const uint32_t q2 = cnt > 2 ? P.freel[base + 2] : 0u, q3 = cnt > 3 ? P.freel[base + 3] : 0u;
-    if (q0 >= P.cap || q1 >= P.cap || q2 >= P.cap || q3 >= P.cap) { raise_err(P, kErrAlloc); return; }
+    uint4 f;
+    if (!split_targets(P, c, base, N, &f)) return;
     const int d = depth_of_cmd(c);
-    // flat vertices: the Alg. 2 decode of the heap ID (no memory beyond the
-    // ID and the root table); world positions: the cache
-    V v0, v1, v2;
-    decode<R>(P, P.id[s], d, v0, v1, v2);
+    // world positions and heap ID: the vertex record; flat vertices: the
+    // Alg. 2 decode of the ID (no memory beyond the root table)
     const T4<R>* wv = world_rec<R>(P, s);
-    const V w0 = ld3<R>(wv[0]), w1 = ld3<R>(wv[1]), w2 = ld3<R>(wv[2]);
+    const T4<R> ra = wv[0], rb = wv[1], rc = wv[2];
+    const uint64_t x = RecId<R>::get(rb, rc);
+    V v0, v1, v2;
+    decode<R>(P, x, d, v0, v1, v2);
+    const V w0 = ld3<R>(ra), w1 = ld3<R>(rb), w2 = ld3<R>(rc);
     const V m = mid3(v0, v1);
     const V wm = world<R>(K, m);
-    uint32_t r0q, r1q = 0xffffffffu, r2q, r3q = 0xffffffffu;
-    if (!hn && !hp) {          // 2x, 2x+1
-        r0q = q0; r2q = q1;
-    } else if (hn && !hp) {    // 2x, 4x+2, 4x+3
-        r0q = q0; r2q = q1; r3q = q2;
-    } else if (!hn && hp) {    // 2x+1, 4x, 4x+1
-        r2q = q0; r0q = q1; r1q = q2;
-    } else {                   // 4x .. 4x+3
-        r0q = q0; r1q = q1; r2q = q2; r3q = q3;
-    }
     // first child (v0, v2, m), or its children (v0, m, m0) and (m, v2, m0)
     if (!hp) {
-        store_world<R>(P, r0q, w0, w2, wm, d + 1, 0);
+        store_world<R>(P, f.x, w0, w2, wm, d + 1, 2 * x);
     } else {
         const V m0 = mid3(v0, v2);
         const V wm0 = world<R>(K, m0);
-        store_world<R>(P, r0q, w0, wm, wm0, d + 2, 0);
-        store_world<R>(P, r1q, wm, w2, wm0, d + 2, 1);
+        store_world<R>(P, f.x, w0, wm, wm0, d + 2, 4 * x);
+        store_world<R>(P, f.y, wm, w2, wm0, d + 2, 4 * x + 1);
     }
     // second child (v2, v1, m), or its children (v2, m, m1) and (m, v1, m1)
     if (!hn) {
-        store_world<R>(P, r2q, w2, w1, wm, d + 1, 1);
+        store_world<R>(P, f.z, w2, w1, wm, d + 1, 2 * x + 1);
     } else {
         const V m1 = mid3(v2, v1);
         const V wm1 = world<R>(K, m1);
-        store_world<R>(P, r2q, w2, wm, wm1, d + 2, 0);
-        store_world<R>(P, r3q, wm, w1, wm1, d + 2, 1);
+        store_world<R>(P, f.z, w2, wm, wm1, d + 2, 4 * x + 2);
+        store_world<R>(P, f.w, wm, w1, wm1, d + 2, 4 * x + 3);
     }
     P.link[s].w = (int)c;
-    P.fwd[s] = make_uint4(r0q, r1q, r2q, r3q);
+    P.fwd[s] = f;
 }
 
-// parent of the sibling pair (c0 even, c1 odd): vertices (c0.v0, c1.v1, c0.v1)
-template <typename R>
-__device__ __forceinline__ void fill_parent(const Pool& P, uint32_t q, int32_t c0, int32_t c1, int depth, int parity)
-{
-    const T4<R>* w0 = world_rec<R>(P, c0);
-    const T4<R>* w1 = world_rec<R>(P, c1);
-    T4<R>* wq = world_rec<R>(P, q);
-    const T4<R> a = w0[0], b = w1[1], c = w0[1];
-    wq[0] = make4(ld3<R>(a), depth);
-    wq[1] = make4(ld3<R>(b), parity);
-    wq[2] = make4(ld3<R>(c), 0);
-}
-
+// Merges: the parent of the sibling pair (c0 even, c1 odd) has vertices
+// (c0.v0, c1.v1, c0.v1) and heap ID c0 / 2, both read from the children's
+// vertex records.
 template <typename R>
 __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c, uint32_t base, uint32_t N)
 {
     const uint4 m = P.fwd[s];   // (sibling, other odd, other even, members)
-    const uint64_t ida = P.id[s] >> 1;
     const bool quad = m.w == 4;
     if (base + (quad ? 2u : 1u) > N) { raise_err(P, kErrAlloc); return; }
-    uint32_t qa = P.freel[base], qb = 0xffffffffu;
+    if (m.x >= P.cap || (quad && (m.y >= P.cap || m.z >= P.cap))) { raise_err(P, kErrPointer); return; }
+    const T4<R>* e0 = world_rec<R>(P, s);
+    const T4<R>* o0 = world_rec<R>(P, m.x);
+    const T4<R> a0 = e0[0], b0 = e0[1], c0 = e0[2], d0 = o0[1];
+    const uint64_t ida = RecId<R>::get(b0, c0) >> 1;
+    T4<R> a1 = a0, b1 = b0, c1 = c0, d1 = d0;
     uint64_t idb = 0;
     if (quad) {
+        const T4<R>* e1 = world_rec<R>(P, m.z);
+        const T4<R>* o1 = world_rec<R>(P, m.y);
+        a1 = e1[0];
+        b1 = e1[1];
+        c1 = e1[2];
+        d1 = o1[1];
+        idb = RecId<R>::get(b1, c1) >> 1;
+    }
+    uint32_t qa = P.freel[base], qb = 0xffffffffu;
+    if (quad) {
         const uint32_t q1 = P.freel[base + 1];
-        idb = P.id[m.z] >> 1;
         const bool a_first = ida < idb;
         qb = a_first ? q1 : qa;
         qa = a_first ? qa : q1;
     }
     if (qa >= P.cap || (quad && qb >= P.cap)) { raise_err(P, kErrAlloc); return; }
     const int dp = depth_of_cmd(c) - 1;
-    fill_parent<R>(P, qa, (int32_t)s, (int32_t)m.x, dp, (int)(ida & 1u));
+    store_world<R>(P, qa, ld3<R>(a0), ld3<R>(d0), ld3<R>(b0), dp, ida);
     P.link[s].w = (int)kMExec;
     P.fwd[s] = make_uint4(qa, m.x, m.y, m.z);
     P.link[m.x].w = (int)kMExec;
     P.fwd[m.x] = make_uint4(qa, 0, 0, 0);
     if (quad) {
-        fill_parent<R>(P, qb, (int32_t)m.z, (int32_t)m.y, dp, (int)(idb & 1u));
+        store_world<R>(P, qb, ld3<R>(a1), ld3<R>(d1), ld3<R>(b1), dp, idb);
         P.link[m.y].w = (int)kMExec;
         P.fwd[m.y] = make_uint4(qb, 0, 0, 0);
         P.link[m.z].w = (int)kMExec;
@@ -1260,13 +1400,14 @@ __device__ __forceinline__ void clear_bit(const Pool& P, uint32_t s)
     atomicAnd(&P.bits[s >> 5], ~(1u << (s & 31u)));
 }
 
-__device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t c)
+__device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t c, uint32_t base, uint32_t N)
 {
     const int db = depth_of_cmd(c);
     const bool hn = c & kMarkN, hp = c & kMarkP;
+    uint4 f;   // the outputs' blocks, from the free list as the fill took them
+    if (!split_targets(P, c, base, N, &f)) return;
     const uint64_t x = P.id[b];
     const int4 lb = P.link[b];
-    const uint4 f = P.fwd[b];
     const int32_t own[3] = {b, b, b};
     const int32_t across[3] = {lb.x, lb.y, lb.z};
     Nb nb[3];
@@ -1330,12 +1471,14 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
     Pool P;
     const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
     const ListShare ls = list_share(P, blk, base, sh);
+    const uint32_t N = P.ctr->N;
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
         uint32_t w;
-        const uint2 e = P.list[list_at(base, P.G, ls.chunk, i, &w)];
+        const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
+        const uint2 e = P.list[at];
         const int32_t b = (int32_t)e.x;
         const uint32_t c = e.y;
-        if (c & kMarks) resolve_split(P, b, c);
+        if (c & kMarks) resolve_split(P, b, c, P.part[w].x + P.lpre[at], N);
         else resolve_merge(P, b, c);
     }
 }
@@ -1423,7 +1566,7 @@ __global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
         } else {
             raise_err(P, kErrPointer);
         }
-        store_world<R>(P, s, world<R>(K, a), world<R>(K, b), world<R>(K, c), d, (int)(id & 1u));
+        store_world<R>(P, s, world<R>(K, a), world<R>(K, b), world<R>(K, c), d, id);
     }
 }
 
@@ -1530,6 +1673,41 @@ __global__ void k_import_records(Pool P, uint32_t b0, uint32_t n, const uint32_t
     P.id[b0 + i] = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
     P.link[b0 + i] = make_int4((int32_t)v[2], (int32_t)v[3], (int32_t)v[4], 0);
     P.fwd[b0 + i] = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+}
+
+// Live records, rank order: (block, id low, id high, twin, next, prev).
+__global__ void k_export_live(Pool P, uint32_t L, uint32_t* out)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= L) return;
+    const uint32_t s = P.live[r];
+    const uint64_t id = P.id[s];
+    const int4 l = P.link[s];
+    uint32_t* o = out + 6 * (size_t)r;
+    o[0] = s;
+    o[1] = (uint32_t)id;
+    o[2] = (uint32_t)(id >> 32);
+    o[3] = (uint32_t)l.x;
+    o[4] = (uint32_t)l.y;
+    o[5] = (uint32_t)l.z;
+}
+
+// Scatter of live records into a cleared pool; a block or pointer out of
+// range raises the pointer flag and is skipped.
+__global__ void k_import_live(Pool P, uint32_t n, const uint32_t* in)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t* v = in + 6 * (size_t)i;
+    const uint32_t s = v[0];
+    const int32_t t = (int32_t)v[3], x = (int32_t)v[4], p = (int32_t)v[5];
+    const bool ok = s < P.cap && (t == -1 || slot_ok(P, t)) && (x == -1 || slot_ok(P, x)) && (p == -1 || slot_ok(P, p));
+    if (!ok) {
+        raise_err(P, kErrPointer);
+        return;
+    }
+    P.id[s] = (uint64_t)v[1] | ((uint64_t)v[2] << 32);
+    P.link[s] = make_int4(t, x, p, 0);
 }
 
 // Triangle export: the cached world positions of every live bisector's
@@ -1738,6 +1916,18 @@ hipError_t launch_export_triangles(const Pool& P, uint32_t L, float* out9, hipSt
     if (!L) return hipGetLastError();
     if (P.f64) hipLaunchKernelGGL(k_export_triangles<double>, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out9);
     else hipLaunchKernelGGL(k_export_triangles<float>, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out9);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_live(const Pool& P, uint32_t L, uint32_t* out6, hipStream_t s)
+{
+    if (L) hipLaunchKernelGGL(k_export_live, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out6);
+    return hipGetLastError();
+}
+
+hipError_t launch_import_live(const Pool& P, uint32_t n, const uint32_t* in6, hipStream_t s)
+{
+    if (n) hipLaunchKernelGGL(k_import_live, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, P, n, in6);
     return hipGetLastError();
 }
 

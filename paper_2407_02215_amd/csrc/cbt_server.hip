@@ -47,9 +47,12 @@ struct SInst {
     int32_t groups = 0, levels = 0;   // schedule (0: library default)
     cbt_handle h = nullptr;
     size_t off = 0, bytes = 0;
-    bool has_snapshot = false;
-    std::vector<uint64_t> s_id;
-    std::vector<int32_t> s_twin, s_next, s_prev;
+    // state of an evicted instance: its live records (cbt_export_live), in
+    // the arena's top end or, when even that is full, on the host
+    enum Snap { kNoSnap, kDevSnap, kHostSnap } snap = kNoSnap;
+    size_t snap_off = 0, snap_bytes = 0;
+    int64_t snap_n = 0;
+    std::vector<uint32_t> snap_host;
     std::deque<Req> q;
     int slot = -1;
     double last_used = 0.0;
@@ -112,6 +115,25 @@ bool arena_alloc(cbt_server s, size_t bytes, size_t* off)
     return false;
 }
 
+// Snapshots are carved from the top of the highest free range that fits,
+// so that workspaces (first fit from the bottom) keep long free ranges.
+bool arena_alloc_top(cbt_server s, size_t bytes, size_t* off)
+{
+    bytes = round_up(bytes);
+    if (s->used + bytes > s->budget) return false;
+    for (auto it = s->free_.rbegin(); it != s->free_.rend(); ++it) {
+        if (it->second >= bytes) {
+            const size_t start = it->first, len = it->second;
+            *off = start + len - bytes;
+            if (len == bytes) s->free_.erase(start);
+            else s->free_[start] = len - bytes;
+            s->used += bytes;
+            return true;
+        }
+    }
+    return false;
+}
+
 void arena_free(cbt_server s, size_t off, size_t bytes)
 {
     bytes = round_up(bytes);
@@ -131,21 +153,38 @@ void arena_free(cbt_server s, size_t off, size_t bytes)
     }
 }
 
+char* inst_ptr(cbt_server s, size_t off) { return s->arena + s->inst_base + off; }
+
+// Evicts a resident instance: its live records (24 bytes per live bisector)
+// are exported into its own vertex cache (48 bytes per block), copied to
+// the arena's top end (or to the host when that is full) and the workspace
+// is released.  Ordered on the auxiliary stream before any reuse.
 cbt_status evict(cbt_server s, SInst& I)
 {
     if (!I.h) return CBT_OK;
-    const size_t cap = (size_t)1 << I.D;
-    I.s_id.resize(cap);
-    I.s_twin.resize(cap);
-    I.s_next.resize(cap);
-    I.s_prev.resize(cap);
-    cbt_status st = cbt_snapshot(I.h, I.s_id.data(), I.s_twin.data(), I.s_next.data(), I.s_prev.data());
+    const cbtk::Pool& P = I.h->P;
+    uint32_t* rec = reinterpret_cast<uint32_t*>(P.vworld);
+    int64_t n = 0;
+    cbt_status st = cbt_export_live(I.h, rec, 2 * (int64_t)P.cap, &n);
     if (st) {
         I.failed = true;
         return st;
     }
-    I.has_snapshot = true;
-    cbt_destroy(I.h);
+    const size_t bytes = sizeof(uint32_t) * 6 * (size_t)n;
+    size_t off = 0;
+    if (arena_alloc_top(s, bytes, &off)) {
+        HIP_TRY(nullptr, hipMemcpyAsync(inst_ptr(s, off), rec, bytes, hipMemcpyDeviceToDevice, s->aux), "snapshot copy");
+        I.snap = SInst::kDevSnap;
+        I.snap_off = off;
+        I.snap_bytes = bytes;
+    } else {
+        I.snap_host.resize(6 * (size_t)n);
+        HIP_TRY(nullptr, hipMemcpyAsync(I.snap_host.data(), rec, bytes, hipMemcpyDeviceToHost, s->aux), "snapshot copy");
+        I.snap = SInst::kHostSnap;
+        s->st.host_snapshots++;
+    }
+    I.snap_n = n;
+    cbt_destroy(I.h);   // synchronises the auxiliary stream
     I.h = nullptr;
     arena_free(s, I.off, I.bytes);
     s->st.evictions++;
@@ -154,9 +193,33 @@ cbt_status evict(cbt_server s, SInst& I)
     return CBT_OK;
 }
 
-// Makes I resident: allocates its workspace (evicting idle instances, least
-// recently used first, when the budget is exhausted), initialises it and
-// restores its snapshot.  CBT_E_BUDGET: cannot fit now.
+// Moves an evicted instance's records from the arena to the host.
+cbt_status snapshot_to_host(cbt_server s, SInst& I)
+{
+    I.snap_host.resize(6 * (size_t)I.snap_n);
+    HIP_TRY(nullptr, hipMemcpyAsync(I.snap_host.data(), inst_ptr(s, I.snap_off), I.snap_bytes, hipMemcpyDeviceToHost,
+                                    s->aux), "snapshot to host");
+    HIP_TRY(nullptr, hipStreamSynchronize(s->aux), "snapshot to host");
+    arena_free(s, I.snap_off, I.snap_bytes);
+    I.snap = SInst::kHostSnap;
+    s->st.host_snapshots++;
+    s->st.bytes_resident = (int64_t)s->used;
+    return CBT_OK;
+}
+
+void drop_snapshot(cbt_server s, SInst& I)
+{
+    if (I.snap == SInst::kDevSnap) arena_free(s, I.snap_off, I.snap_bytes);
+    I.snap = SInst::kNoSnap;
+    I.snap_n = 0;
+    std::vector<uint32_t>().swap(I.snap_host);
+    s->st.bytes_resident = (int64_t)s->used;
+}
+
+// Makes I resident: allocates its workspace, initialises it and imports its
+// records.  When the budget is exhausted, idle resident instances are
+// evicted, least recently used first, then the oldest snapshots in the arena
+// move to the host.  CBT_E_BUDGET: cannot fit now.
 cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
 {
     if (I.h) return CBT_OK;
@@ -176,41 +239,41 @@ cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
             if (std::find(pinned.begin(), pinned.end(), J.id) != pinned.end()) continue;
             if (!victim || J.last_used < victim->last_used) victim = &J;
         }
-        if (!victim) return CBT_E_BUDGET;
-        cbt_status st = evict(s, *victim);
+        if (victim) {
+            cbt_status st = evict(s, *victim);
+            if (st) return st;
+            continue;
+        }
+        SInst* old = nullptr;
+        for (auto& kv : s->inst) {
+            SInst& J = kv.second;
+            if (J.snap != SInst::kDevSnap || &J == &I) continue;
+            if (!old || J.last_used < old->last_used) old = &J;
+        }
+        if (!old) return CBT_E_BUDGET;
+        cbt_status st = snapshot_to_host(s, *old);
         if (st) return st;
     }
     cbt_mesh m{I.H, I.twin.data(), I.next.data(), I.prev.data(), I.vert.data(), I.V, I.pos.data()};
     cbt_handle h = nullptr;
-    cbt_status st = cbt_init(&m, I.D, s->arena + s->inst_base + off, bytes, s->aux, &h);
+    cbt_status st = cbt_init(&m, I.D, inst_ptr(s, off), bytes, s->aux, &h);
     if (st) {
         arena_free(s, off, bytes);
         I.failed = true;
         return st;
     }
-    if (I.groups) {
-        st = cbt_set_schedule(h, I.groups, I.levels);
-        if (st) {
-            cbt_destroy(h);
-            arena_free(s, off, bytes);
-            I.failed = true;
-            return st;
-        }
+    if (I.groups) st = cbt_set_schedule(h, I.groups, I.levels);
+    if (!st && I.snap == SInst::kDevSnap)
+        st = cbt_import_live(h, reinterpret_cast<const uint32_t*>(inst_ptr(s, I.snap_off)), I.snap_n, 0);
+    else if (!st && I.snap == SInst::kHostSnap)
+        st = cbt_import_live(h, I.snap_host.data(), I.snap_n, 1);
+    if (st) {
+        cbt_destroy(h);
+        arena_free(s, off, bytes);
+        I.failed = true;
+        return st;
     }
-    if (I.has_snapshot) {
-        st = cbt_restore(h, I.s_id.data(), I.s_twin.data(), I.s_next.data(), I.s_prev.data());
-        if (st) {
-            cbt_destroy(h);
-            arena_free(s, off, bytes);
-            I.failed = true;
-            return st;
-        }
-        I.has_snapshot = false;
-        std::vector<uint64_t>().swap(I.s_id);
-        std::vector<int32_t>().swap(I.s_twin);
-        std::vector<int32_t>().swap(I.s_next);
-        std::vector<int32_t>().swap(I.s_prev);
-    }
+    drop_snapshot(s, I);
     I.h = h;
     I.off = off;
     I.bytes = bytes;
@@ -642,6 +705,7 @@ cbt_status cbt_server_close(cbt_server s, int64_t instance_id)
         s->st.resident--;
         s->st.bytes_resident = (int64_t)s->used;
     }
+    drop_snapshot(s, I);
     s->inst.erase(it);
     s->st.instances--;
     return CBT_OK;

@@ -248,3 +248,38 @@ def test_schedule_does_not_change_results(groups, levels):
     assert_same_state(inst, orc, f"schedule {groups}/{levels}")
     assert_same_tree(inst, orc, f"schedule {groups}/{levels}")
     inst.close()
+
+
+def test_live_records_roundtrip():
+    """cbt_export_live gives the reference's live bisectors in ascending
+    block order; importing them (from device or host memory) into fresh
+    instances reproduces the state, and the update continues identically."""
+    w = I.workload("planet", frames=24, table_res=64)
+    a = cbt.Instance(w.mesh, w.depth, w.lod)
+    orc = Oracle(w.mesh, w.depth, w.lod)
+    for cam in w.cameras[:12]:
+        a.update(cam)
+        orc.frame(camera=cam)
+    rec = a.export_live()
+    r = rec.cpu().numpy().view(np.uint32)
+    ids, tw, nx, pv = orc.pool()
+    live = np.nonzero(ids)[0]
+    assert r.shape == (live.size, 6)
+    assert np.array_equal(r[:, 0], live)
+    assert np.array_equal(r[:, 1].astype(np.uint64) | (r[:, 2].astype(np.uint64) << np.uint64(32)), ids[live])
+    for col, ref in ((3, tw), (4, nx), (5, pv)):
+        assert np.array_equal(r[:, col].view(np.int32), ref[live])
+    b = cbt.Instance(w.mesh, w.depth, w.lod)
+    b.import_live(rec)
+    c = cbt.Instance(w.mesh, w.depth, w.lod)
+    c.import_live(r.copy())
+    for x in (b, c):
+        assert_same_state(x, orc, "imported")
+        assert_same_tree(x, orc, "imported")
+    for f, cam in enumerate(w.cameras[12:24]):
+        orc.frame(camera=cam)
+        for x in (a, b, c):
+            x.update(cam)
+    for x in (a, b, c):
+        assert_same_state(x, orc, "after import")
+        x.close()
