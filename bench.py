@@ -163,7 +163,7 @@ def run_single(args) -> dict:
     traffic = args.traffic
     if traffic is None and args.precision == 32 and args.workload == "terrain":
         from paper_2407_02215_amd import traffic as T
-        traffic = T.lookup(args.stage, args.warmup, args.steps)
+        traffic = T.lookup(args.stage, args.warmup, args.steps, inst.schedule())
     vb = 96 if args.precision == 64 else 48
     alg = sum(algorithmic_bytes(args.stage, s, vb) for s in stats) / len(stats)
     mean_ms = stage_ms / max(1, launches)

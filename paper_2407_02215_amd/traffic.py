@@ -8,10 +8,11 @@ dispatches come in its protocol order: W warm-up frames, then the counting,
 timed and latency passes over the same K frames; the timed pass is
 dispatches [W + K, W + 2K) of the kernel.  The result is written to
 ``traffic.json`` beside this file together with a digest of the kernel
-source, and the benchmark reports it only while that digest still matches.
+source and the launch schedule the counter run used (read from its
+benchmark line); the benchmark reports it only while both still match.
 
     python -m paper_2407_02215_amd.traffic --fetch F.csv --write W.csv \\
-        --copy-fetch CF.csv --copy-write CW.csv --kernel fill --warmup 40 --steps 200
+        --copy-fetch CF.csv --copy-write CW.csv --bench-log F.log --kernel fill --warmup 40 --steps 200
 """
 from __future__ import annotations
 
@@ -60,7 +61,20 @@ def scale(path: str, counter: str) -> float:
     return COPY_BYTES / (max(v) * 1024.0)
 
 
-def measure(fetch, write, copy_fetch, copy_write, stage, warmup, steps) -> dict:
+def bench_schedule(path: str) -> list:
+    """Launch schedule [rank groups, reduce levels] from the benchmark line
+    (the last JSON line with a "metric" key) in a log."""
+    sched = None
+    for line in open(path, errors="replace"):
+        line = line.strip()
+        if line.startswith('{"metric"'):
+            sched = json.loads(line)["config"]["schedule"]
+    if sched is None:
+        raise SystemExit(f"no benchmark line in {path}")
+    return [int(x) for x in sched]
+
+
+def measure(fetch, write, copy_fetch, copy_write, stage, warmup, steps, schedule) -> dict:
     m = _kernel_match(stage)
     f = per_dispatch(fetch, "FETCH_SIZE", m)
     w = per_dispatch(write, "WRITE_SIZE", m)
@@ -72,19 +86,19 @@ def measure(fetch, write, copy_fetch, copy_write, stage, warmup, steps) -> dict:
     fb = sum(f[lo:hi]) / steps * 1024.0 * sf
     wb = sum(w[lo:hi]) / steps * 1024.0 * sw
     return {"kernel": stage, "bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
-            "fetch_scale": sf, "write_scale": sw, "warmup": warmup, "steps": steps,
+            "fetch_scale": sf, "write_scale": sw, "warmup": warmup, "steps": steps, "schedule": schedule,
             "source_sha256": source_digest()}
 
 
-def lookup(stage: str, warmup: int, steps: int):
+def lookup(stage: str, warmup: int, steps: int, schedule):
     """Bytes per launch of the stage's kernel if measured on this kernel
-    source and frame range, else None."""
+    source, frame range and launch schedule, else None."""
     if not os.path.exists(TABLE):
         return None
     with open(TABLE) as f:
         t = json.load(f)
     if (t.get("kernel") != stage or t.get("warmup") != warmup or t.get("steps") != steps
-            or t.get("source_sha256") != source_digest()):
+            or t.get("schedule") != [int(x) for x in schedule] or t.get("source_sha256") != source_digest()):
         return None
     return float(t["bytes_per_launch"])
 
@@ -95,12 +109,13 @@ def main():
     ap.add_argument("--write", required=True)
     ap.add_argument("--copy-fetch", required=True)
     ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--bench-log", required=True, help="output of the FETCH_SIZE run (its benchmark line)")
     ap.add_argument("--kernel", default="fill")
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--out", default=TABLE)
     a = ap.parse_args()
-    t = measure(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.warmup, a.steps)
+    t = measure(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.warmup, a.steps, bench_schedule(a.bench_log))
     with open(a.out, "w") as f:
         json.dump(t, f, indent=1)
     print(json.dumps(t))
