@@ -127,7 +127,9 @@ def run_single(args) -> dict:
     w = I.workload(args.workload, frames=max(frames, 8))
     if len(w.cameras) < frames:
         raise SystemExit(f"workload {args.workload} has {len(w.cameras)} frames, asked for {frames}")
-    inst = cbt.Instance(w.mesh, w.depth, w.lod, tuned=True, precision=args.precision)
+    inst = cbt.Instance(w.mesh, w.depth, w.lod, tuned=args.schedule is None, precision=args.precision)
+    if args.schedule is not None:
+        inst.set_schedule(*(int(x) for x in args.schedule.split(",")))
     print(f"# warm-up {args.warmup} frames, schedule {inst.schedule()}", file=sys.stderr, flush=True)
     for cam in w.cameras[:args.warmup]:
         inst.update(cam)
@@ -329,7 +331,10 @@ def run_serve(args) -> dict:
         res = {"p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                "value": st["bisector_updates"] / wall, "wall_s": wall, "requests": len(done), "all_ok": ok,
                "batches": st["batches"], "mean_batch": len(done) / max(1, st["batches"]),
-               "admissions": st["admissions"], "evictions": st["evictions"]}
+               "admissions": st["admissions"], "evictions": st["evictions"],
+               "host_snapshots": st["host_snapshots"],
+               "admit_ms": {"total": st["admit_ms"], "max": st["admit_ms_max"]},
+               "evict_ms": {"total": st["evict_ms"], "max": st["evict_ms_max"]}}
         sample = sorted(ids)[:: max(1, len(ids) // 16)]
         states = {k: srv.query(ids[k]) for k in sample}
         srv.close()
@@ -369,6 +374,8 @@ def main():
     ap.add_argument("--workload", default="terrain", choices=["terrain", "planet", "cube"])
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64],
                     help="vertices, world positions and size test in binary32 or binary64 (single mode)")
+    ap.add_argument("--schedule", default=None,
+                    help="rank workgroups,reduction levels (single mode; default: the tuned table)")
     ap.add_argument("--stage", default="fill", choices=["classify", "fill", "resolve", "frame"])
     ap.add_argument("--traffic", type=float, default=None,
                     help="HBM bytes per launch of the profiled stage from the byte counters; by default "

@@ -363,7 +363,7 @@ typedef struct {
     int64_t memory_budget;  /* bytes for instance workspaces (0: the whole arena) */
     int32_t max_batch;      /* instances per batched launch, 1..4096            */
     int32_t slots;          /* batches in flight, each on its own stream, 1..8  */
-    int64_t map_capacity;   /* workgroups per batched launch (all three grids)  */
+    int64_t map_capacity;   /* workgroups per batched launch (all four grids)   */
 } cbt_server_config;
 
 typedef struct {
@@ -383,6 +383,8 @@ typedef struct {
     int64_t bisector_updates;   /* sum of live counts over served frames */
     int64_t bytes_resident, bytes_budget;   /* arena bytes in use (workspaces and records) */
     int64_t host_snapshots;                 /* evictions whose records went to host memory */
+    double admit_ms, admit_ms_max;          /* host time spent admitting instances: total, longest */
+    double evict_ms, evict_ms_max;          /* host time spent evicting instances: total, longest */
 } cbt_server_stats;
 
 size_t cbt_server_overhead_bytes(const cbt_server_config* cfg);   /* 0: invalid cfg */

@@ -486,10 +486,11 @@ class Completion(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "instances", "resident", "queued", "in_flight", "requests", "admissions", "evictions", "batches", "frames",
-        "bisector_updates", "bytes_resident", "bytes_budget", "host_snapshots")]
+        "bisector_updates", "bytes_resident", "bytes_budget", "host_snapshots")] + [
+        (n, C.c_double) for n in ("admit_ms", "admit_ms_max", "evict_ms", "evict_ms_max")]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: (float(getattr(self, f)) if t is C.c_double else int(getattr(self, f))) for f, t in self._fields_}
 
 
 SERVER_EXPORTS = ["cbt_server_overhead_bytes", "cbt_server_create", "cbt_server_open", "cbt_server_set_schedule",

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <vector>
 
 using cbtk::Counters;
@@ -32,6 +33,38 @@ cbt_status fail(cbt_handle h, cbt_status st, const char* fmt, ...)
     std::memcpy(g_err, buf, sizeof buf);
     if (h) std::memcpy(h->err, buf, sizeof buf);
     return st;
+}
+
+// Pinned counter mirrors come from slabs of 4096 slots allocated once and
+// kept for the life of the process: pinned allocations are slow and may
+// synchronise the device, which would stall servers that admit and evict
+// instances all the time.
+namespace {
+std::mutex g_pin_mu;
+std::vector<Counters*> g_pin_free;
+}  // namespace
+
+Counters* pinned_counters()
+{
+    std::lock_guard<std::mutex> lock(g_pin_mu);
+    if (g_pin_free.empty()) {
+        constexpr size_t kSlots = 4096;
+        Counters* slab = nullptr;
+        if (hipHostMalloc(reinterpret_cast<void**>(&slab), sizeof(Counters) * kSlots, hipHostMallocDefault) !=
+            hipSuccess)
+            return nullptr;
+        for (size_t i = kSlots; i-- > 0;) g_pin_free.push_back(slab + i);
+    }
+    Counters* c = g_pin_free.back();
+    g_pin_free.pop_back();
+    return c;
+}
+
+void release_counters(Counters* c)
+{
+    if (!c) return;
+    std::lock_guard<std::mutex> lock(g_pin_mu);
+    g_pin_free.push_back(c);
 }
 
 cbt_status hip_fail(cbt_handle h, hipError_t e, const char* what)
@@ -299,7 +332,8 @@ cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* de
     h->P.k = k;
     h->P.G = cbth::default_rank_groups(D);
     h->P.sub = cbtk::kMaxReduceSub;
-    if (hipHostMalloc(reinterpret_cast<void**>(&h->hctr), sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+    h->hctr = cbth::pinned_counters();
+    if (!h->hctr) {
         delete h;
         return fail(nullptr, CBT_E_DEVICE, "pinned host allocation failed");
     }
@@ -369,7 +403,7 @@ cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* de
     return CBT_OK;
 init_fail:
     (void)hipStreamSynchronize(s);
-    (void)hipHostFree(h->hctr);
+    cbth::release_counters(h->hctr);
     delete h;
     return rc;
 }
@@ -771,7 +805,7 @@ cbt_status cbt_destroy(cbt_handle h)
     if (!h) return CBT_OK;
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
-    (void)hipHostFree(h->hctr);
+    cbth::release_counters(h->hctr);
     delete h;
     return CBT_OK;
 }

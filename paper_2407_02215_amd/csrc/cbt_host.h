@@ -34,6 +34,9 @@ bool world_changed(const cbtk::LodK& a, const cbtk::LodK& b);
 // counters of a finished frame -> cbt_frame_stats (device flags -> CBT_E_DEVICE)
 cbt_status stats_from_counters(cbt_handle h, const cbtk::Counters& c, cbt_frame_stats* stats);
 uint32_t default_rank_groups(int32_t D);
+// a pinned host mirror of one instance's counters (NULL when out of memory)
+cbtk::Counters* pinned_counters();
+void release_counters(cbtk::Counters* c);
 
 }  // namespace cbth
 

@@ -696,6 +696,14 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
     const int maxd = 63 - P.k;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t nsplit = 0, nmerge = 0, scost = 0, nlist = 0, tile = 0;
+    // the rank entries of the next tile are loaded while this tile's
+    // records are in flight (past the chunk: block 0, in bounds, unused)
+    uint32_t sn[kClassRows];
+#pragma unroll
+    for (int j = 0; j < kClassRows; ++j) {
+        const uint32_t r = r0 + j * kBlock + threadIdx.x;
+        sn[j] = r < r1 ? P.live[r] : 0u;
+    }
     for (uint32_t base = r0; base < r1; base += kBlock * kClassRows, ++tile) {
         // every row's loads in flight before the first row is processed
         uint32_t sr[kClassRows], dr[kClassRows];
@@ -703,16 +711,16 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
         bool cand[kClassRows];
 #pragma unroll
         for (int j = 0; j < kClassRows; ++j) {
-            const uint32_t r = base + j * kBlock + threadIdx.x;
-            sr[j] = r < r1 ? P.live[r] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < kClassRows; ++j) {
-            // past the chunk sr[j] is block 0: an in-bounds load, unused
+            sr[j] = sn[j];
             const T4<R>* w = world_rec<R>(P, sr[j]);
             wa[j] = w[0];
             wb[j] = w[1];
             wc[j] = w[2];
+        }
+#pragma unroll
+        for (int j = 0; j < kClassRows; ++j) {
+            const uint32_t r = base + (kClassRows + j) * kBlock + threadIdx.x;
+            sn[j] = r < r1 ? P.live[r] : 0u;
         }
 #pragma unroll
         for (int j = 0; j < kClassRows; ++j) {
@@ -930,12 +938,16 @@ __global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
     const uint32_t F = P.ctr->F, Tm = P.ctr->Tm;
     uint2 carry = P.part[blk];
     uint32_t nm = 0, nlist = 0;
+    uint32_t sn[kSeg];   // the next tile's segment, loaded a tile ahead
+    load_seg(P, r0 + threadIdx.x * kSeg, r1, sn);
     for (uint32_t base = r0; base < r1; base += kBlock * kSeg) {
         const uint32_t t0 = base + threadIdx.x * kSeg;
         uint32_t sr[kSeg], cr[kSeg];
-        load_seg(P, t0, r1, sr);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) sr[j] = sn[j];
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) cr[j] = t0 + j < r1 ? P.cmd[sr[j]] : 0u;
+        load_seg(P, t0 + kBlock * kSeg, r1, sn);
         // reservations: (merge blocks, split blocks 3d + 4) per rank
         uint2 v[kSeg];
         uint2 loc = make_uint2(0, 0);
@@ -1043,41 +1055,43 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
     rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     uint32_t nexec = 0, nsc = 0, nfree = 0;
     uint2 run = make_uint2(0, 0);   // (owners, outputs) of earlier tiles
+    uint32_t sn[kSeg];              // the next tile's segment, loaded a tile ahead
+    load_seg(P, r0 + threadIdx.x * kSeg, r1, sn);
     for (uint32_t base = r0; base < r1; base += kBlock * kSeg) {
         const uint32_t t0 = base + threadIdx.x * kSeg;
-        // loads of the whole segment in flight together: rank entries,
-        // commands, then the members of accepted merges and their commands
         uint32_t sr[kSeg], cr[kSeg];
-        uint4 mr[kSeg];
-        load_seg(P, t0, r1, sr);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) sr[j] = sn[j];
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) cr[j] = t0 + j < r1 ? P.cmd[sr[j]] : 0u;
+        load_seg(P, t0 + kBlock * kSeg, r1, sn);
+        // split owners from the command word alone; accepted merges (a few
+        // per cent of the ranks) are checked one by one: a configuration
+        // with a split-marked member stays (splits win)
+        uint32_t kk = 0;   // 4 bits of output count per rank
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            const bool acc = !(cr[j] & kMarks) && (cr[j] & kMAcc);
-            mr[j] = acc ? P.fwd[sr[j]] : make_uint4(0, 0, 0, 0);
+            const uint32_t c = cr[j];
+            if (c & kMarks) {
+                kk |= split_outputs(c) << (4 * j);
+                ++nsc;
+                ++nfree;
+            } else if (c & kMAcc) {
+                const uint4 m = P.fwd[sr[j]];
+                bool any = (P.cmd[m.x] & kMarks) != 0;
+                if (m.w == 4) any = any || (P.cmd[m.y] & kMarks) || (P.cmd[m.z] & kMarks);
+                if (!any) {
+                    cr[j] = c | kMExec;
+                    kk |= (m.w / 2) << (4 * j);
+                    ++nexec;
+                    nfree += m.w;
+                }
+            }
         }
         uint2 loc = make_uint2(0, 0);   // (owners, outputs) of this segment
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            uint32_t c = cr[j], k = 0;
-            if (c & kMarks) {
-                k = split_outputs(c);
-                ++nsc;
-                ++nfree;
-            } else if (mr[j].w) {
-                // splits win: a configuration with a split-marked member stays
-                bool any = (P.cmd[mr[j].x] & kMarks) != 0;
-                if (mr[j].w == 4) any = any || (P.cmd[mr[j].y] & kMarks) || (P.cmd[mr[j].z] & kMarks);
-                if (!any) {
-                    c |= kMExec;
-                    k = mr[j].w / 2;
-                    ++nexec;
-                    nfree += mr[j].w;
-                }
-            }
-            cr[j] = c;
-            mr[j].w = k;   // outputs of rank t0 + j
+            const uint32_t k = (kk >> (4 * j)) & 15u;
             loc = make_uint2(loc.x + (k ? 1u : 0u), loc.y + k);
         }
         uint2 tot;
@@ -1085,7 +1099,7 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
         uint32_t at = r0 + run.x + pre.x, outs = run.y + pre.y;
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            const uint32_t k = mr[j].w;
+            const uint32_t k = (kk >> (4 * j)) & 15u;
             if (k) {
                 P.list[at] = make_uint2(sr[j], cr[j]);
                 P.lpre[at] = outs;

@@ -159,9 +159,17 @@ char* inst_ptr(cbt_server s, size_t off) { return s->arena + s->inst_base + off;
 // are exported into its own vertex cache (48 bytes per block), copied to
 // the arena's top end (or to the host when that is full) and the workspace
 // is released.  Ordered on the auxiliary stream before any reuse.
+void add_time(double* total, double* longest, double t0)
+{
+    const double ms = (now_s() - t0) * 1e3;
+    *total += ms;
+    *longest = ms > *longest ? ms : *longest;
+}
+
 cbt_status evict(cbt_server s, SInst& I)
 {
     if (!I.h) return CBT_OK;
+    const double t0 = now_s();
     const cbtk::Pool& P = I.h->P;
     uint32_t* rec = reinterpret_cast<uint32_t*>(P.vworld);
     int64_t n = 0;
@@ -190,6 +198,7 @@ cbt_status evict(cbt_server s, SInst& I)
     s->st.evictions++;
     s->st.resident--;
     s->st.bytes_resident = (int64_t)s->used;
+    add_time(&s->st.evict_ms, &s->st.evict_ms_max, t0);
     return CBT_OK;
 }
 
@@ -254,6 +263,7 @@ cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
         cbt_status st = snapshot_to_host(s, *old);
         if (st) return st;
     }
+    const double t0 = now_s();
     cbt_mesh m{I.H, I.twin.data(), I.next.data(), I.prev.data(), I.vert.data(), I.V, I.pos.data()};
     cbt_handle h = nullptr;
     cbt_status st = cbt_init(&m, I.D, inst_ptr(s, off), bytes, s->aux, &h);
@@ -280,6 +290,7 @@ cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
     s->st.admissions++;
     s->st.resident++;
     s->st.bytes_resident = (int64_t)s->used;
+    add_time(&s->st.admit_ms, &s->st.admit_ms_max, t0);
     return CBT_OK;
 }
 
