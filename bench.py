@@ -316,6 +316,16 @@ def run_serve(args) -> dict:
             ids[k] = srv.open(w.mesh, D, w.lod)
         done = []
         t0 = time.perf_counter()
+        last = t0
+
+        def progress():
+            nonlocal last
+            now = time.perf_counter()
+            if now - last > 5.0:
+                print(f"#   {len(done)} of {len(trace)} requests done after {now - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+                last = now
+
         for t, k, c in trace:
             while time.perf_counter() - t0 < t:
                 done += srv.poll()
@@ -323,6 +333,13 @@ def run_serve(args) -> dict:
                 w, D, _ = specs[k]
                 ids[k] = srv.open(w.mesh, D, w.lod)
             srv.submit(ids[k], specs[k][2][c], len(done))
+            progress()
+        while len(done) < len(trace):
+            got = srv.poll(wait=True)
+            done += got
+            progress()
+            if not got and srv.stats()["in_flight"] == 0:
+                break
         done += srv.drain()
         wall = time.perf_counter() - t0
         st = srv.stats()

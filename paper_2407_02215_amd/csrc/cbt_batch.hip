@@ -24,7 +24,7 @@ struct cbt_batch_s {
     hipStream_t stream;
     Inst* d_inst;
     Counters* d_ctr;
-    uint32_t *d_map_rank, *d_map_word, *d_map_red;
+    uint32_t *d_map_rank, *d_map_word, *d_map_red, *d_map_list;
     Inst* h_stage[2];           // pinned descriptor staging, double-buffered
     hipEvent_t staged[2];       // the upload from that buffer has completed
     bool stage_used[2];
@@ -41,10 +41,15 @@ struct cbt_batch_s {
 namespace {
 
 struct Layout {
-    size_t inst, ctr, map_rank, map_word, map_red, total;
+    size_t inst, ctr, map_rank, map_word, map_red, map_list, total;
 };
 
-Layout batch_layout(int n, uint64_t nr, uint64_t nw, uint64_t nd)
+// workgroups of the batched grids: rank, bitfield-word, reduction and list
+struct Grids {
+    uint64_t nr, nw, nd, nl;
+};
+
+Layout batch_layout(int n, const Grids& g)
 {
     Layout L{};
     size_t off = 0;
@@ -55,9 +60,10 @@ Layout batch_layout(int n, uint64_t nr, uint64_t nw, uint64_t nd)
     };
     L.inst = take(sizeof(Inst) * (size_t)n);
     L.ctr = take(sizeof(Counters) * (size_t)n);
-    L.map_rank = take(4 * nr);
-    L.map_word = take(4 * nw);
-    L.map_red = take(4 * nd);
+    L.map_rank = take(4 * g.nr);
+    L.map_word = take(4 * g.nw);
+    L.map_red = take(4 * g.nd);
+    L.map_list = take(4 * g.nl);
     L.total = off;
     return L;
 }
@@ -77,15 +83,17 @@ cbt_status check_members(const cbt_handle* members, int32_t n)
     return CBT_OK;
 }
 
-void grid_totals(const cbt_handle* members, int32_t n, uint64_t* nr, uint64_t* nw, uint64_t* nd)
+Grids grid_totals(const cbt_handle* members, int32_t n)
 {
-    *nr = *nw = *nd = 0;
+    Grids g{0, 0, 0, 0};
     for (int i = 0; i < n; ++i) {
         const Pool& P = members[i]->P;
-        *nr += P.G;
-        *nw += cbtk::word_groups(P);
-        *nd += cbtk::reduce_groups(P);
+        g.nr += P.G;
+        g.nw += cbtk::word_groups(P);
+        g.nd += cbtk::reduce_groups(P);
+        g.nl += cbtk::list_groups(P);
     }
+    return g;
 }
 
 cbt_status batch_fail(cbt_batch b, hipError_t e, const char* what)
@@ -170,9 +178,7 @@ extern "C" {
 size_t cbt_batch_workspace_bytes(const cbt_handle* members, int32_t n)
 {
     if (check_members(members, n) != CBT_OK) return 0;
-    uint64_t nr, nw, nd;
-    grid_totals(members, n, &nr, &nw, &nd);
-    return batch_layout(n, nr, nw, nd).total;
+    return batch_layout(n, grid_totals(members, n)).total;
 }
 
 cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_workspace, size_t workspace_bytes,
@@ -185,9 +191,8 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
     if (flags & ~CBT_BATCH_GRAPH) return cbth::fail(nullptr, CBT_E_ARG, "unknown batch flags 0x%x", flags);
     if ((flags & CBT_BATCH_GRAPH) && !hip_stream)
         return cbth::fail(nullptr, CBT_E_ARG, "graph capture needs a stream other than the null stream");
-    uint64_t nr, nw, nd;
-    grid_totals(members, n, &nr, &nw, &nd);
-    const Layout L = batch_layout(n, nr, nw, nd);
+    const Grids gt = grid_totals(members, n);
+    const Layout L = batch_layout(n, gt);
     if (!device_workspace) return cbth::fail(nullptr, CBT_E_ARG, "device workspace is NULL");
     if (reinterpret_cast<uintptr_t>(device_workspace) & 255)
         return cbth::fail(nullptr, CBT_E_ARG, "workspace must be 256-byte aligned");
@@ -205,11 +210,13 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
     b->d_map_rank = reinterpret_cast<uint32_t*>(ws + L.map_rank);
     b->d_map_word = reinterpret_cast<uint32_t*>(ws + L.map_word);
     b->d_map_red = reinterpret_cast<uint32_t*>(ws + L.map_red);
+    b->d_map_list = reinterpret_cast<uint32_t*>(ws + L.map_list);
     b->m.assign(members, members + n);
-    std::vector<uint32_t> mr, mw, md;
-    mr.reserve(nr);
-    mw.reserve(nw);
-    md.reserve(nd);
+    std::vector<uint32_t> mr, mw, md, ml;
+    mr.reserve(gt.nr);
+    mw.reserve(gt.nw);
+    md.reserve(gt.nd);
+    ml.reserve(gt.nl);
     for (int i = 0; i < n; ++i) {
         const Pool& P = members[i]->P;
         b->pools.push_back(P);
@@ -217,6 +224,7 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
         for (uint32_t g = 0; g < P.G; ++g) mr.push_back(tag | g);
         for (uint32_t g = 0; g < cbtk::word_groups(P); ++g) mw.push_back(tag | g);
         for (uint32_t g = 0; g < cbtk::reduce_groups(P); ++g) md.push_back(tag | g);
+        for (uint32_t g = 0; g < cbtk::list_groups(P); ++g) ml.push_back(tag | g);
     }
     cbt_status rc = CBT_OK;
     auto bail = [&](cbt_status s) {
@@ -245,6 +253,7 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
         if (hipMemcpyAsync(b->d_map_rank, mr.data(), 4 * mr.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(b->d_map_word, mw.data(), 4 * mw.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(b->d_map_red, md.data(), 4 * md.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(b->d_map_list, ml.data(), 4 * ml.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             bail(cbth::fail(nullptr, CBT_E_DEVICE, "block map upload failed"));
             break;
@@ -268,10 +277,12 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
     X.B.map_rank = b->d_map_rank;
     X.B.map_word = b->d_map_word;
     X.B.map_red = b->d_map_red;
+    X.B.map_list = b->d_map_list;
     X.n_inst = (uint32_t)n;
-    X.grid_rank = (uint32_t)nr;
-    X.grid_word = (uint32_t)nw;
-    X.grid_red = (uint32_t)nd;
+    X.grid_rank = (uint32_t)gt.nr;
+    X.grid_word = (uint32_t)gt.nw;
+    X.grid_red = (uint32_t)gt.nd;
+    X.grid_list = (uint32_t)gt.nl;
     *out = b;
     return CBT_OK;
 }

@@ -140,6 +140,7 @@ struct Batch {
     const uint32_t* map_rank;
     const uint32_t* map_word;
     const uint32_t* map_red;
+    const uint32_t* map_list;
 };
 
 // Everything a launch sequence needs: either one instance passed by value
@@ -150,11 +151,18 @@ struct Launch {
     Inst one;
     Batch B;
     uint32_t n_inst;
-    uint32_t grid_rank, grid_word, grid_red;
+    uint32_t grid_rank, grid_word, grid_red, grid_list;
 };
 
 // per-instance grid sizes
 uint32_t word_groups(const Pool& P);
+// workgroups of the passes over the compacted work lists: half the rank
+// workgroups (at least 16).  Their loads are dependent and random; fewer
+// waves in flight measured faster than the rank passes' count
+__host__ __device__ inline uint32_t list_groups(const Pool& P)
+{
+    return P.G / 2 > 16u ? P.G / 2 : 16u;
+}
 uint32_t reduce_groups(const Pool& P);
 int reduce_levels(const Pool& P);
 

@@ -293,7 +293,8 @@ __device__ __forceinline__ ListShare list_share(const Pool& P, uint32_t blk, uin
     }
     if (threadIdx.x == 0) base[G] = tot;
     __syncthreads();
-    const uint32_t per = (tot + G - 1) / G;
+    const uint32_t GL = list_groups(P);
+    const uint32_t per = (tot + GL - 1) / GL;
     const uint64_t a = (uint64_t)blk * per, b = a + per;
     ListShare s;
     s.i0 = (uint32_t)(a < tot ? a : tot);
@@ -342,17 +343,27 @@ __device__ __forceinline__ bool slot_ok(const Pool& P, int32_t s) { return (uint
 
 __device__ __forceinline__ int depth_of_cmd(uint32_t c) { return (int)((c & kDepthMask) >> kDepthShift); }
 
-// number of set bits in the words before word w, read off the tree
-__device__ uint32_t ones_before_word(const Pool& P, uint32_t w)
+// Number of set bits in the words before word w, read off the tree: the
+// left siblings along w's path from the root.  Their indices follow from
+// w's bits alone, so the lanes of the first wave load one level each, all
+// at once, and sum them; the result reaches every thread of the workgroup
+// through sh_out (one barrier, which every thread must reach).
+__device__ uint32_t ones_before_word(const Pool& P, uint32_t w, uint32_t* sh_out)
 {
-    const int LW = P.D - 5;
-    uint32_t node = 1, sum = 0;
-    for (int l = LW - 1; l >= 0; --l) {
-        const uint32_t bit = (w >> l) & 1u;
-        if (bit) sum += P.tree[2 * node];
-        node = 2 * node + bit;
+    if (threadIdx.x < 64) {
+        const int LW = P.D - 5;   // the word level; LW <= 25 < 64
+        const int l = (int)threadIdx.x;
+        uint32_t v = 0;
+        if (l < LW && ((w >> l) & 1u)) {
+            const uint32_t node = (1u << (LW - 1 - l)) | (w >> (l + 1));   // the path's node above level l
+            v = P.tree[2 * node];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (threadIdx.x == 0) *sh_out = v;
     }
-    return sum;
+    __syncthreads();
+    return *sh_out;
 }
 
 // ---------------------------------------------------------------------------
@@ -397,7 +408,8 @@ __global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
         const uint32_t w = w0 + j * kBlock + threadIdx.x;
         words[j] = (w < P.W) ? P.bits[w] : 0u;
     }
-    uint32_t base = ones_before_word(P, w0);
+    __shared__ uint32_t sb;
+    uint32_t base = ones_before_word(P, w0, &sb);
 #pragma unroll
     for (int j = 0; j < kSteps; ++j) {
         const uint32_t it = j * kBlock;
@@ -841,7 +853,7 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
     __shared__ uint32_t sh[8];
     __shared__ uint32_t base[kMaxRankGroups + 1];
     Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
     const ListShare ls = list_share(P, blk, base, sh);
     uint32_t ncfg = 0, res = 0, wres = 0xffffffffu;
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
@@ -1026,7 +1038,7 @@ __global__ void __launch_bounds__(kBlock) k_walk(Batch B, Inst one)
     __shared__ uint32_t sh[8];
     __shared__ uint32_t base[kMaxRankGroups + 1];
     Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
     const ListShare ls = list_share(P, blk, base, sh);
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
         uint32_t w;
@@ -1136,7 +1148,8 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
     const uint32_t N = P.ctr->N;
     const uint32_t w0 = blk * kWordsPerBlock;
     if (w0 >= P.W || N == 0) return;
-    uint32_t zb = 32u * w0 - ones_before_word(P, w0);
+    __shared__ uint32_t sb;
+    uint32_t zb = 32u * w0 - ones_before_word(P, w0, &sb);
     if (zb >= N) return;
     for (uint32_t it = 0; it < kWordsPerBlock; it += kBlock) {
         const uint32_t w = w0 + it + threadIdx.x;
@@ -1297,7 +1310,7 @@ __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
     Pool P;
     LodK K;
     const uint8_t* inj;
-    const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
+    const uint32_t blk = pick_k<kB>(B, one, B.map_list, P, K, inj);
     (void)inj;
     const ListShare ls = list_share(P, blk, base, sh);
     const uint32_t N = P.ctr->N;
@@ -1483,7 +1496,7 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
     __shared__ uint32_t sh[8];
     __shared__ uint32_t base[kMaxRankGroups + 1];
     Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
     const ListShare ls = list_share(P, blk, base, sh);
     const uint32_t N = P.ctr->N;
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
@@ -1827,6 +1840,7 @@ Launch single_launch(const Pool& P, const LodK& K, const uint8_t* inj)
     X.grid_rank = P.G;
     X.grid_word = word_groups(P);
     X.grid_red = reduce_groups(P);
+    X.grid_list = list_groups(P);
     return X;
 }
 
@@ -1849,7 +1863,7 @@ static hipError_t enumerate_seq(const Launch& X, hipStream_t s)
 template <bool kB, typename R>
 static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* ev)
 {
-    const dim3 g(X.grid_rank), b(kBlock), gw(X.grid_word), gi(X.n_inst);
+    const dim3 g(X.grid_rank), b(kBlock), gw(X.grid_word), gi(X.n_inst), gl(X.grid_list);
     auto mark = [&](int stage, bool begin) {
         if (ev && ev->stage == stage) (void)hipEventRecord(begin ? ev->begin : ev->end, s);
     };
@@ -1863,14 +1877,14 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL((k_classify<kB, R>), g, b, 0, s, X.B, X.one);
     mark(kClass, false);
     mark(kVote, true);
-    hipLaunchKernelGGL(k_vote<kB>, g, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL(k_vote<kB>, gl, b, 0, s, X.B, X.one);
     mark(kVote, false);
     mark(kBudget, true);
     hipLaunchKernelGGL(k_scan_parts<kB>, gi, dim3(1024), 0, s, X.B, X.one, 0);
     hipLaunchKernelGGL(k_budget<kB>, g, b, 0, s, X.B, X.one);
     mark(kBudget, false);
     mark(kChain, true);
-    hipLaunchKernelGGL(k_walk<kB>, g, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL(k_walk<kB>, gl, b, 0, s, X.B, X.one);
     mark(kChain, false);
     mark(kOwners, true);
     hipLaunchKernelGGL(k_owners<kB>, g, b, 0, s, X.B, X.one);
@@ -1882,10 +1896,10 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL(k_freelist<kB>, gw, b, 0, s, X.B, X.one);
     mark(kFree, false);
     mark(kFill, true);
-    hipLaunchKernelGGL((k_fill<kB, R>), g, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL((k_fill<kB, R>), gl, b, 0, s, X.B, X.one);
     mark(kFill, false);
     mark(kResolve, true);
-    hipLaunchKernelGGL(k_resolve<kB>, g, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL(k_resolve<kB>, gl, b, 0, s, X.B, X.one);
     mark(kResolve, false);
     mark(kReduce, true);
     hipError_t e = reduce_seq<kB>(X, s);

@@ -362,7 +362,7 @@ cbt_status launch_slot(cbt_server s, Slot& S)
               [](const SInst* a, const SInst* b) { return a->q.front().t_arrive < b->q.front().t_arrive; });
     std::vector<SInst*> pick;
     std::vector<int64_t> pinned;
-    uint64_t nr = 0, nw = 0, nd = 0;
+    uint64_t nr = 0, nw = 0, nd = 0, nl = 0;
     for (SInst* I : cand) {
         if ((int32_t)pick.size() >= s->cfg.max_batch) break;
         cbt_status st = admit(s, *I, pinned);
@@ -375,11 +375,12 @@ cbt_status launch_slot(cbt_server s, Slot& S)
             continue;
         }
         const cbtk::Pool& P = I->h->P;
-        const uint64_t r = P.G, w = cbtk::word_groups(P), d = cbtk::reduce_groups(P);
-        if ((nr + r) + (nw + w) + (nd + d) > (uint64_t)s->cfg.map_capacity) break;
+        const uint64_t r = P.G, w = cbtk::word_groups(P), d = cbtk::reduce_groups(P), l = cbtk::list_groups(P);
+        if ((nr + r) + (nw + w) + (nd + d) + (nl + l) > (uint64_t)s->cfg.map_capacity) break;
         nr += r;
         nw += w;
         nd += d;
+        nl += l;
         pick.push_back(I);
         pinned.push_back(I->id);
     }
@@ -388,7 +389,8 @@ cbt_status launch_slot(cbt_server s, Slot& S)
     uint32_t* mr = S.h_map;
     uint32_t* mw = mr + nr;
     uint32_t* md = mw + nw;
-    uint32_t ar = 0, aw = 0, ad = 0;
+    uint32_t* ml = md + nd;
+    uint32_t ar = 0, aw = 0, ad = 0, al = 0;
     S.ids.clear();
     S.reqs.clear();
     for (int i = 0; i < n; ++i) {
@@ -409,6 +411,7 @@ cbt_status launch_slot(cbt_server s, Slot& S)
         for (uint32_t g = 0; g < h->P.G; ++g) mr[ar++] = tag | g;
         for (uint32_t g = 0; g < cbtk::word_groups(h->P); ++g) mw[aw++] = tag | g;
         for (uint32_t g = 0; g < cbtk::reduce_groups(h->P); ++g) md[ad++] = tag | g;
+        for (uint32_t g = 0; g < cbtk::list_groups(h->P); ++g) ml[al++] = tag | g;
         I.slot = (int)(&S - s->slots.data());
         S.ids.push_back(I.id);
         S.reqs.push_back(r);
@@ -420,13 +423,16 @@ cbt_status launch_slot(cbt_server s, Slot& S)
     X.B.map_rank = S.d_map;
     X.B.map_word = S.d_map + nr;
     X.B.map_red = S.d_map + nr + nw;
+    X.B.map_list = S.d_map + nr + nw + nd;
     X.n_inst = (uint32_t)n;
     X.grid_rank = (uint32_t)nr;
     X.grid_word = (uint32_t)nw;
     X.grid_red = (uint32_t)nd;
+    X.grid_list = (uint32_t)nl;
     hipStream_t st = S.stream;
     HIP_TRY(nullptr, hipMemcpyAsync(S.d_inst, S.h_inst, sizeof(Inst) * (size_t)n, hipMemcpyHostToDevice, st), "descriptors");
-    HIP_TRY(nullptr, hipMemcpyAsync(S.d_map, S.h_map, 4 * (size_t)(nr + nw + nd), hipMemcpyHostToDevice, st), "block maps");
+    HIP_TRY(nullptr, hipMemcpyAsync(S.d_map, S.h_map, 4 * (size_t)(nr + nw + nd + nl), hipMemcpyHostToDevice, st),
+            "block maps");
     HIP_TRY(nullptr, cbtk::launch_frame(X, st, nullptr), "batched frame");
     HIP_TRY(nullptr, cbtk::launch_gather_counters(X, S.d_ctr, st), "gather counters");
     HIP_TRY(nullptr, hipMemcpyAsync(S.h_ctr, S.d_ctr, sizeof(Counters) * (size_t)n, hipMemcpyDeviceToHost, st), "counters");
@@ -463,15 +469,16 @@ Slot* oldest_busy(cbt_server s)
     return o;
 }
 
-// workgroups of the three batched grids one instance adds
+// workgroups of the four batched grids one instance adds
 uint64_t grid_need(int32_t D, int32_t groups, int32_t levels)
 {
     cbtk::Pool P{};
     P.D = D;
+    P.cap = (uint32_t)(1ull << D);
     P.W = (uint32_t)((1ull << D) / 32);
     P.G = groups ? (uint32_t)groups : cbth::default_rank_groups(D);
     P.sub = levels ? levels : cbtk::kMaxReduceSub;
-    return (uint64_t)P.G + cbtk::word_groups(P) + cbtk::reduce_groups(P);
+    return (uint64_t)P.G + cbtk::word_groups(P) + cbtk::reduce_groups(P) + cbtk::list_groups(P);
 }
 
 size_t slot_bytes(const cbt_server_config& c)
