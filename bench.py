@@ -24,10 +24,15 @@ Single-mode protocol (the pipeline is deterministic):
   1. warm up W frames;  2. snapshot the pool;
   3. run the K frames once with per-frame counters (untimed) for the live
      counts and the algorithmic bytes;  4. restore;
-  5. run the K frames timed, with HIP events around the profiled stage on the
-     library's stream (roofline);  6. restore;
+  5. run the K frames timed (no events);  6. restore;
   7. run the K frames again with events around every whole frame (p50/p99
-     frame latency) and check the final state equals the timed pass's.
+     frame latency) and check the final state equals the timed pass's;
+  8. once per surveyed stage (classify, vote, fill, resolve): restore and
+     run the K frames with HIP events around that stage's launches on the
+     library's stream; the roofline is reported for the longest stage;
+  9. export the final state's triangles 20 times (HIP events).
+Every pass runs the same K frames, so each kernel's dispatches of one pass
+([W + jK, W + (j+1)K) in dispatch order) see the same work.
 """
 from __future__ import annotations
 
@@ -62,6 +67,12 @@ def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
         # rank -> block (4), the vertex record (vb), command write (4); even
         # merge requests are listed (8 for about half of them)
         return (8.0 + vb) * L + 4.0 * R
+    if stage == "vote":
+        # per listed even member: its list entry (8) and pointer record (16),
+        # the commands of the three other members (12), the Prev pointer of
+        # the twin-side member (16) and two IDs for a cycle of four (16); per
+        # configuration found its forwarding record and command (20)
+        return 68.0 * st["merge_candidates"] + 20.0 * st["merge_configs"]
     if stage == "fill":
         # owner entries (8 + 4); a split bisector's ID (8) and vertex record
         # (vb) read, its fate + forwarding written (20); per split output a
@@ -85,6 +96,9 @@ def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
         # tree passes (3/8 byte per pool block, taken as L here)
         return (28.0 + vb) * L + algorithmic_bytes("fill", st, vb) + algorithmic_bytes("resolve", st, vb)
     raise KeyError(stage)
+
+
+SURVEY_STAGES = ("classify", "vote", "fill", "resolve")
 
 
 def percentile(xs, q):
@@ -127,6 +141,12 @@ def run_single(args) -> dict:
     w = I.workload(args.workload, frames=max(frames, 8))
     if len(w.cameras) < frames:
         raise SystemExit(f"workload {args.workload} has {len(w.cameras)} frames, asked for {frames}")
+    if args.criterion == "area":
+        # the same triangles as the edge thresholds: a bisector with base
+        # edge b has area b^2 / 4
+        import dataclasses
+        w = dataclasses.replace(w, lod=dataclasses.replace(
+            w.lod, split_px=w.lod.split_px ** 2 / 4, merge_px=w.lod.merge_px ** 2 / 4, criterion=I.CRIT_AREA))
     inst = cbt.Instance(w.mesh, w.depth, w.lod, tuned=args.schedule is None, precision=args.precision)
     if args.schedule is not None:
         inst.set_schedule(*(int(x) for x in args.schedule.split(",")))
@@ -140,15 +160,12 @@ def run_single(args) -> dict:
     stats = [inst.update(cam, stats=True) for cam in timed]
     inst.restore(*snap)
     print("# timed pass", file=sys.stderr, flush=True)
-    inst.time_stage(args.stage)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for cam in timed:
         inst.update(cam)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    launches, stage_ms = inst.stage_time()
-    inst.time_stage(None)
     check = [a.copy() for a in inst.pool()]
     print("# latency pass", file=sys.stderr, flush=True)
     inst.restore(*snap)
@@ -159,16 +176,42 @@ def run_single(args) -> dict:
     inst.time_stage(None)
     again = inst.pool()
     assert all(np.array_equal(a, b) for a, b in zip(check, again)), "non-deterministic frame"
+    # stage survey: the same frames once per stage with HIP events around
+    # that stage's launches; the roofline is reported for the longest one
+    # (or the one --stage names)
+    survey = {}
+    for stage in (SURVEY_STAGES if args.stage == "auto" else (args.stage,)):
+        inst.restore(*snap)
+        inst.time_stage(stage)
+        for cam in timed:
+            inst.update(cam)
+        n_st, ms_st = inst.stage_time()
+        inst.time_stage(None)
+        survey[stage] = ms_st / max(1, n_st)
+    dominant = max(survey, key=survey.get)
+    # triangle export of the final state: live list (4), vertex record, 36
+    # bytes written per triangle
+    L = inst.live_count()
+    tri = torch.empty((L, 3, 3), dtype=torch.float32, device="cuda")
+    inst.export_triangles(tri)
+    inst.time_stage("export")
+    for _ in range(20):
+        inst.export_triangles(tri)
+    n_exp, exp_ms = inst.stage_time()
+    inst.time_stage(None)
+    rec = 96 if args.precision == 64 else 48
+    exp_bytes = L * (4.0 + rec + 36.0)
+    exp_mean = exp_ms / max(1, n_exp)
 
     updates = sum(s["live_before"] for s in stats)
     value = updates / elapsed
     traffic = args.traffic
-    if traffic is None and args.precision == 32 and args.workload == "terrain":
+    if traffic is None and args.precision == 32 and args.workload == "terrain" and args.criterion == "edge":
         from paper_2407_02215_amd import traffic as T
-        traffic = T.lookup(args.stage, args.warmup, args.steps, inst.schedule())
+        traffic = T.lookup(dominant, args.warmup, args.steps, inst.schedule())
     vb = 96 if args.precision == 64 else 48
-    alg = sum(algorithmic_bytes(args.stage, s, vb) for s in stats) / len(stats)
-    mean_ms = stage_ms / max(1, launches)
+    alg = sum(algorithmic_bytes(dominant, s, vb) for s in stats) / len(stats)
+    mean_ms = survey[dominant]
     achieved = alg / (mean_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -183,17 +226,49 @@ def run_single(args) -> dict:
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 64 else "f32",
         "data": "synthetic (seeded workload generator)",
-        "config": {"workload": args.workload, "cbt_depth": w.depth, "halfedges": w.mesh.H,
+        "config": {"workload": args.workload, "criterion": args.criterion, "cbt_depth": w.depth,
+                   "halfedges": w.mesh.H,
                    "frames": f"{args.warmup}..{frames - 1}", "mean_live": updates / len(stats),
                    "schedule": list(inst.schedule())},
         "latency_ms": {"p50": percentile(frame_ms, 50), "p99": percentile(frame_ms, 99),
                        "what": "GPU time of one whole update, HIP events"},
-        "roofline": {"bound": "hbm", "kernel": args.stage, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "export": {"triangles": L, "ms": exp_mean, "alg_bytes": exp_bytes,
+                   "achieved_gbs": exp_bytes / (exp_mean * 1e-3) / 1e9},
+        "stage_ms": survey,
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
                      "mean_launch_ms": mean_ms, "alg_bytes_per_launch": alg},
     }
     inst.close()
     return out
+
+
+def run_converge(args) -> dict:
+    """Multi-pass mode from the base mesh at one camera: passes until
+    nothing changes, timed as a whole (each pass synchronises to read its
+    counters) and pass by pass with HIP events."""
+    import torch
+    from paper_2407_02215_amd import cbt
+    from paper_2407_02215_amd import inputs as I
+    w = I.workload(args.workload, frames=256 if args.workload == "planet" else None)
+    cam = w.cameras[min(args.camera, len(w.cameras) - 1)]
+    runs = []
+    for rep in range(3):
+        inst = cbt.Instance(w.mesh, w.depth, w.lod, tuned=True, precision=args.precision)
+        torch.cuda.synchronize()
+        inst.time_stage("frame")
+        t0 = time.perf_counter()
+        passes, last = inst.update_converge(cam, max_passes=64)
+        wall = time.perf_counter() - t0
+        pass_ms = inst.stage_times()
+        runs.append({"passes": passes, "wall_ms": wall * 1e3, "gpu_ms": float(sum(pass_ms)),
+                     "live": inst.live_count(), "converged": last["allocations"] == 0 and last["frees"] == 0})
+        inst.close()
+    best = min(runs, key=lambda r: r["wall_ms"])
+    return {"metric": "multi-pass update to the fixpoint", "value": best["wall_ms"], "unit": "ms",
+            "higher_is_better": False, "n_gpus": 1, "runs": runs,
+            "dtype": "f64" if args.precision == 64 else "f32", "data": "synthetic (seeded workload generator)",
+            "config": {"workload": args.workload, "camera": args.camera, "cbt_depth": w.depth}}
 
 
 def run_batch(args) -> dict:
@@ -385,7 +460,7 @@ def run_serve(args) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "converge"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="terrain", choices=["terrain", "planet", "cube"])
@@ -393,7 +468,11 @@ def main():
                     help="vertices, world positions and size test in binary32 or binary64 (single mode)")
     ap.add_argument("--schedule", default=None,
                     help="rank workgroups,reduction levels (single mode; default: the tuned table)")
-    ap.add_argument("--stage", default="fill", choices=["classify", "fill", "resolve", "frame"])
+    ap.add_argument("--criterion", default="edge", choices=["edge", "area"],
+                    help="size test of the LOD (single mode): projected base-edge length or triangle area")
+    ap.add_argument("--camera", type=int, default=255, help="camera index (converge mode)")
+    ap.add_argument("--stage", default="auto", choices=["auto"] + list(SURVEY_STAGES) + ["frame"],
+                    help="kernel whose roofline is reported; auto: the longest of the surveyed stages")
     ap.add_argument("--traffic", type=float, default=None,
                     help="HBM bytes per launch of the profiled stage from the byte counters; by default "
                          "the value paper_2407_02215_amd/traffic.py recorded for this kernel source")
@@ -428,6 +507,8 @@ def main():
         if not args.no_cpu_baseline:
             print("# CPU reference baseline", file=sys.stderr, flush=True)
             out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, args.precision)
+    elif args.mode == "converge":
+        out = run_converge(args)
     elif args.mode == "batch":
         args.steps = 48 if args.steps is None else args.steps
         args.warmup = 16 if args.warmup is None else args.warmup

@@ -136,6 +136,7 @@ typedef struct {
     int64_t frees;            /* released blocks                              */
     int64_t live_after;
     int64_t max_depth;        /* 0 unless requested through cbt_query         */
+    int64_t merge_candidates; /* even MERGE members examined by the vote      */
 } cbt_frame_stats;
 
 /* Live bisectors in ascending slot order (two-call pattern: with capacity

@@ -57,7 +57,8 @@ class LodParams(C.Structure):
 class FrameStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "live_before", "free_before", "split_requests", "split_accepted", "merge_requests", "merge_configs",
-        "merge_accepted", "merges_executed", "split_consumed", "allocations", "frees", "live_after", "max_depth")]
+        "merge_accepted", "merges_executed", "split_consumed", "allocations", "frees", "live_after", "max_depth",
+        "merge_candidates")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -151,6 +151,7 @@ cbt_status stats_from_counters(cbt_handle h, const Counters& c, cbt_frame_stats*
     stats->allocations = c.N;
     stats->frees = c.stat[cbtk::kStFrees];
     stats->live_after = (int64_t)c.L + c.N - c.stat[cbtk::kStFrees];
+    stats->merge_candidates = c.stat[cbtk::kStMergeCand];
     return CBT_OK;
 }
 

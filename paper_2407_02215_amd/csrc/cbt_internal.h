@@ -11,7 +11,7 @@ namespace cbtk {
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kMaxRankGroups = 2048;   // rank workgroups of one instance, at most
 constexpr int kMinRankGroups = 16;
-constexpr int kWordsPerBlock = 1024;   // bitfield words per workgroup (enumeration, free list)
+constexpr int kWordsPerBlock = 256;    // bitfield words per workgroup (enumeration, free list)
 constexpr int kMaxReduceSub = 10;      // tree levels reduced inside one workgroup, at most
 constexpr int kMinReduceSub = 5;
 constexpr int kMaxBatch = 4096;        // instances in one batched launch
@@ -56,6 +56,7 @@ enum StatIndex {
     kStMergeExec,
     kStSplitConsumed,
     kStFrees,
+    kStMergeCand,   // even members listed for the merge vote
     kStCount
 };
 

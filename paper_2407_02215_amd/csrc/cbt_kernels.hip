@@ -800,6 +800,7 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
         P.lcnt[blk] = nlist;
         if (a) atomicAdd(&P.ctr->stat[kStSplitReq], a);
         if (b) atomicAdd(&P.ctr->stat[kStMergeReq], b);
+        if (nlist) atomicAdd(&P.ctr->stat[kStMergeCand], nlist);
     }
 }
 

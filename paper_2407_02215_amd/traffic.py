@@ -4,15 +4,17 @@ Two counter runs of the benchmark (``--pmc FETCH_SIZE``, then
 ``--pmc WRITE_SIZE``) give KiB per dispatch; two runs of a plain device copy
 of known size (``bench.py --copy-calibration``) give the scale of each
 counter (bytes moved / bytes the counter reports).  The benchmark's kernel
-dispatches come in its protocol order: W warm-up frames, then the counting,
-timed and latency passes over the same K frames; the timed pass is
-dispatches [W + K, W + 2K) of the kernel.  The result is written to
-``traffic.json`` beside this file together with a digest of the kernel
-source and the launch schedule the counter run used (read from its
-benchmark line); the benchmark reports it only while both still match.
+dispatches come in its protocol order: W warm-up frames, then passes over
+the same K frames (counting, timed, latency, stage survey); the timed pass
+is dispatches [W + K, W + 2K) of the kernel.  The kernel is the one whose
+roofline the benchmark line reports (``--kernel auto``) or a named stage.
+The result is written to ``traffic.json`` beside this file together with a
+digest of the kernel source and the launch schedule the counter run used
+(read from its benchmark line); the benchmark reports it only while both
+still match.
 
     python -m paper_2407_02215_amd.traffic --fetch F.csv --write W.csv \\
-        --copy-fetch CF.csv --copy-write CW.csv --bench-log F.log --kernel fill --warmup 40 --steps 200
+        --copy-fetch CF.csv --copy-write CW.csv --bench-log F.log --kernel auto --warmup 40 --steps 200
 """
 from __future__ import annotations
 
@@ -61,24 +63,23 @@ def scale(path: str, counter: str) -> float:
     return COPY_BYTES / (max(v) * 1024.0)
 
 
-def bench_schedule(path: str) -> list:
-    """Launch schedule [rank groups, reduce levels] from the benchmark line
-    (the last JSON line with a "metric" key) in a log."""
-    sched = None
+def bench_line(path: str) -> dict:
+    """The benchmark line (the last JSON line with a "metric" key) of a log."""
+    line_ = None
     for line in open(path, errors="replace"):
         line = line.strip()
         if line.startswith('{"metric"'):
-            sched = json.loads(line)["config"]["schedule"]
-    if sched is None:
+            line_ = json.loads(line)
+    if line_ is None:
         raise SystemExit(f"no benchmark line in {path}")
-    return [int(x) for x in sched]
+    return line_
 
 
 def measure(fetch, write, copy_fetch, copy_write, stage, warmup, steps, schedule) -> dict:
     m = _kernel_match(stage)
     f = per_dispatch(fetch, "FETCH_SIZE", m)
     w = per_dispatch(write, "WRITE_SIZE", m)
-    need = warmup + 3 * steps
+    need = warmup + 2 * steps
     if len(f) < need or len(w) < need:
         raise SystemExit(f"expected {need} dispatches of k_{stage}, found {len(f)} / {len(w)}")
     lo, hi = warmup + steps, warmup + 2 * steps
@@ -110,12 +111,15 @@ def main():
     ap.add_argument("--copy-fetch", required=True)
     ap.add_argument("--copy-write", required=True)
     ap.add_argument("--bench-log", required=True, help="output of the FETCH_SIZE run (its benchmark line)")
-    ap.add_argument("--kernel", default="fill")
+    ap.add_argument("--kernel", default="auto", help="stage name, or auto: the benchmark line's roofline kernel")
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--out", default=TABLE)
     a = ap.parse_args()
-    t = measure(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.warmup, a.steps, bench_schedule(a.bench_log))
+    b = bench_line(a.bench_log)
+    kernel = b["roofline"]["kernel"] if a.kernel == "auto" else a.kernel
+    t = measure(a.fetch, a.write, a.copy_fetch, a.copy_write, kernel, a.warmup, a.steps,
+                [int(x) for x in b["config"]["schedule"]])
     with open(a.out, "w") as f:
         json.dump(t, f, indent=1)
     print(json.dumps(t))
