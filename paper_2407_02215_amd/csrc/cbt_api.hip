@@ -373,8 +373,8 @@ cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* de
         }                                         \
     } while (0)
     INIT_TRY(hipMemsetAsync(P.id, 0, sizeof(uint64_t) * P.cap, s), "clear IDs");
-    INIT_TRY(hipMemsetAsync(P.link, 0, sizeof(int4) * P.cap, s), "clear pointers");
-    INIT_TRY(hipMemsetAsync(P.fwd, 0xff, sizeof(uint4) * P.cap, s), "clear forwarding");
+    INIT_TRY(hipMemset2DAsync(&P.lf[0].l, sizeof(cbtk::LinkFwd), 0, sizeof(int4), P.cap, s), "clear pointers");
+    INIT_TRY(hipMemset2DAsync(&P.lf[0].f, sizeof(cbtk::LinkFwd), 0xff, sizeof(uint4), P.cap, s), "clear forwarding");
     INIT_TRY(hipMemsetAsync(P.lpre, 0, sizeof(uint32_t) * P.cap, s), "clear list offsets");
     INIT_TRY(hipMemsetAsync(P.bits, 0, sizeof(uint32_t) * P.W, s), "clear bitfield");
     INIT_TRY(hipMemsetAsync(P.cmd, 0, sizeof(uint32_t) * P.cap, s), "clear commands");
@@ -762,8 +762,8 @@ cbt_status cbt_import_live(cbt_handle h, const uint32_t* records, int64_t count,
     if (count < 1 || count > (int64_t)P.cap) return fail(h, CBT_E_ARG, "record count %lld outside [1, 2^D]", (long long)count);
     hipStream_t s = h->stream;
     HIP_TRY(h, hipMemsetAsync(P.id, 0, sizeof(uint64_t) * P.cap, s), "clear IDs");
-    HIP_TRY(h, hipMemsetAsync(P.link, 0, sizeof(int4) * P.cap, s), "clear pointers");
-    HIP_TRY(h, hipMemsetAsync(P.fwd, 0xff, sizeof(uint4) * P.cap, s), "clear forwarding");
+    HIP_TRY(h, hipMemset2DAsync(&P.lf[0].l, sizeof(cbtk::LinkFwd), 0, sizeof(int4), P.cap, s), "clear pointers");
+    HIP_TRY(h, hipMemset2DAsync(&P.lf[0].f, sizeof(cbtk::LinkFwd), 0xff, sizeof(uint4), P.cap, s), "clear forwarding");
     if (on_host) {
         size_t scratch_bytes;
         uint32_t* scratch = reinterpret_cast<uint32_t*>(list_scratch(P, &scratch_bytes));

@@ -84,19 +84,25 @@ struct LodK {
     int32_t crit;                          // size criterion (CBT_CRIT_*)
 };
 
+// The pointer record and the forwarding record of one block share a
+// 32-byte line: a pass that finds a neighbour consumed reads its forwarding
+// without another random access, and the fill writes a consumed bisector's
+// fate and forwarding in one line.
+struct LinkFwd {
+    int4 l;    // twin, next, prev (blocks, -1 on a border) and the bisector's
+               // fate this frame: 0 between frames; once the fill has run,
+               // the command word of a bisector consumed by a split (marks
+               // and depth), or kMExec for a merged member
+    uint4 f;   // during a frame: blocks given to a split bisector's outputs,
+               // or the parent block of a merged member; on the smallest
+               // member of a merge configuration first its other members,
+               // then (parent, members)
+};
+
 // Device state of one instance, carved from its workspace.
 struct Pool {
     uint64_t* id;      // [cap] heap ID per block (stale when free)
-    int4* link;        // [cap] twin, next, prev (blocks, -1 on a border) and
-                       //       the bisector's fate this frame: 0 between
-                       //       frames; once the fill has run, the command word
-                       //       of a bisector consumed by a split (marks and
-                       //       depth), or kMExec for a merged member
-    uint4* fwd;        // [cap] during a frame: blocks given to a split
-                       //       bisector's outputs, or the parent block of a
-                       //       merged member; on the smallest member of a
-                       //       merge configuration first its other members,
-                       //       then (parent, members)
+    LinkFwd* lf;       // [cap] pointer and forwarding records, side by side
     float4* vworld;    // [3 cap] world positions of the three vertices; w of
                        //         the first holds the subdivision depth, of the
                        //         second the parity of the heap ID (as integers);

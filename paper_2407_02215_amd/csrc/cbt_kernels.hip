@@ -827,7 +827,7 @@ __device__ __forceinline__ int merge_config_even(const Pool& P, int d, int4 l1, 
     if (j2 < 0) return 0;
     const uint32_t a3 = j3 >= 0 ? (uint32_t)j3 : 0u;   // in bounds either way
     const uint32_t cm2 = P.cmd[j2];
-    const int32_t j4 = P.link[a3].z;
+    const int32_t j4 = P.lf[a3].l.z;
     const uint32_t cm3 = P.cmd[a3];
     if (depth_of_cmd(cm2) != d) return 0;
     *j2o = j2;
@@ -863,13 +863,13 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
         const uint32_t s = e.x;
         int32_t j2 = -1, j3 = -1, j4 = -1;
         uint32_t c2 = 0, c3 = 0, c4 = 0;
-        const int m = merge_config_even(P, (int)e.y, P.link[s], &j2, &j3, &j4, &c2, &c3, &c4);
+        const int m = merge_config_even(P, (int)e.y, P.lf[s].l, &j2, &j3, &j4, &c2, &c3, &c4);
         if (!m || (m == 4 && P.id[j4] < P.id[s])) continue;   // not the smallest member
         bool ok = (c2 & kDecMask) == kMerge;
         if (m == 4) ok = ok && (c3 & kDecMask) == kMerge && (c4 & kDecMask) == kMerge;
         if (!ok) continue;
         P.cmd[s] |= kMCfg | kMMin | kMUnan | (m == 4 ? kMQuad : 0u);
-        P.fwd[s] = make_uint4((uint32_t)j2, (uint32_t)j3, (uint32_t)j4, (uint32_t)m);
+        P.lf[s].f = make_uint4((uint32_t)j2, (uint32_t)j3, (uint32_t)j4, (uint32_t)m);
         if (w != wres) {
             if (res) atomicAdd(&P.part[wres].x, res);
             wres = w;
@@ -1014,10 +1014,10 @@ __device__ void walk_chain(const Pool& P, uint32_t s)
     if (old & kMarkB) return;
     int32_t cur = (int32_t)s;
     for (int it = 0; it < 130; ++it) {
-        const int32_t n = P.link[cur].x;
+        const int32_t n = P.lf[cur].l.x;
         if (n < 0) return;
         if (!slot_ok(P, n)) { raise_err(P, kErrPointer); return; }
-        const int4 ln = P.link[n];
+        const int4 ln = P.lf[n].l;
         if (ln.x == cur) {
             atomicOr(&P.cmd[n], kMarkB);
             return;
@@ -1090,7 +1090,7 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
                 ++nsc;
                 ++nfree;
             } else if (c & kMAcc) {
-                const uint4 m = P.fwd[sr[j]];
+                const uint4 m = P.lf[sr[j]].f;
                 bool any = (P.cmd[m.x] & kMarks) != 0;
                 if (m.w == 4) any = any || (P.cmd[m.y] & kMarks) || (P.cmd[m.z] & kMarks);
                 if (!any) {
@@ -1251,8 +1251,8 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
         store_world<R>(P, f.z, w2, wm, wm1, d + 2, 4 * x + 2);
         store_world<R>(P, f.w, wm, w1, wm1, d + 2, 4 * x + 3);
     }
-    P.link[s].w = (int)c;
-    P.fwd[s] = f;
+    P.lf[s].l.w = (int)c;
+    P.lf[s].f = f;
 }
 
 // Merges: the parent of the sibling pair (c0 even, c1 odd) has vertices
@@ -1261,7 +1261,7 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
 template <typename R>
 __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c, uint32_t base, uint32_t N)
 {
-    const uint4 m = P.fwd[s];   // (sibling, other odd, other even, members)
+    const uint4 m = P.lf[s].f;   // (sibling, other odd, other even, members)
     const bool quad = m.w == 4;
     if (base + (quad ? 2u : 1u) > N) { raise_err(P, kErrAlloc); return; }
     if (m.x >= P.cap || (quad && (m.y >= P.cap || m.z >= P.cap))) { raise_err(P, kErrPointer); return; }
@@ -1290,16 +1290,16 @@ __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c
     if (qa >= P.cap || (quad && qb >= P.cap)) { raise_err(P, kErrAlloc); return; }
     const int dp = depth_of_cmd(c) - 1;
     store_world<R>(P, qa, ld3<R>(a0), ld3<R>(d0), ld3<R>(b0), dp, ida);
-    P.link[s].w = (int)kMExec;
-    P.fwd[s] = make_uint4(qa, m.x, m.y, m.z);
-    P.link[m.x].w = (int)kMExec;
-    P.fwd[m.x] = make_uint4(qa, 0, 0, 0);
+    P.lf[s].l.w = (int)kMExec;
+    P.lf[s].f = make_uint4(qa, m.x, m.y, m.z);
+    P.lf[m.x].l.w = (int)kMExec;
+    P.lf[m.x].f = make_uint4(qa, 0, 0, 0);
     if (quad) {
         store_world<R>(P, qb, ld3<R>(a1), ld3<R>(d1), ld3<R>(b1), dp, idb);
-        P.link[m.y].w = (int)kMExec;
-        P.fwd[m.y] = make_uint4(qb, 0, 0, 0);
-        P.link[m.z].w = (int)kMExec;
-        P.fwd[m.z] = make_uint4(qb, 0, 0, 0);
+        P.lf[m.y].l.w = (int)kMExec;
+        P.lf[m.y].f = make_uint4(qb, 0, 0, 0);
+        P.lf[m.z].l.w = (int)kMExec;
+        P.lf[m.z].f = make_uint4(qb, 0, 0, 0);
     }
 }
 
@@ -1378,7 +1378,7 @@ __device__ __forceinline__ void load_nbs(const Pool& P, const int32_t (&b)[N], c
     for (int i = 0; i < N; ++i) {
         const bool ok = slot_ok(P, n[i]);
         if (n[i] >= 0 && !ok) raise_err(P, kErrPointer);
-        ln[i] = P.link[ok ? n[i] : 0];
+        ln[i] = P.lf[ok ? n[i] : 0].l;
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -1391,7 +1391,7 @@ __device__ __forceinline__ void load_nbs(const Pool& P, const int32_t (&b)[N], c
         r[i].c = use ? (uint32_t)ln[i].w : 0u;
     }
 #pragma unroll
-    for (int i = 0; i < N; ++i) r[i].fw = P.fwd[r[i].c ? r[i].n : 0];
+    for (int i = 0; i < N; ++i) r[i].fw = P.lf[r[i].c ? r[i].n : 0].f;
 }
 
 // New neighbour across (a piece of) an old edge, seen from output x: the
@@ -1411,7 +1411,7 @@ __device__ __forceinline__ int32_t piece_target(const Pool& P, const Nb& nb, int
     }
     if (nb.c & kMExec) return (int32_t)nb.fw.x;
     if (piece != kWhole) { raise_err(P, kErrEdge); return -1; }
-    reinterpret_cast<int*>(&P.link[nb.n])[nb.f] = (int)x;
+    reinterpret_cast<int*>(&P.lf[nb.n].l)[nb.f] = (int)x;
     return nb.n;
 }
 
@@ -1420,7 +1420,7 @@ __device__ __forceinline__ void store_new(const Pool& P, uint32_t q, uint64_t id
 {
     if (q >= P.cap) { raise_err(P, kErrAlloc); return; }
     P.id[q] = id;
-    P.link[q] = make_int4(t, n, p, 0);
+    P.lf[q].l = make_int4(t, n, p, 0);
 }
 
 __device__ __forceinline__ void clear_bit(const Pool& P, uint32_t s)
@@ -1435,7 +1435,7 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
     uint4 f;   // the outputs' blocks, from the free list as the fill took them
     if (!split_targets(P, c, base, N, &f)) return;
     const uint64_t x = P.id[b];
-    const int4 lb = P.link[b];
+    const int4 lb = P.lf[b].l;
     const int32_t own[3] = {b, b, b};
     const int32_t across[3] = {lb.x, lb.y, lb.z};
     Nb nb[3];
@@ -1469,15 +1469,15 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
 // one round each; a border pair loads its own members twice (unused).
 __device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t c)
 {
-    const uint4 f = P.fwd[b];   // (parent, sibling, other odd, other even)
+    const uint4 f = P.lf[b].f;   // (parent, sibling, other odd, other even)
     const uint64_t ida = P.id[b] >> 1;
     const int d = depth_of_cmd(c);
     const bool quad = (c & kMQuad) != 0;
     const uint32_t e2 = quad ? f.w : (uint32_t)b, o2 = quad ? f.z : f.y;
-    const uint32_t qb = P.fwd[e2].x;            // the second parent
+    const uint32_t qb = P.lf[e2].f.x;            // the second parent
     const uint64_t idb = P.id[e2] >> 1;
     const int32_t mem[4] = {(int32_t)f.y, b, (int32_t)o2, (int32_t)e2};
-    const int32_t twin[4] = {P.link[f.y].x, P.link[b].x, P.link[o2].x, P.link[e2].x};
+    const int32_t twin[4] = {P.lf[f.y].l.x, P.lf[b].l.x, P.lf[o2].l.x, P.lf[e2].l.x};
     Nb nb[4];
     load_nbs(P, mem, twin, nb);
     store_new(P, f.x, ida, quad ? (int32_t)qb : -1, piece_target(P, nb[0], d, kWhole, f.x),
@@ -1619,7 +1619,7 @@ __global__ void k_gather_links(Pool P, uint32_t r0, uint32_t n, int32_t* out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int4 l = P.link[P.live[r0 + i]];
+    const int4 l = P.lf[P.live[r0 + i]].l;
     out[3 * (size_t)i + 0] = l.x;
     out[3 * (size_t)i + 1] = l.y;
     out[3 * (size_t)i + 2] = l.z;
@@ -1684,7 +1684,7 @@ __global__ void k_export_records(Pool P, uint32_t b0, uint32_t n, uint32_t* out)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t id = P.id[b0 + i];
-    const int4 l = P.link[b0 + i];
+    const int4 l = P.lf[b0 + i].l;
     uint32_t* o = out + 5 * (size_t)i;
     o[0] = (uint32_t)id;
     o[1] = (uint32_t)(id >> 32);
@@ -1699,8 +1699,8 @@ __global__ void k_import_records(Pool P, uint32_t b0, uint32_t n, const uint32_t
     if (i >= n) return;
     const uint32_t* v = in + 5 * (size_t)i;
     P.id[b0 + i] = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
-    P.link[b0 + i] = make_int4((int32_t)v[2], (int32_t)v[3], (int32_t)v[4], 0);
-    P.fwd[b0 + i] = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+    P.lf[b0 + i].l = make_int4((int32_t)v[2], (int32_t)v[3], (int32_t)v[4], 0);
+    P.lf[b0 + i].f = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
 }
 
 // Live records, rank order: (block, id low, id high, twin, next, prev).
@@ -1710,7 +1710,7 @@ __global__ void k_export_live(Pool P, uint32_t L, uint32_t* out)
     if (r >= L) return;
     const uint32_t s = P.live[r];
     const uint64_t id = P.id[s];
-    const int4 l = P.link[s];
+    const int4 l = P.lf[s].l;
     uint32_t* o = out + 6 * (size_t)r;
     o[0] = s;
     o[1] = (uint32_t)id;
@@ -1735,7 +1735,7 @@ __global__ void k_import_live(Pool P, uint32_t n, const uint32_t* in)
         return;
     }
     P.id[s] = (uint64_t)v[1] | ((uint64_t)v[2] << 32);
-    P.link[s] = make_int4(t, x, p, 0);
+    P.lf[s].l = make_int4(t, x, p, 0);
 }
 
 // Triangle export: the cached world positions of every live bisector's
@@ -1796,7 +1796,7 @@ size_t workspace_layout(int32_t H, int32_t D, int32_t f64, Pool* P, char* base)
         off = (off + bytes + 255) & ~(size_t)255;
         return o;
     };
-    const size_t o_id = take(8 * cap), o_link = take(16 * cap), o_fwd = take(16 * cap);
+    const size_t o_id = take(8 * cap), o_lf = take(sizeof(LinkFwd) * cap);
     const size_t vrec = f64 ? 3 * sizeof(double4) : 3 * sizeof(float4);   // one vertex-cache record
     const size_t o_world = take(vrec * cap), o_cmd = take(4 * cap);
     const size_t o_bits = take(4 * W), o_tree = take(4 * TW), o_live = take(4 * cap);
@@ -1805,8 +1805,7 @@ size_t workspace_layout(int32_t H, int32_t D, int32_t f64, Pool* P, char* base)
     const size_t o_root = take((f64 ? 72 : 36) * (size_t)H);
     if (P) {
         P->id = reinterpret_cast<uint64_t*>(base + o_id);
-        P->link = reinterpret_cast<int4*>(base + o_link);
-        P->fwd = reinterpret_cast<uint4*>(base + o_fwd);
+        P->lf = reinterpret_cast<LinkFwd*>(base + o_lf);
         P->vworld = reinterpret_cast<float4*>(base + o_world);
         P->cmd = reinterpret_cast<uint32_t*>(base + o_cmd);
         P->bits = reinterpret_cast<uint32_t*>(base + o_bits);
