@@ -27,9 +27,10 @@ Single-mode protocol (the pipeline is deterministic):
   5. run the K frames timed (no events);  6. restore;
   7. run the K frames again with events around every whole frame (p50/p99
      frame latency) and check the final state equals the timed pass's;
-  8. once per surveyed stage (classify, vote, fill, resolve): restore and
-     run the K frames with HIP events around that stage's launches on the
-     library's stream; the roofline is reported for the longest stage;
+  8. once per stage: restore and run the K frames with HIP events around
+     that stage's launches on the library's stream; the roofline is
+     reported for the longest stage with a byte model (classify, vote,
+     fill, resolve);
   9. export the final state's triangles 20 times (HIP events).
 Every pass runs the same K frames, so each kernel's dispatches of one pass
 ([W + jK, W + (j+1)K) in dispatch order) see the same work.
@@ -98,7 +99,8 @@ def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
     raise KeyError(stage)
 
 
-SURVEY_STAGES = ("classify", "vote", "fill", "resolve")
+SURVEY_STAGES = ("classify", "vote", "fill", "resolve")          # stages with a byte model
+EXTRA_STAGES = ("enumerate", "budget", "chain", "owners", "freelist", "reduce")
 
 
 def percentile(xs, q):
@@ -180,7 +182,7 @@ def run_single(args) -> dict:
     # that stage's launches; the roofline is reported for the longest one
     # (or the one --stage names)
     survey = {}
-    for stage in (SURVEY_STAGES if args.stage == "auto" else (args.stage,)):
+    for stage in (SURVEY_STAGES + EXTRA_STAGES if args.stage == "auto" else (args.stage,)):
         inst.restore(*snap)
         inst.time_stage(stage)
         for cam in timed:
@@ -188,7 +190,7 @@ def run_single(args) -> dict:
         n_st, ms_st = inst.stage_time()
         inst.time_stage(None)
         survey[stage] = ms_st / max(1, n_st)
-    dominant = max(survey, key=survey.get)
+    dominant = max((k for k in survey if k in SURVEY_STAGES or k == args.stage), key=survey.get)
     # triangle export of the final state: live list (4), vertex record, 36
     # bytes written per triangle
     L = inst.live_count()

@@ -270,13 +270,14 @@ cbt_status cbt_frame_constants(cbt_handle h, const cbt_camera* camera,
  * launches and their summed duration in milliseconds. */
 enum {
     CBT_STAGE_NONE = 0,
-    CBT_STAGE_ENUMERATE = 1,  /* live blocks in rank order                     */
-    CBT_STAGE_CLASSIFY = 2,   /* decode, LOD test, merge configuration         */
-    CBT_STAGE_VOTE = 3,       /* merge unanimity, reservation amounts          */
+    CBT_STAGE_ENUMERATE = 1,  /* frame set-up, live blocks in rank order       */
+    CBT_STAGE_CLASSIFY = 2,   /* LOD test on the vertex cache, command words   */
+    CBT_STAGE_VOTE = 3,       /* merge configurations, unanimity, reservations */
     CBT_STAGE_BUDGET = 4,     /* rank-order reservation cut                    */
     CBT_STAGE_CHAIN = 5,      /* compatibility-chain split marks               */
     CBT_STAGE_OWNERS = 6,     /* outputs per owner                             */
-    CBT_STAGE_OFFSETS = 7,    /* allocation offsets                            */
+    CBT_STAGE_OFFSETS = 7,    /* no launch: the allocation offsets are scanned
+                                 inside the free-list, fill and pointer passes */
     CBT_STAGE_FREELIST = 8,   /* free blocks                                   */
     CBT_STAGE_FILL = 9,       /* new heap IDs, forwarding records              */
     CBT_STAGE_RESOLVE = 10,   /* neighbour pointers, bitfield clears           */

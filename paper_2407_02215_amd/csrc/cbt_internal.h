@@ -63,8 +63,6 @@ enum StatIndex {
 struct Counters {
     uint32_t L;     // live blocks at frame start (CBT root)
     uint32_t F;     // free blocks
-    uint32_t Tm;    // total merge reservation (saturated)
-    uint32_t Ts;    // total split reservation (saturated)
     uint32_t N;     // allocations of this frame
     uint32_t err;   // sticky error flags
     uint32_t pad[2];

@@ -8,8 +8,8 @@
 // scans) alternate with heavy passes over compacted per-workgroup work
 // lists, so divergent pointer work runs with full wavefronts:
 //
-//   begin      L = CBT root, F = 2^D - L                              (kernel 1)
-//   enumerate  rank -> block list; each workgroup's base comes from the
+//   enumerate  L = CBT root, F = 2^D - L (its first workgroup)       (kernel 1)
+//              rank -> block list; each workgroup's base comes from the
 //              tree (the prefix form of the Alg. 7 descent)          (kernel 2)
 //   classify   LOD test on the cached world positions -> command word;
 //              split reservations per workgroup; list: even members
@@ -162,6 +162,22 @@ __device__ __forceinline__ uint2 block_excl_scan_sat(uint2 v, uint2* sh, uint2* 
     return sat_add2(pre, ex);
 }
 
+// saturating sum of pairs over the workgroup, returned to every thread;
+// sh holds >= 4 uint2
+__device__ __forceinline__ uint2 block_reduce_sat2(uint2 v, uint2* sh)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = sat_add2(v, make_uint2(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64)));
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    uint2 t = make_uint2(0, 0);
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) t = sat_add2(t, sh[i]);
+    __syncthreads();
+    return t;
+}
+
 // exclusive scan of pairs (plain sums); sh holds >= 4 uint2
 __device__ __forceinline__ uint2 block_excl_scan2(uint2 v, uint2* sh, uint2* total)
 {
@@ -272,26 +288,40 @@ struct ListShare {
     uint32_t chunk;       // ranks per rank workgroup
 };
 
-__device__ __forceinline__ ListShare list_share(const Pool& P, uint32_t blk, uint32_t* base, uint32_t* sh)
+// With obase non-NULL the owners' output counts (the partials the owner
+// pass leaves) are scanned the same way: obase[w] = outputs of the rank
+// workgroups before w, obase[G] = N.
+__device__ __forceinline__ ListShare list_share(const Pool& P, uint32_t blk, uint32_t* base, uint32_t* sh,
+                                                uint32_t* obase = nullptr)
 {
     constexpr int E = kMaxRankGroups / kBlock;
     const uint32_t G = P.G;
-    uint32_t v[E], loc = 0;
+    uint32_t v[E], o[E], loc = 0, oloc = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t w = threadIdx.x * E + e;
         v[e] = w < G ? P.lcnt[w] : 0u;
+        o[e] = (obase && w < G) ? P.part[w].x : 0u;
         loc += v[e];
+        oloc += o[e];
     }
-    uint32_t tot;
+    uint32_t tot, otot = 0;
     uint32_t run = block_excl_scan(loc, sh, &tot);
+    uint32_t orun = obase ? block_excl_scan(oloc, sh, &otot) : 0u;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t w = threadIdx.x * E + e;
-        if (w < G) base[w] = run;
+        if (w < G) {
+            base[w] = run;
+            if (obase) obase[w] = orun;
+        }
         run += v[e];
+        orun += o[e];
     }
-    if (threadIdx.x == 0) base[G] = tot;
+    if (threadIdx.x == 0) {
+        base[G] = tot;
+        if (obase) obase[G] = otot;
+    }
     __syncthreads();
     const uint32_t GL = list_groups(P);
     const uint32_t per = (tot + GL - 1) / GL;
@@ -370,25 +400,10 @@ __device__ uint32_t ones_before_word(const Pool& P, uint32_t w, uint32_t* sh_out
 // kernel: frame begin (one workgroup per instance)
 // ---------------------------------------------------------------------------
 
-template <bool kB>
-__global__ void k_begin(Batch B, Inst one)
-{
-    Pool P;
-    pick_inst<kB>(B, one, P);
-    if (threadIdx.x == 0) {
-        const uint32_t L = P.tree[1];
-        P.ctr->L = L;
-        P.ctr->F = P.cap - L;
-        P.ctr->Tm = 0;
-        P.ctr->Ts = 0;
-        P.ctr->N = 0;
-    }
-    if (threadIdx.x < kStCount) P.ctr->stat[threadIdx.x] = 0;
-}
-
 // ---------------------------------------------------------------------------
-// kernel: enumerate live blocks (rank order = ascending block index).  Each
-// 256-word step is staged in LDS so the rank list is written coalesced.
+// kernel: frame set-up and enumeration of the live blocks (rank order =
+// ascending block index).  Each 256-word step is staged in LDS so the rank
+// list is written coalesced.
 // ---------------------------------------------------------------------------
 
 template <bool kB>
@@ -398,6 +413,17 @@ __global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
     __shared__ uint32_t stage[kBlock * 32];
     Pool P;
     const uint32_t blk = pick<kB>(B, one, B.map_word, P);
+    if (blk == 0) {
+        // frame set-up (kernel 1): L = the CBT root, F = 2^D - L, counters
+        // cleared; no other workgroup reads the counters
+        if (threadIdx.x == 0) {
+            const uint32_t L = P.tree[1];
+            P.ctr->L = L;
+            P.ctr->F = P.cap - L;
+            P.ctr->N = 0;
+        }
+        if (threadIdx.x < kStCount) P.ctr->stat[threadIdx.x] = 0;
+    }
     const uint32_t w0 = blk * kWordsPerBlock;
     if (w0 >= P.W) return;
     // all of this workgroup's words in flight while the tree is descended
@@ -883,54 +909,6 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
     if (threadIdx.x == 0 && u) atomicAdd(&P.ctr->stat[kStMergeCfg], u);
 }
 
-// exclusive saturating scan of one instance's G per-workgroup partials (one
-// workgroup of 1024 threads per instance, two partials each); mode 0: the
-// totals are the reservations, mode 1: the allocations
-template <bool kB>
-__global__ void __launch_bounds__(1024) k_scan_parts(Batch B, Inst one, int mode)
-{
-    constexpr int E = kMaxRankGroups / 1024;
-    __shared__ uint2 sh[16];
-    Pool P;
-    pick_inst<kB>(B, one, P);
-    const uint32_t G = P.G;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint2 v[E];
-    uint2 loc = make_uint2(0, 0);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t i = threadIdx.x * E + e;
-        v[e] = i < G ? P.part[i] : make_uint2(0, 0);
-        loc = sat_add2(loc, v[e]);
-    }
-    const uint2 inc = wave_incl_scan_sat(loc);
-    if (lane == 63) sh[w] = inc;
-    __syncthreads();
-    uint2 pre = make_uint2(0, 0), tot = make_uint2(0, 0);
-    for (int i = 0; i < 16; ++i) {
-        const uint2 t = sh[i];
-        if (i < w) pre = sat_add2(pre, t);
-        tot = sat_add2(tot, t);
-    }
-    const uint32_t ex = __shfl_up(inc.x, 1, 64), ey = __shfl_up(inc.y, 1, 64);
-    uint2 run = lane ? sat_add2(pre, make_uint2(ex, ey)) : pre;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t i = threadIdx.x * E + e;
-        if (i < G) P.part[i] = run;
-        run = sat_add2(run, v[e]);
-    }
-    if (threadIdx.x == 0) {
-        if (mode == 0) {
-            P.ctr->Tm = tot.x;
-            P.ctr->Ts = tot.y;
-        } else {
-            P.ctr->N = tot.x;
-            if (tot.x > P.ctr->F) raise_err(P, kErrAlloc);
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // kernel: reservation cut
 // ---------------------------------------------------------------------------
@@ -948,8 +926,17 @@ __global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
     const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
     uint32_t r0, r1;
     rank_range(P.ctr->L, P.G, blk, &r0, &r1);
-    const uint32_t F = P.ctr->F, Tm = P.ctr->Tm;
-    uint2 carry = P.part[blk];
+    // reservations (merge, split) of the rank workgroups before this one,
+    // and the merge total: every workgroup sums the partials itself
+    uint2 before = make_uint2(0, 0), all = before;
+    for (uint32_t g = threadIdx.x; g < P.G; g += kBlock) {
+        const uint2 v = P.part[g];
+        all = sat_add2(all, v);
+        if (g < blk) before = sat_add2(before, v);
+    }
+    uint2 carry = block_reduce_sat2(before, sh2);
+    const uint32_t Tm = block_reduce_sat2(all, sh2).x;
+    const uint32_t F = P.ctr->F;
     uint32_t nm = 0, nlist = 0;
     uint32_t sn[kSeg];   // the next tile's segment, loaded a tile ahead
     load_seg(P, r0 + threadIdx.x * kSeg, r1, sn);
@@ -1146,7 +1133,14 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
     __shared__ uint32_t stage[kBlock * 32];
     Pool P;
     const uint32_t blk = pick<kB>(B, one, B.map_word, P);
-    const uint32_t N = P.ctr->N;
+    // N = the outputs of every owner (the sum of the owners' partials)
+    uint32_t n = 0;
+    for (uint32_t g = threadIdx.x; g < P.G; g += kBlock) n += P.part[g].x;
+    const uint32_t N = block_sum(n, sh);
+    if (blk == 0 && threadIdx.x == 0) {
+        P.ctr->N = N;
+        if (N > P.ctr->F) raise_err(P, kErrAlloc);
+    }
     const uint32_t w0 = blk * kWordsPerBlock;
     if (w0 >= P.W || N == 0) return;
     __shared__ uint32_t sb;
@@ -1313,13 +1307,14 @@ __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
     const uint8_t* inj;
     const uint32_t blk = pick_k<kB>(B, one, B.map_list, P, K, inj);
     (void)inj;
-    const ListShare ls = list_share(P, blk, base, sh);
-    const uint32_t N = P.ctr->N;
+    __shared__ uint32_t obase[kMaxRankGroups + 1];
+    const ListShare ls = list_share(P, blk, base, sh, obase);
+    const uint32_t N = obase[P.G];
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
         uint32_t w;
         const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
         const uint2 e = P.list[at];
-        const uint32_t off = P.part[w].x + P.lpre[at];
+        const uint32_t off = obase[w] + P.lpre[at];
         if (e.y & kMarks) fill_split<R>(P, K, e.x, e.y, off, N);
         else fill_merge<R>(P, e.x, e.y, off, N);
     }
@@ -1498,15 +1493,16 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
     __shared__ uint32_t base[kMaxRankGroups + 1];
     Pool P;
     const uint32_t blk = pick<kB>(B, one, B.map_list, P);
-    const ListShare ls = list_share(P, blk, base, sh);
-    const uint32_t N = P.ctr->N;
+    __shared__ uint32_t obase[kMaxRankGroups + 1];
+    const ListShare ls = list_share(P, blk, base, sh, obase);
+    const uint32_t N = obase[P.G];
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
         uint32_t w;
         const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
         const uint2 e = P.list[at];
         const int32_t b = (int32_t)e.x;
         const uint32_t c = e.y;
-        if (c & kMarks) resolve_split(P, b, c, P.part[w].x + P.lpre[at], N);
+        if (c & kMarks) resolve_split(P, b, c, obase[w] + P.lpre[at], N);
         else resolve_merge(P, b, c);
     }
 }
@@ -1855,7 +1851,6 @@ static hipError_t reduce_seq(const Launch& X, hipStream_t s)
 template <bool kB>
 static hipError_t enumerate_seq(const Launch& X, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_begin<kB>, dim3(X.n_inst), dim3(64), 0, s, X.B, X.one);
     hipLaunchKernelGGL(k_enumerate<kB>, dim3(X.grid_word), dim3(kBlock), 0, s, X.B, X.one);
     return hipGetLastError();
 }
@@ -1863,13 +1858,12 @@ static hipError_t enumerate_seq(const Launch& X, hipStream_t s)
 template <bool kB, typename R>
 static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* ev)
 {
-    const dim3 g(X.grid_rank), b(kBlock), gw(X.grid_word), gi(X.n_inst), gl(X.grid_list);
+    const dim3 g(X.grid_rank), b(kBlock), gw(X.grid_word), gl(X.grid_list);
     auto mark = [&](int stage, bool begin) {
         if (ev && ev->stage == stage) (void)hipEventRecord(begin ? ev->begin : ev->end, s);
     };
     enum { kEnum = 1, kClass, kVote, kBudget, kChain, kOwners, kOffsets, kFree, kFill, kResolve, kReduce, kFrame };
     mark(kFrame, true);
-    hipLaunchKernelGGL(k_begin<kB>, gi, dim3(64), 0, s, X.B, X.one);
     mark(kEnum, true);
     hipLaunchKernelGGL(k_enumerate<kB>, gw, b, 0, s, X.B, X.one);
     mark(kEnum, false);
@@ -1880,7 +1874,6 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL(k_vote<kB>, gl, b, 0, s, X.B, X.one);
     mark(kVote, false);
     mark(kBudget, true);
-    hipLaunchKernelGGL(k_scan_parts<kB>, gi, dim3(1024), 0, s, X.B, X.one, 0);
     hipLaunchKernelGGL(k_budget<kB>, g, b, 0, s, X.B, X.one);
     mark(kBudget, false);
     mark(kChain, true);
@@ -1889,9 +1882,6 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     mark(kOwners, true);
     hipLaunchKernelGGL(k_owners<kB>, g, b, 0, s, X.B, X.one);
     mark(kOwners, false);
-    mark(kOffsets, true);
-    hipLaunchKernelGGL(k_scan_parts<kB>, gi, dim3(1024), 0, s, X.B, X.one, 1);
-    mark(kOffsets, false);
     mark(kFree, true);
     hipLaunchKernelGGL(k_freelist<kB>, gw, b, 0, s, X.B, X.one);
     mark(kFree, false);
