@@ -58,7 +58,7 @@ namespace cbtk {
 // Ranks each thread of a rank-order pass loads before it processes them
 // (all rows' loads in flight at once: these passes are bound by the latency
 // of the rank -> block -> command chain, not by bandwidth).
-constexpr int kClassRows = 2;   // LOD test: 48 bytes of vertices per rank
+constexpr int kClassRows = 4;   // LOD test: 48 bytes of vertices per rank
 // The rank-order scans (budget, owners) give each thread kSeg consecutive
 // ranks: one workgroup scan per kBlock * kSeg ranks, and the segment of
 // rank-list entries is one pair of 16-byte loads.  Rank chunks are whole
@@ -353,16 +353,21 @@ __device__ __forceinline__ uint32_t list_at(const uint32_t* base, uint32_t G, ui
 // from r1 on read as block 0 (in bounds, unused)
 __device__ __forceinline__ void load_seg(const Pool& P, uint32_t t0, uint32_t r1, uint32_t (&s)[kSeg])
 {
-    static_assert(kSeg == 8, "two 16-byte loads per segment");
-    uint4 a = make_uint4(0, 0, 0, 0), b = a;
+    static_assert(kSeg % 4 == 0, "whole 16-byte loads per segment");
+    uint4 q[kSeg / 4];
+#pragma unroll
+    for (int i = 0; i < kSeg / 4; ++i) q[i] = make_uint4(0, 0, 0, 0);
     if (t0 < r1) {
         const uint4* p = reinterpret_cast<const uint4*>(P.live + t0);
-        a = p[0];
-        b = p[1];
-    }
-    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int j = 0; j < kSeg; ++j) s[j] = t0 + j < r1 ? v[j] : 0u;
+        for (int i = 0; i < kSeg / 4; ++i) q[i] = p[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kSeg / 4; ++i) {
+        const uint32_t v[4] = {q[i].x, q[i].y, q[i].z, q[i].w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[4 * i + k] = t0 + 4 * i + k < r1 ? v[k] : 0u;
+    }
 }
 
 __device__ __forceinline__ int ilog2_64(uint64_t x) { return 63 - __clzll((long long)x); }
@@ -1068,12 +1073,13 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
         // split owners from the command word alone; accepted merges (a few
         // per cent of the ranks) are checked one by one: a configuration
         // with a split-marked member stays (splits win)
-        uint32_t kk = 0;   // 4 bits of output count per rank
+        uint64_t kk = 0;   // 4 bits of output count per rank
+        static_assert(kSeg <= 16, "output counts of a segment in 64 bits");
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
             const uint32_t c = cr[j];
             if (c & kMarks) {
-                kk |= split_outputs(c) << (4 * j);
+                kk |= (uint64_t)split_outputs(c) << (4 * j);
                 ++nsc;
                 ++nfree;
             } else if (c & kMAcc) {
@@ -1082,7 +1088,7 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
                 if (m.w == 4) any = any || (P.cmd[m.y] & kMarks) || (P.cmd[m.z] & kMarks);
                 if (!any) {
                     cr[j] = c | kMExec;
-                    kk |= (m.w / 2) << (4 * j);
+                    kk |= (uint64_t)(m.w / 2) << (4 * j);
                     ++nexec;
                     nfree += m.w;
                 }
@@ -1091,7 +1097,7 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
         uint2 loc = make_uint2(0, 0);   // (owners, outputs) of this segment
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            const uint32_t k = (kk >> (4 * j)) & 15u;
+            const uint32_t k = (uint32_t)(kk >> (4 * j)) & 15u;
             loc = make_uint2(loc.x + (k ? 1u : 0u), loc.y + k);
         }
         uint2 tot;
@@ -1099,7 +1105,7 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
         uint32_t at = r0 + run.x + pre.x, outs = run.y + pre.y;
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            const uint32_t k = (kk >> (4 * j)) & 15u;
+            const uint32_t k = (uint32_t)(kk >> (4 * j)) & 15u;
             if (k) {
                 P.list[at] = make_uint2(sr[j], cr[j]);
                 P.lpre[at] = outs;
@@ -1418,12 +1424,46 @@ __device__ __forceinline__ void store_new(const Pool& P, uint32_t q, uint64_t id
     P.lf[q].l = make_int4(t, n, p, 0);
 }
 
-__device__ __forceinline__ void clear_bit(const Pool& P, uint32_t s)
+// Bits of consumed bisectors to clear, at most two bitfield words per work
+// item (a split bisector; or the two sibling pairs of a merge, each pair
+// usually in one word).  kNoWord: nothing.  Device-wide atomics are
+// expensive on a multi-die GPU (each goes past the die's L2), so the lanes
+// of a wave first merge the masks of equal words and one lane per word
+// clears them.
+constexpr uint32_t kNoWord = 0xffffffffu;
+struct Clears {
+    uint32_t w[2], m[2];
+};
+
+__device__ __forceinline__ void add_clear(const Pool& P, Clears& c, int slot, uint32_t s)
 {
-    atomicAnd(&P.bits[s >> 5], ~(1u << (s & 31u)));
+    const uint32_t w = s >> 5, m = 1u << (s & 31u);
+    if (c.w[slot] == kNoWord) {
+        c.w[slot] = w;
+        c.m[slot] = m;
+    } else if (c.w[slot] == w) {
+        c.m[slot] |= m;
+    } else {
+        atomicAnd(&P.bits[w], ~m);   // a pair split across two words
+    }
 }
 
-__device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t c, uint32_t base, uint32_t N)
+// Every lane of the wave calls this (convergent): a segmented OR over
+// neighbouring lanes with the same word, then one atomic per run of lanes.
+__device__ __forceinline__ void clear_bits_wave(const Pool& P, uint32_t w, uint32_t m)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t wo = __shfl_down(w, o, 64), mo = __shfl_down(m, o, 64);
+        if (lane + o < 64 && wo == w) m |= mo;
+    }
+    const uint32_t wp = __shfl_up(w, 1, 64);
+    if (w != kNoWord && (lane == 0 || wp != w)) atomicAnd(&P.bits[w], ~m);
+}
+
+__device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t c, uint32_t base, uint32_t N,
+                                              Clears& cl)
 {
     const int db = depth_of_cmd(c);
     const bool hn = c & kMarkN, hp = c & kMarkP;
@@ -1454,7 +1494,7 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
         store_new(P, f.w, 4 * x + 3, piece_target(P, nT, db, kHalf1, f.w), piece_target(P, nN, db, kHalf0, f.w),
                   (int32_t)f.z);
     }
-    clear_bit(P, (uint32_t)b);
+    add_clear(P, cl, 0, (uint32_t)b);
 }
 
 // Parents of an executed merge (owner b, the smallest member): a parent q of
@@ -1462,7 +1502,7 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
 // edge = c0's base edge and Twin = the other parent (or the border).  The
 // members' pointer records, then their base-edge neighbours, are loaded in
 // one round each; a border pair loads its own members twice (unused).
-__device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t c)
+__device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t c, Clears& cl)
 {
     const uint4 f = P.lf[b].f;   // (parent, sibling, other odd, other even)
     const uint64_t ida = P.id[b] >> 1;
@@ -1479,11 +1519,11 @@ __device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t
               piece_target(P, nb[1], d, kWhole, f.x));
     if (quad) {
         store_new(P, qb, idb, (int32_t)f.x, piece_target(P, nb[2], d, kWhole, qb), piece_target(P, nb[3], d, kWhole, qb));
-        clear_bit(P, f.z);
-        clear_bit(P, f.w);
+        add_clear(P, cl, 1, f.z);
+        add_clear(P, cl, 1, f.w);
     }
-    clear_bit(P, (uint32_t)b);
-    clear_bit(P, f.y);
+    add_clear(P, cl, 0, (uint32_t)b);
+    add_clear(P, cl, 0, f.y);
 }
 
 template <bool kB>
@@ -1496,14 +1536,21 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
     __shared__ uint32_t obase[kMaxRankGroups + 1];
     const ListShare ls = list_share(P, blk, base, sh, obase);
     const uint32_t N = obase[P.G];
-    for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
-        uint32_t w;
-        const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
-        const uint2 e = P.list[at];
-        const int32_t b = (int32_t)e.x;
-        const uint32_t c = e.y;
-        if (c & kMarks) resolve_split(P, b, c, obase[w] + P.lpre[at], N);
-        else resolve_merge(P, b, c);
+    // uniform trip count: the bit clears are merged across the wave
+    for (uint32_t i0 = ls.i0; i0 < ls.i1; i0 += kBlock) {
+        const uint32_t i = i0 + threadIdx.x;
+        Clears cl = {{kNoWord, kNoWord}, {0u, 0u}};
+        if (i < ls.i1) {
+            uint32_t w;
+            const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
+            const uint2 e = P.list[at];
+            const int32_t b = (int32_t)e.x;
+            const uint32_t c = e.y;
+            if (c & kMarks) resolve_split(P, b, c, obase[w] + P.lpre[at], N, cl);
+            else resolve_merge(P, b, c, cl);
+        }
+        clear_bits_wave(P, cl.w[0], cl.m[0]);
+        clear_bits_wave(P, cl.w[1], cl.m[1]);
     }
 }
 
