@@ -161,12 +161,14 @@ struct Launch {
 
 // per-instance grid sizes
 uint32_t word_groups(const Pool& P);
-// workgroups of the passes over the compacted work lists: half the rank
-// workgroups (at least 16).  Their loads are dependent and random; fewer
-// waves in flight measured faster than the rank passes' count
+// workgroups of the passes over the compacted work lists (and of the LOD
+// pass, two rank chunks each): half the rank workgroups rounded up, at
+// least 16.  Their loads are dependent and random; fewer waves in flight
+// measured faster than the rank passes' count
 __host__ __device__ inline uint32_t list_groups(const Pool& P)
 {
-    return P.G / 2 > 16u ? P.G / 2 : 16u;
+    const uint32_t h = (P.G + 1) / 2;
+    return h > 16u ? h : 16u;
 }
 uint32_t reduce_groups(const Pool& P);
 int reduce_levels(const Pool& P);

@@ -59,6 +59,10 @@ namespace cbtk {
 // (all rows' loads in flight at once: these passes are bound by the latency
 // of the rank -> block -> command chain, not by bandwidth).
 constexpr int kClassRows = 4;   // LOD test: 48 bytes of vertices per rank
+// The LOD pass runs on the list passes' grid (half the rank workgroups),
+// each of its workgroups taking two consecutive rank chunks: fewer, longer
+// streams of vertex records measured faster.
+constexpr uint32_t kClassChunks = 2;
 // The rank-order scans (budget, owners) give each thread kSeg consecutive
 // ranks: one workgroup scan per kBlock * kSeg ranks, and the segment of
 // rank-list entries is one pair of 16-byte loads.  Rank chunks are whole
@@ -733,105 +737,113 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
     Pool P;
     LodK K;
     const uint8_t* inj;
-    const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
-    uint32_t r0, r1;
-    rank_range(P.ctr->L, P.G, blk, &r0, &r1);
+    // each workgroup classifies kClassChunks consecutive rank chunks (the
+    // grid of the list passes), each chunk with its own partial and list
+    const uint32_t blk = pick_k<kB>(B, one, B.map_list, P, K, inj);
     const int maxd = 63 - P.k;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t nsplit = 0, nmerge = 0, scost = 0, nlist = 0, tile = 0;
-    // the rank entries of the next tile are loaded while this tile's
-    // records are in flight (past the chunk: block 0, in bounds, unused)
-    uint32_t sn[kClassRows];
-#pragma unroll
-    for (int j = 0; j < kClassRows; ++j) {
-        const uint32_t r = r0 + j * kBlock + threadIdx.x;
-        sn[j] = r < r1 ? P.live[r] : 0u;
-    }
-    for (uint32_t base = r0; base < r1; base += kBlock * kClassRows, ++tile) {
-        // every row's loads in flight before the first row is processed
-        uint32_t sr[kClassRows], dr[kClassRows];
-        T4<R> wa[kClassRows], wb[kClassRows], wc[kClassRows];
-        bool cand[kClassRows];
+    uint32_t nsplit = 0, nmerge = 0, ncand = 0, tile = 0;
+    for (uint32_t rb = blk * kClassChunks; rb < (blk + 1) * kClassChunks && rb < P.G; ++rb) {
+        uint32_t r0, r1;
+        rank_range(P.ctr->L, P.G, rb, &r0, &r1);
+        uint32_t scost = 0, nlist = 0;
+        // the rank entries of the next tile are loaded while this tile's
+        // records are in flight (past the chunk: block 0, in bounds, unused)
+        uint32_t sn[kClassRows];
 #pragma unroll
         for (int j = 0; j < kClassRows; ++j) {
-            sr[j] = sn[j];
-            const T4<R>* w = world_rec<R>(P, sr[j]);
-            wa[j] = w[0];
-            wb[j] = w[1];
-            wc[j] = w[2];
-        }
-#pragma unroll
-        for (int j = 0; j < kClassRows; ++j) {
-            const uint32_t r = base + (kClassRows + j) * kBlock + threadIdx.x;
+            const uint32_t r = r0 + j * kBlock + threadIdx.x;
             sn[j] = r < r1 ? P.live[r] : 0u;
         }
+        for (uint32_t base = r0; base < r1; base += kBlock * kClassRows, ++tile) {
+            // every row's loads in flight before the first row is processed
+            uint32_t sr[kClassRows], dr[kClassRows];
+            T4<R> wa[kClassRows], wb[kClassRows], wc[kClassRows];
+            bool cand[kClassRows];
 #pragma unroll
-        for (int j = 0; j < kClassRows; ++j) {
-            cand[j] = false;
-            dr[j] = 0;
-            const uint32_t r = base + j * kBlock + threadIdx.x;
-            if (r >= r1) continue;
-            const uint32_t s = sr[j];
-            const int d = w_int(wa[j].w);
-            dr[j] = (uint32_t)d;
-            uint32_t dec;
-            if (inj) {
-                dec = inj[s];
-                if (dec > kMerge) {
-                    raise_err(P, kErrDecision);
+            for (int j = 0; j < kClassRows; ++j) {
+                sr[j] = sn[j];
+                const T4<R>* w = world_rec<R>(P, sr[j]);
+                wa[j] = w[0];
+                wb[j] = w[1];
+                wc[j] = w[2];
+            }
+#pragma unroll
+            for (int j = 0; j < kClassRows; ++j) {
+                const uint32_t r = base + (kClassRows + j) * kBlock + threadIdx.x;
+                sn[j] = r < r1 ? P.live[r] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < kClassRows; ++j) {
+                cand[j] = false;
+                dr[j] = 0;
+                const uint32_t r = base + j * kBlock + threadIdx.x;
+                if (r >= r1) continue;
+                const uint32_t s = sr[j];
+                const int d = w_int(wa[j].w);
+                dr[j] = (uint32_t)d;
+                uint32_t dec;
+                if (inj) {
+                    dec = inj[s];
+                    if (dec > kMerge) {
+                        raise_err(P, kErrDecision);
+                        dec = kKeep;
+                    }
+                } else {
+                    dec = lod_decide<R>(K, ld3<R>(wa[j]), ld3<R>(wb[j]), ld3<R>(wc[j]));
+                }
+                if (dec == kMerge && d == 0) dec = kKeep;       // roots never merge
+                if (dec == kSplit && d + 1 > maxd) dec = kKeep; // index width
+                if ((uint32_t)d > 63u) {
+                    raise_err(P, kErrPointer);
                     dec = kKeep;
                 }
-            } else {
-                dec = lod_decide<R>(K, ld3<R>(wa[j]), ld3<R>(wb[j]), ld3<R>(wc[j]));
+                P.cmd[s] = dec | ((uint32_t)d << kDepthShift);
+                if (dec == kSplit) {
+                    ++nsplit;
+                    scost += 3u * (uint32_t)d + 4u;
+                } else if (dec == kMerge) {
+                    ++nmerge;
+                    // configurations are found from their even members (Alg. 4)
+                    cand[j] = (RecId<R>::low(wb[j]) & 1u) == 0;
+                }
             }
-            if (dec == kMerge && d == 0) dec = kKeep;       // roots never merge
-            if (dec == kSplit && d + 1 > maxd) dec = kKeep; // index width
-            if ((uint32_t)d > 63u) {
-                raise_err(P, kErrPointer);
-                dec = kKeep;
+            uint64_t m[kClassRows];
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int j = 0; j < kClassRows; ++j) {
+                m[j] = __ballot(cand[j]);
+                cnt += (uint32_t)__popcll(m[j]);
             }
-            P.cmd[s] = dec | ((uint32_t)d << kDepthShift);
-            if (dec == kSplit) {
-                ++nsplit;
-                scost += 3u * (uint32_t)d + 4u;
-            } else if (dec == kMerge) {
-                ++nmerge;
-                // configurations are found from their even members (Alg. 4)
-                cand[j] = (RecId<R>::low(wb[j]) & 1u) == 0;
+            if (lane == 0) wcnt[tile & 1][wv] = cnt;
+            __syncthreads();
+            uint32_t at = r0 + nlist, ttot = 0;
+#pragma unroll
+            for (int i = 0; i < kBlock / 64; ++i) {
+                const uint32_t t = wcnt[tile & 1][i];
+                at += i < wv ? t : 0u;
+                ttot += t;
             }
-        }
-        uint64_t m[kClassRows];
-        uint32_t cnt = 0;
 #pragma unroll
-        for (int j = 0; j < kClassRows; ++j) {
-            m[j] = __ballot(cand[j]);
-            cnt += (uint32_t)__popcll(m[j]);
+            for (int j = 0; j < kClassRows; ++j) {
+                if (cand[j]) P.list[at + lanes_below(m[j])] = make_uint2(sr[j], dr[j]);
+                at += (uint32_t)__popcll(m[j]);
+            }
+            nlist += ttot;
         }
-        if (lane == 0) wcnt[tile & 1][wv] = cnt;
-        __syncthreads();
-        uint32_t at = r0 + nlist, ttot = 0;
-#pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) {
-            const uint32_t t = wcnt[tile & 1][i];
-            at += i < wv ? t : 0u;
-            ttot += t;
+        const uint32_t c = block_sum(scost, sh);
+        if (threadIdx.x == 0) {
+            P.part[rb] = make_uint2(0, c);
+            P.lcnt[rb] = nlist;
         }
-#pragma unroll
-        for (int j = 0; j < kClassRows; ++j) {
-            if (cand[j]) P.list[at + lanes_below(m[j])] = make_uint2(sr[j], dr[j]);
-            at += (uint32_t)__popcll(m[j]);
-        }
-        nlist += ttot;
+        ncand += nlist;
     }
     const uint32_t a = block_sum(nsplit, sh);
     const uint32_t b = block_sum(nmerge, sh);
-    const uint32_t c = block_sum(scost, sh);
     if (threadIdx.x == 0) {
-        P.part[blk] = make_uint2(0, c);
-        P.lcnt[blk] = nlist;
         if (a) atomicAdd(&P.ctr->stat[kStSplitReq], a);
         if (b) atomicAdd(&P.ctr->stat[kStMergeReq], b);
-        if (nlist) atomicAdd(&P.ctr->stat[kStMergeCand], nlist);
+        if (ncand) atomicAdd(&P.ctr->stat[kStMergeCand], ncand);
     }
 }
 
@@ -1915,7 +1927,7 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL(k_enumerate<kB>, gw, b, 0, s, X.B, X.one);
     mark(kEnum, false);
     mark(kClass, true);
-    hipLaunchKernelGGL((k_classify<kB, R>), g, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL((k_classify<kB, R>), gl, b, 0, s, X.B, X.one);
     mark(kClass, false);
     mark(kVote, true);
     hipLaunchKernelGGL(k_vote<kB>, gl, b, 0, s, X.B, X.one);
