@@ -70,10 +70,11 @@ def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
         return (8.0 + vb) * L + 4.0 * R
     if stage == "vote":
         # per listed even member: its list entry (8) and pointer record (16),
-        # the commands of the three other members (12), the Prev pointer of
-        # the twin-side member (16) and two IDs for a cycle of four (16); per
-        # configuration found its forwarding record and command (20)
-        return 68.0 * st["merge_candidates"] + 20.0 * st["merge_configs"]
+        # the commands of the three other members (12) and the Prev pointer
+        # of the twin-side member (16); per unanimous configuration the two
+        # IDs each of its even members compares (32), its forwarding record
+        # and command (20)
+        return 52.0 * st["merge_candidates"] + 52.0 * st["merge_configs"]
     if stage == "fill":
         # owner entries (8 + 4); a split bisector's ID (8) and vertex record
         # (vb) read, its fate + forwarding written (20); per split output a

@@ -860,11 +860,18 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
 // edge) is the odd child of the parent's twin: the depths in the members'
 // command words decide, without their heap IDs.  The smallest ID of a
 // configuration is always an even member (c0 < c1), so configurations are
-// detected, once, from their even members.  The loads of each level are
-// issued together; c2..c4 receive the members' command words.
-__device__ __forceinline__ int merge_config_even(const Pool& P, int d, int4 l1, int32_t* j2o, int32_t* j3o,
-                                                 int32_t* j4o, uint32_t* c2, uint32_t* c3, uint32_t* c4)
+// detected, once, from their even members.
+//
+// A configuration merges only if every member decided MERGE (unanimity),
+// so each member's decision is checked as soon as its command word arrives
+// and the next level of loads is skipped on a refusal; the heap IDs that
+// pick the smallest member of a cycle of four are loaded for unanimous
+// cycles only.  Returns the configuration size (0: none that merges, or
+// not found from its smallest member).
+__device__ __forceinline__ int merge_vote_even(const Pool& P, uint32_t s, int d, int32_t* j2o, int32_t* j3o,
+                                               int32_t* j4o)
 {
+    const int4 l1 = P.lf[s].l;
     const int32_t j2 = l1.y, j3 = l1.z;
     if ((j2 >= 0 && !slot_ok(P, j2)) || (j3 >= 0 && !slot_ok(P, j3))) { raise_err(P, kErrPointer); return 0; }
     if (j2 < 0) return 0;
@@ -872,25 +879,23 @@ __device__ __forceinline__ int merge_config_even(const Pool& P, int d, int4 l1, 
     const uint32_t cm2 = P.cmd[j2];
     const int32_t j4 = P.lf[a3].l.z;
     const uint32_t cm3 = P.cmd[a3];
-    if (depth_of_cmd(cm2) != d) return 0;
+    const auto merges = [d](uint32_t c) { return depth_of_cmd(c) == d && (c & kDecMask) == kMerge; };
+    if (!merges(cm2)) return 0;
     *j2o = j2;
-    *c2 = cm2;
     if (j3 < 0) return 2;
-    if (depth_of_cmd(cm3) != d) return 0;
-    if (j4 < 0) return 0;
+    if (!merges(cm3) || j4 < 0) return 0;
     if (!slot_ok(P, j4)) { raise_err(P, kErrPointer); return 0; }
     const uint32_t cm4 = P.cmd[j4];
-    if (depth_of_cmd(cm4) != d) return 0;
+    if (!merges(cm4)) return 0;
+    if (P.id[j4] < P.id[s]) return 0;   // found from the cycle's smallest member
     *j3o = j3;
     *j4o = j4;
-    *c3 = cm3;
-    *c4 = cm4;
     return 4;
 }
 
-// A configuration merges only if every member decided MERGE (unanimity);
-// its reservation, one block per parent, is charged to the smallest member
-// (added to the partial of the rank workgroup that holds it).
+// A unanimous configuration's reservation, one block per parent, is charged
+// to the smallest member (added to the partial of the rank workgroup that
+// holds it).
 template <bool kB>
 __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
 {
@@ -905,12 +910,8 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
         const uint2 e = P.list[list_at(base, P.G, ls.chunk, i, &w)];   // (block, depth)
         const uint32_t s = e.x;
         int32_t j2 = -1, j3 = -1, j4 = -1;
-        uint32_t c2 = 0, c3 = 0, c4 = 0;
-        const int m = merge_config_even(P, (int)e.y, P.lf[s].l, &j2, &j3, &j4, &c2, &c3, &c4);
-        if (!m || (m == 4 && P.id[j4] < P.id[s])) continue;   // not the smallest member
-        bool ok = (c2 & kDecMask) == kMerge;
-        if (m == 4) ok = ok && (c3 & kDecMask) == kMerge && (c4 & kDecMask) == kMerge;
-        if (!ok) continue;
+        const int m = merge_vote_even(P, s, (int)e.y, &j2, &j3, &j4);
+        if (!m) continue;
         P.cmd[s] |= kMCfg | kMMin | kMUnan | (m == 4 ? kMQuad : 0u);
         P.lf[s].f = make_uint4((uint32_t)j2, (uint32_t)j3, (uint32_t)j4, (uint32_t)m);
         if (w != wres) {
