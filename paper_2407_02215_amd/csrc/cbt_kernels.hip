@@ -1062,6 +1062,18 @@ __device__ __forceinline__ uint32_t split_outputs(uint32_t cmd)
     return 2u + ((cmd & kMarkN) ? 1u : 0u) + ((cmd & kMarkP) ? 1u : 0u);
 }
 
+// Whether a member of an accepted configuration (the smallest member's
+// forwarding record: sibling, other odd, other even, size) is split-marked;
+// the members' command words are loaded together.
+__device__ __forceinline__ uint32_t merge_vetoed(const Pool& P, uint4 m)
+{
+    const bool quad = m.w == 4;
+    const uint32_t a = P.cmd[m.x];
+    const uint32_t b = quad ? P.cmd[m.y] : 0u;
+    const uint32_t c = quad ? P.cmd[m.z] : 0u;
+    return ((a | b | c) & kMarks) ? 1u : 0u;
+}
+
 template <bool kB>
 __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
 {
@@ -1083,11 +1095,15 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) cr[j] = t0 + j < r1 ? P.cmd[sr[j]] : 0u;
         load_seg(P, t0 + kBlock * kSeg, r1, sn);
-        // split owners from the command word alone; accepted merges (a few
-        // per cent of the ranks) are checked one by one: a configuration
-        // with a split-marked member stays (splits win)
+        // split owners from the command word alone; an accepted merge (a
+        // few per cent of the ranks) executes unless a member is split-marked
+        // (splits win).  The checks of a thread's first two accepted merges
+        // are issued together, so a wave waits for two levels of loads per
+        // tile rather than two per rank that holds a merge in some lane;
+        // further ones (rare) are checked one by one.
         uint64_t kk = 0;   // 4 bits of output count per rank
         static_assert(kSeg <= 16, "output counts of a segment in 64 bits");
+        uint32_t macc = 0;
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
             const uint32_t c = cr[j];
@@ -1096,11 +1112,39 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
                 ++nsc;
                 ++nfree;
             } else if (c & kMAcc) {
-                const uint4 m = P.lf[sr[j]].f;
-                bool any = (P.cmd[m.x] & kMarks) != 0;
-                if (m.w == 4) any = any || (P.cmd[m.y] & kMarks) || (P.cmd[m.z] & kMarks);
-                if (!any) {
-                    cr[j] = c | kMExec;
+                macc |= 1u << j;
+            }
+        }
+        if (macc) {
+            const int ja = __ffs(macc) - 1;
+            const uint32_t rest = macc & (macc - 1);
+            const int jb = rest ? __ffs(rest) - 1 : -1;
+            uint32_t sa = 0, sb = 0;
+#pragma unroll
+            for (int j = 0; j < kSeg; ++j) {
+                sa = j == ja ? sr[j] : sa;
+                sb = j == jb ? sr[j] : sb;
+            }
+            const uint4 ma = P.lf[sa].f;
+            const uint4 mb = jb >= 0 ? P.lf[sb].f : make_uint4(0, 0, 0, 0);
+            const uint32_t va = merge_vetoed(P, ma), vb = jb >= 0 ? merge_vetoed(P, mb) : 1u;
+#pragma unroll
+            for (int j = 0; j < kSeg; ++j) {
+                if (!((macc >> j) & 1u)) continue;
+                uint4 m;
+                uint32_t veto;
+                if (j == ja) {
+                    m = ma;
+                    veto = va;
+                } else if (j == jb) {
+                    m = mb;
+                    veto = vb;
+                } else {
+                    m = P.lf[sr[j]].f;
+                    veto = merge_vetoed(P, m);
+                }
+                if (!veto) {
+                    cr[j] |= kMExec;
                     kk |= (uint64_t)(m.w / 2) << (4 * j);
                     ++nexec;
                     nfree += m.w;
@@ -1316,6 +1360,59 @@ __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c
     }
 }
 
+// One loop step of a workgroup over the owner list regroups its items so
+// that split owners take the lowest threads (in list order), then merges,
+// then empty items: each wave then runs one of the two item paths (but the
+// wave at the boundary) instead of both one after the other.  An item is
+// (block, command word, first free-list position).  Every thread of the
+// workgroup calls this; returns whether this thread holds an item.
+struct OwnerStage {
+    uint32_t cnt[2][kBlock / 64];
+    uint4 item[kBlock];
+};
+
+__device__ __forceinline__ bool group_owners(OwnerStage& st, bool valid, uint3& it)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool split = valid && (it.y & kMarks);
+    const bool merge = valid && !(it.y & kMarks);
+    const uint64_t ms = __ballot(split), mm = __ballot(merge);
+    if (lane == 0) {
+        st.cnt[0][wv] = (uint32_t)__popcll(ms);
+        st.cnt[1][wv] = (uint32_t)__popcll(mm);
+    }
+    __syncthreads();
+    uint32_t ps = 0, ts = 0, pm = 0, tm = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+        const uint32_t a = st.cnt[0][i], b = st.cnt[1][i];
+        ps += i < wv ? a : 0u;
+        pm += i < wv ? b : 0u;
+        ts += a;
+        tm += b;
+    }
+    if (split) st.item[ps + lanes_below(ms)] = make_uint4(it.x, it.y, it.z, 0);
+    if (merge) st.item[ts + pm + lanes_below(mm)] = make_uint4(it.x, it.y, it.z, 0);
+    __syncthreads();
+    const bool got = threadIdx.x < ts + tm;
+    if (got) {
+        const uint4 v = st.item[threadIdx.x];
+        it = make_uint3(v.x, v.y, v.z);
+    }
+    __syncthreads();   // the stage is reused by the next step
+    return got;
+}
+
+// the owner-list item of entry i of this workgroup's share
+__device__ __forceinline__ uint3 owner_item(const Pool& P, const uint32_t* base, const uint32_t* obase, uint32_t chunk,
+                                            uint32_t i)
+{
+    uint32_t w;
+    const uint32_t at = list_at(base, P.G, chunk, i, &w);
+    const uint2 e = P.list[at];
+    return make_uint3(e.x, e.y, obase[w] + P.lpre[at]);
+}
+
 template <bool kB, typename R>
 __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
 {
@@ -1329,13 +1426,14 @@ __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
     __shared__ uint32_t obase[kMaxRankGroups + 1];
     const ListShare ls = list_share(P, blk, base, sh, obase);
     const uint32_t N = obase[P.G];
-    for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
-        uint32_t w;
-        const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
-        const uint2 e = P.list[at];
-        const uint32_t off = obase[w] + P.lpre[at];
-        if (e.y & kMarks) fill_split<R>(P, K, e.x, e.y, off, N);
-        else fill_merge<R>(P, e.x, e.y, off, N);
+    __shared__ OwnerStage st;
+    for (uint32_t i0 = ls.i0; i0 < ls.i1; i0 += kBlock) {   // uniform trip count
+        const uint32_t i = i0 + threadIdx.x;
+        uint3 it = make_uint3(0, 0, 0);
+        if (i < ls.i1) it = owner_item(P, base, obase, ls.chunk, i);
+        if (!group_owners(st, i < ls.i1, it)) continue;
+        if (it.y & kMarks) fill_split<R>(P, K, it.x, it.y, it.z, N);
+        else fill_merge<R>(P, it.x, it.y, it.z, N);
     }
 }
 
@@ -1549,18 +1647,18 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
     __shared__ uint32_t obase[kMaxRankGroups + 1];
     const ListShare ls = list_share(P, blk, base, sh, obase);
     const uint32_t N = obase[P.G];
-    // uniform trip count: the bit clears are merged across the wave
+    __shared__ OwnerStage st;
+    // uniform trip count: items are regrouped across the workgroup and the
+    // bit clears merged across the wave
     for (uint32_t i0 = ls.i0; i0 < ls.i1; i0 += kBlock) {
         const uint32_t i = i0 + threadIdx.x;
+        uint3 it = make_uint3(0, 0, 0);
+        if (i < ls.i1) it = owner_item(P, base, obase, ls.chunk, i);
+        const bool got = group_owners(st, i < ls.i1, it);
         Clears cl = {{kNoWord, kNoWord}, {0u, 0u}};
-        if (i < ls.i1) {
-            uint32_t w;
-            const uint32_t at = list_at(base, P.G, ls.chunk, i, &w);
-            const uint2 e = P.list[at];
-            const int32_t b = (int32_t)e.x;
-            const uint32_t c = e.y;
-            if (c & kMarks) resolve_split(P, b, c, obase[w] + P.lpre[at], N, cl);
-            else resolve_merge(P, b, c, cl);
+        if (got) {
+            if (it.y & kMarks) resolve_split(P, (int32_t)it.x, it.y, it.z, N, cl);
+            else resolve_merge(P, (int32_t)it.x, it.y, cl);
         }
         clear_bits_wave(P, cl.w[0], cl.m[0]);
         clear_bits_wave(P, cl.w[1], cl.m[1]);
