@@ -1277,13 +1277,14 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
 {
     using V = Vec3<R>;
     const bool hn = c & kMarkN, hp = c & kMarkP;
+    // world positions and heap ID: the vertex record, loaded with the
+    // outputs' blocks; flat vertices: the Alg. 2 decode of the ID (no memory
+    // beyond the root table)
+    const T4<R>* wv = world_rec<R>(P, s);
+    const T4<R> ra = wv[0], rb = wv[1], rc = wv[2];
     uint4 f;
     if (!split_targets(P, c, base, N, &f)) return;
     const int d = depth_of_cmd(c);
-    // world positions and heap ID: the vertex record; flat vertices: the
-    // Alg. 2 decode of the ID (no memory beyond the root table)
-    const T4<R>* wv = world_rec<R>(P, s);
-    const T4<R> ra = wv[0], rb = wv[1], rc = wv[2];
     const uint64_t x = RecId<R>::get(rb, rc);
     V v0, v1, v2;
     decode<R>(P, x, d, v0, v1, v2);
@@ -1318,13 +1319,18 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
 template <typename R>
 __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c, uint32_t base, uint32_t N)
 {
+    // the smallest member's record and first free block are loaded with
+    // its forwarding record, the other members' records after it
+    if (base + 1u > N) { raise_err(P, kErrAlloc); return; }
+    const T4<R>* e0 = world_rec<R>(P, s);
+    const T4<R> a0 = e0[0], b0 = e0[1], c0 = e0[2];
+    uint32_t qa = P.freel[base], qb = 0xffffffffu;
     const uint4 m = P.lf[s].f;   // (sibling, other odd, other even, members)
     const bool quad = m.w == 4;
-    if (base + (quad ? 2u : 1u) > N) { raise_err(P, kErrAlloc); return; }
+    if (quad && base + 2u > N) { raise_err(P, kErrAlloc); return; }
     if (m.x >= P.cap || (quad && (m.y >= P.cap || m.z >= P.cap))) { raise_err(P, kErrPointer); return; }
-    const T4<R>* e0 = world_rec<R>(P, s);
     const T4<R>* o0 = world_rec<R>(P, m.x);
-    const T4<R> a0 = e0[0], b0 = e0[1], c0 = e0[2], d0 = o0[1];
+    const T4<R> d0 = o0[1];
     const uint64_t ida = RecId<R>::get(b0, c0) >> 1;
     T4<R> a1 = a0, b1 = b0, c1 = c0, d1 = d0;
     uint64_t idb = 0;
@@ -1337,7 +1343,6 @@ __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c
         d1 = o1[1];
         idb = RecId<R>::get(b1, c1) >> 1;
     }
-    uint32_t qa = P.freel[base], qb = 0xffffffffu;
     if (quad) {
         const uint32_t q1 = P.freel[base + 1];
         const bool a_first = ida < idb;
@@ -1425,7 +1430,9 @@ __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
     (void)inj;
     __shared__ uint32_t obase[kMaxRankGroups + 1];
     const ListShare ls = list_share(P, blk, base, sh, obase);
-    const uint32_t N = obase[P.G];
+    // outputs past the free blocks (an over-committed frame, flagged by the
+    // free-list pass) are refused, so free-list reads stay below F
+    const uint32_t N = min(obase[P.G], P.ctr->F);
     __shared__ OwnerStage st;
     for (uint32_t i0 = ls.i0; i0 < ls.i1; i0 += kBlock) {   // uniform trip count
         const uint32_t i = i0 + threadIdx.x;
@@ -1578,10 +1585,10 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
 {
     const int db = depth_of_cmd(c);
     const bool hn = c & kMarkN, hp = c & kMarkP;
+    const uint64_t x = P.id[b];   // loaded with the outputs' blocks
+    const int4 lb = P.lf[b].l;
     uint4 f;   // the outputs' blocks, from the free list as the fill took them
     if (!split_targets(P, c, base, N, &f)) return;
-    const uint64_t x = P.id[b];
-    const int4 lb = P.lf[b].l;
     const int32_t own[3] = {b, b, b};
     const int32_t across[3] = {lb.x, lb.y, lb.z};
     Nb nb[3];
@@ -1619,6 +1626,11 @@ __device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t
     const uint64_t ida = P.id[b] >> 1;
     const int d = depth_of_cmd(c);
     const bool quad = (c & kMQuad) != 0;
+    // a record the fill did not rewrite (its allocation failed) is refused
+    if (f.x >= P.cap || f.y >= P.cap || (quad && (f.z >= P.cap || f.w >= P.cap))) {
+        raise_err(P, kErrAlloc);
+        return;
+    }
     const uint32_t e2 = quad ? f.w : (uint32_t)b, o2 = quad ? f.z : f.y;
     const uint32_t qb = P.lf[e2].f.x;            // the second parent
     const uint64_t idb = P.id[e2] >> 1;
@@ -1646,7 +1658,9 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
     const uint32_t blk = pick<kB>(B, one, B.map_list, P);
     __shared__ uint32_t obase[kMaxRankGroups + 1];
     const ListShare ls = list_share(P, blk, base, sh, obase);
-    const uint32_t N = obase[P.G];
+    // outputs past the free blocks (an over-committed frame, flagged by the
+    // free-list pass) are refused, so free-list reads stay below F
+    const uint32_t N = min(obase[P.G], P.ctr->F);
     __shared__ OwnerStage st;
     // uniform trip count: items are regrouped across the workgroup and the
     // bit clears merged across the wave
