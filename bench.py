@@ -104,6 +104,43 @@ SURVEY_STAGES = ("classify", "vote", "fill", "resolve")          # stages with a
 EXTRA_STAGES = ("enumerate", "budget", "chain", "owners", "freelist", "reduce")
 
 
+def random_calibration() -> dict:
+    """The rate at which this GPU serves random line reads, the pattern of
+    the pointer passes: gathers of 4-byte elements at uniformly random
+    positions of a 2 GiB array (each element its own 128-byte line) and of
+    whole 128-byte rows at random, timed with HIP events (torch's gather
+    kernel; indices and outputs are sequential and small beside the lines)."""
+    import torch
+    n = 512 << 20                      # floats: 2 GiB
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    rows = x.view(-1, 32)              # 128-byte rows
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    m = 16 << 20
+    idx = torch.randint(0, n, (m,), device="cuda", generator=g)
+    ridx = torch.randint(0, rows.shape[0], (m // 4,), device="cuda", generator=g)
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e-3
+
+    t_el = timed(lambda: torch.index_select(x, 0, idx))
+    t_row = timed(lambda: torch.index_select(rows, 0, ridx))
+    return {"random_element_gather": {"elements": m, "ms": t_el * 1e3, "lines_per_s": m / t_el,
+                                      "line_gbs": m * 128 / t_el / 1e9},
+            "random_row_gather": {"rows": m // 4, "ms": t_row * 1e3, "lines_per_s": m / 4 / t_row,
+                                  "line_gbs": m / 4 * 128 / t_row / 1e9,
+                                  "read_plus_write_gbs": m / 4 * 256 / t_row / 1e9}}
+
+
 def percentile(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs, np.float64), q)) if len(xs) else None
@@ -489,7 +526,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 256 MiB device copies (scale of the HBM byte counters)")
+    ap.add_argument("--random-calibration", action="store_true",
+                    help="only time gathers at random positions (the rate of random 128-byte line reads)")
     args = ap.parse_args()
+    if args.random_calibration:
+        print(json.dumps(random_calibration()), flush=True)
+        return
     if args.copy_calibration:
         import torch
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
