@@ -216,7 +216,7 @@ cbt_status cbth::validate_mesh(const cbt_mesh* m)
 // vertices.  The mean is accumulated once per face, from the face's smallest
 // halfedge index along Next, in binary32, then divided by the side count, so
 // every root of a face shares the same bits (watertight shared edges).
-static void root_triangles(const cbt_mesh* m, std::vector<float>& out)
+void cbth::root_triangles(const cbt_mesh* m, std::vector<float>& out)
 {
     const int32_t H = m->H;
     out.assign(9 * (size_t)H, 0.0f);
@@ -308,21 +308,31 @@ cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace, siz
     return cbt_init_ex(mesh, D, 0, device_workspace, workspace_bytes, hip_stream, out);
 }
 
-cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* device_workspace,
-                       size_t workspace_bytes, void* hip_stream, cbt_handle* out)
+// Handle set-up shared by cbt_init_ex and the server's admissions.  With
+// base set, the pool receives the base mesh (Section 3.3, "Initialization")
+// and the call synchronises; without it (an import of live records follows
+// on the same stream, which clears and fills the pool) only the root
+// triangles are uploaded, from roots_cached when given (a host array that
+// outlives the upload), and nothing waits.
+static cbt_status init_impl(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* device_workspace,
+                            size_t workspace_bytes, void* hip_stream, cbt_handle* out, bool base,
+                            const float* roots_cached, bool validated)
 {
     if (!out) return fail(nullptr, CBT_E_ARG, "output handle pointer is NULL");
     *out = nullptr;
     if (flags & ~(uint32_t)CBT_INIT_FP64) return fail(nullptr, CBT_E_ARG, "unknown init flags 0x%x", flags);
     const int32_t f64 = (flags & CBT_INIT_FP64) ? 1 : 0;
-    cbt_status st = cbth::validate_mesh(mesh);
-    if (st) return st;
+    if (!validated) {
+        cbt_status st = cbth::validate_mesh(mesh);
+        if (st) return st;
+    }
     const int k = ceil_log2(mesh->H);
     if (D < 5 || D > 30 || D < k) return fail(nullptr, CBT_E_DEPTH, "depth %d outside [max(5, ceil(log2 H)=%d), 30]", D, k);
     const size_t need = cbtk::workspace_layout(mesh->H, D, f64, nullptr, nullptr);
     if (!device_workspace) return fail(nullptr, CBT_E_ARG, "device workspace is NULL");
     if (reinterpret_cast<uintptr_t>(device_workspace) & 255) return fail(nullptr, CBT_E_ARG, "workspace must be 256-byte aligned");
     if (workspace_bytes < need) return fail(nullptr, CBT_E_BUDGET, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    if (roots_cached && f64) return fail(nullptr, CBT_E_ARG, "cached root triangles are binary32");
 
     cbt_instance* h = new (std::nothrow) cbt_instance();
     if (!h) return fail(nullptr, CBT_E_ARG, "out of host memory");
@@ -339,31 +349,23 @@ cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* de
         return fail(nullptr, CBT_E_DEVICE, "pinned host allocation failed");
     }
     std::memset(h->hctr, 0, sizeof(Counters));
+    std::memset(&h->wk, 0, sizeof h->wk);   // flat world positions until LOD parameters arrive
 
-    // Section 3.3 "Initialization": roots in blocks 0..H-1, packed as
-    // (id low, id high, twin, next, prev)
     const int32_t H = mesh->H;
-    std::vector<uint32_t> recs(5 * (size_t)H);
-    for (int32_t i = 0; i < H; ++i) {
-        const uint64_t id = (uint64_t(1) << k) + (uint64_t)i;
-        recs[5 * (size_t)i + 0] = (uint32_t)id;
-        recs[5 * (size_t)i + 1] = (uint32_t)(id >> 32);
-        recs[5 * (size_t)i + 2] = (uint32_t)mesh->twin[i];
-        recs[5 * (size_t)i + 3] = (uint32_t)mesh->next[i];
-        recs[5 * (size_t)i + 4] = (uint32_t)mesh->prev[i];
-    }
-    std::vector<uint32_t> words((H + 31) / 32, 0u);
-    for (int32_t i = 0; i < H; ++i) words[i >> 5] |= 1u << (i & 31);
     std::vector<float> roots;
     std::vector<double> roots64;
-    if (f64) root_triangles64(mesh, roots64);
-    else root_triangles(mesh, roots);
-
+    if (!roots_cached) {
+        if (f64) root_triangles64(mesh, roots64);
+        else cbth::root_triangles(mesh, roots);
+    }
+    const void* root_src = roots_cached ? static_cast<const void*>(roots_cached)
+                           : f64        ? static_cast<const void*>(roots64.data())
+                                        : static_cast<const void*>(roots.data());
+    const size_t root_bytes = 9 * (size_t)H * (f64 ? sizeof(double) : sizeof(float));
     const Pool& P = h->P;
     hipStream_t s = h->stream;
-    // the vertex-cache region (48 bytes per block, cap >= H) stages the roots
-    uint32_t* staging = reinterpret_cast<uint32_t*>(P.vworld);
     cbt_status rc = CBT_OK;
+    std::vector<uint32_t> recs;
 #define INIT_TRY(expr, what)                      \
     do {                                          \
         hipError_t e_ = (expr);                   \
@@ -372,33 +374,32 @@ cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* de
             goto init_fail;                       \
         }                                         \
     } while (0)
-    INIT_TRY(hipMemsetAsync(P.id, 0, sizeof(uint64_t) * P.cap, s), "clear IDs");
-    INIT_TRY(hipMemset2DAsync(&P.lf[0].l, sizeof(cbtk::LinkFwd), 0, sizeof(int4), P.cap, s), "clear pointers");
-    INIT_TRY(hipMemset2DAsync(&P.lf[0].f, sizeof(cbtk::LinkFwd), 0xff, sizeof(uint4), P.cap, s), "clear forwarding");
-    INIT_TRY(hipMemsetAsync(P.lpre, 0, sizeof(uint32_t) * P.cap, s), "clear list offsets");
-    INIT_TRY(hipMemsetAsync(P.bits, 0, sizeof(uint32_t) * P.W, s), "clear bitfield");
-    INIT_TRY(hipMemsetAsync(P.cmd, 0, sizeof(uint32_t) * P.cap, s), "clear commands");
-    INIT_TRY(hipMemsetAsync(P.live, 0, sizeof(uint32_t) * P.cap, s), "clear rank list");
-    INIT_TRY(hipMemsetAsync(P.freel, 0, sizeof(uint32_t) * P.cap, s), "clear free list");
-    INIT_TRY(hipMemsetAsync(P.list, 0, sizeof(uint2) * P.cap, s), "clear work lists");
-    INIT_TRY(hipMemsetAsync(P.lcnt, 0, sizeof(uint32_t) * cbtk::kMaxRankGroups, s), "clear list lengths");
-    INIT_TRY(hipMemsetAsync(P.part, 0, sizeof(uint2) * cbtk::kMaxRankGroups, s), "clear partials");
-    INIT_TRY(hipMemsetAsync(P.ctr, 0, sizeof(Counters), s), "clear counters");
-    INIT_TRY(hipMemcpyAsync(staging, recs.data(), sizeof(uint32_t) * recs.size(), hipMemcpyHostToDevice, s), "upload roots");
-    INIT_TRY(cbtk::launch_import_records(P, 0, (uint32_t)H, staging, s), "root records");
-    INIT_TRY(hipMemsetAsync(P.vworld, 0, (f64 ? sizeof(double4) : sizeof(float4)) * 3 * (size_t)P.cap, s),
-             "clear vertex cache");
-    INIT_TRY(hipMemcpyAsync(P.bits, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice, s), "upload bits");
-    if (f64)
-        INIT_TRY(hipMemcpyAsync(P.root, roots64.data(), sizeof(double) * roots64.size(), hipMemcpyHostToDevice, s),
-                 "upload root triangles");
-    else
-        INIT_TRY(hipMemcpyAsync(P.root, roots.data(), sizeof(float) * roots.size(), hipMemcpyHostToDevice, s),
-                 "upload root triangles");
-    std::memset(&h->wk, 0, sizeof h->wk);   // flat world positions until LOD parameters arrive
-    INIT_TRY(cbtk::launch_reduce(cbtk::single_launch(P, h->wk, nullptr), s), "sum reduction");
-    INIT_TRY(cbtk::launch_refresh(cbtk::single_launch(P, h->wk, nullptr), s), "vertex cache");
-    INIT_TRY(hipStreamSynchronize(s), "init synchronise");
+    INIT_TRY(hipMemcpyAsync(P.root, root_src, root_bytes, hipMemcpyHostToDevice, s), "upload root triangles");
+    if (base) {
+        // roots in blocks 0..H-1, packed as (id low, id high, twin, next,
+        // prev) and staged in the vertex-cache region (48 bytes per block,
+        // cap >= H); the bitfield follows from the IDs
+        recs.resize(5 * (size_t)H);
+        for (int32_t i = 0; i < H; ++i) {
+            const uint64_t id = (uint64_t(1) << k) + (uint64_t)i;
+            recs[5 * (size_t)i + 0] = (uint32_t)id;
+            recs[5 * (size_t)i + 1] = (uint32_t)(id >> 32);
+            recs[5 * (size_t)i + 2] = (uint32_t)mesh->twin[i];
+            recs[5 * (size_t)i + 3] = (uint32_t)mesh->next[i];
+            recs[5 * (size_t)i + 4] = (uint32_t)mesh->prev[i];
+        }
+        uint32_t* staging = reinterpret_cast<uint32_t*>(P.vworld);
+        INIT_TRY(cbtk::launch_clear_pool(P, s), "clear pool");
+        INIT_TRY(hipMemcpyAsync(staging, recs.data(), sizeof(uint32_t) * recs.size(), hipMemcpyHostToDevice, s),
+                 "upload roots");
+        INIT_TRY(cbtk::launch_import_records(P, 0, (uint32_t)H, staging, s), "root records");
+        INIT_TRY(cbtk::launch_bits_from_ids(P, s), "bitfield");
+        INIT_TRY(cbtk::launch_reduce(cbtk::single_launch(P, h->wk, nullptr), s), "sum reduction");
+        INIT_TRY(cbtk::launch_refresh(cbtk::single_launch(P, h->wk, nullptr), s), "vertex cache");
+        INIT_TRY(hipStreamSynchronize(s), "init synchronise");
+    } else if (!roots_cached) {
+        INIT_TRY(hipStreamSynchronize(s), "init synchronise");   // the local root array goes out of scope
+    }
 #undef INIT_TRY
     *out = h;
     return CBT_OK;
@@ -407,6 +408,12 @@ init_fail:
     cbth::release_counters(h->hctr);
     delete h;
     return rc;
+}
+
+cbt_status cbt_init_ex(const cbt_mesh* mesh, int32_t D, uint32_t flags, void* device_workspace,
+                       size_t workspace_bytes, void* hip_stream, cbt_handle* out)
+{
+    return init_impl(mesh, D, flags, device_workspace, workspace_bytes, hip_stream, out, true, nullptr, false);
 }
 
 static cbt_status read_counters(cbt_handle h)
@@ -761,9 +768,7 @@ cbt_status cbt_import_live(cbt_handle h, const uint32_t* records, int64_t count,
     const Pool& P = h->P;
     if (count < 1 || count > (int64_t)P.cap) return fail(h, CBT_E_ARG, "record count %lld outside [1, 2^D]", (long long)count);
     hipStream_t s = h->stream;
-    HIP_TRY(h, hipMemsetAsync(P.id, 0, sizeof(uint64_t) * P.cap, s), "clear IDs");
-    HIP_TRY(h, hipMemset2DAsync(&P.lf[0].l, sizeof(cbtk::LinkFwd), 0, sizeof(int4), P.cap, s), "clear pointers");
-    HIP_TRY(h, hipMemset2DAsync(&P.lf[0].f, sizeof(cbtk::LinkFwd), 0xff, sizeof(uint4), P.cap, s), "clear forwarding");
+    HIP_TRY(h, cbtk::launch_clear_pool(P, s), "clear pool");
     if (on_host) {
         size_t scratch_bytes;
         uint32_t* scratch = reinterpret_cast<uint32_t*>(list_scratch(P, &scratch_bytes));
@@ -829,3 +834,9 @@ const char* cbt_status_string(cbt_status s)
 const char* cbt_last_error(cbt_handle h) { return h ? h->err : g_err; }
 
 }  // extern "C"
+
+cbt_status cbth::init_for_import(const cbt_mesh* mesh, int32_t D, void* device_workspace, size_t workspace_bytes,
+                                 void* hip_stream, const float* roots, cbt_handle* out)
+{
+    return init_impl(mesh, D, 0, device_workspace, workspace_bytes, hip_stream, out, false, roots, true);
+}

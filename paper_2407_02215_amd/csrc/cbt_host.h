@@ -27,6 +27,13 @@ namespace cbth {
 cbt_status fail(cbt_handle h, cbt_status st, const char* fmt, ...);
 cbt_status hip_fail(cbt_handle h, hipError_t e, const char* what);
 cbt_status validate_mesh(const cbt_mesh* m);
+// root triangles (Alg. 1) of a validated mesh, 9 floats per halfedge
+void root_triangles(const cbt_mesh* m, std::vector<float>& out);
+// a binary32 handle on a validated mesh whose pool an import of live
+// records (cbt_import_live, same stream) fills next: the root triangles are
+// uploaded from roots (kept alive by the caller) and nothing waits
+cbt_status init_for_import(const cbt_mesh* mesh, int32_t D, void* device_workspace, size_t workspace_bytes,
+                           void* hip_stream, const float* roots, cbt_handle* out);
 cbt_status check_lod(cbt_handle h, const cbt_camera* c, const cbt_lod_params* lp);
 void make_lodk(const cbt_camera* c, const cbt_lod_params* lp, cbtk::LodK* K);
 // the world-position parameters differ from those the vertex cache holds

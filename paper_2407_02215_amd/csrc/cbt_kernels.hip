@@ -1766,6 +1766,29 @@ __global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
     }
 }
 
+// Clears a pool before it is filled: heap IDs, pointer and forwarding
+// records, command words, the per-workgroup partials and list lengths and
+// the counters, in one launch.  The rank, free and work lists and the
+// vertex cache are written before they are read in every frame and are
+// left as they are.
+__global__ void k_clear_pool(Pool P)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < P.cap; s += stride) {
+        P.id[s] = 0;
+        P.lf[s].l = make_int4(0, 0, 0, 0);
+        P.lf[s].f = make_uint4(~0u, ~0u, ~0u, ~0u);
+        P.cmd[s] = 0;
+    }
+    if (blockIdx.x == 0) {
+        for (uint32_t g = threadIdx.x; g < (uint32_t)kMaxRankGroups; g += blockDim.x) {
+            P.lcnt[g] = 0;
+            P.part[g] = make_uint2(0, 0);
+        }
+        if (threadIdx.x == 0) *P.ctr = Counters{};
+    }
+}
+
 __global__ void k_bits_from_ids(Pool P)
 {
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2125,6 +2148,13 @@ hipError_t launch_gather_counters(const Launch& X, Counters* out, hipStream_t s)
 {
     if (X.batched && X.n_inst)
         hipLaunchKernelGGL(k_gather_counters, dim3(cdiv(X.n_inst, kBlock)), dim3(kBlock), 0, s, X.B, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_pool(const Pool& P, hipStream_t s)
+{
+    const uint32_t blocks = cdiv(P.cap, kBlock) < 4096u ? cdiv(P.cap, kBlock) : 4096u;
+    hipLaunchKernelGGL(k_clear_pool, dim3(blocks), dim3(kBlock), 0, s, P);
     return hipGetLastError();
 }
 

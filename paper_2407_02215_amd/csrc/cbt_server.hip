@@ -42,6 +42,7 @@ struct SInst {
     int64_t id = 0;
     std::vector<int32_t> twin, next, prev, vert;
     std::vector<float> pos;
+    std::vector<float> roots;   // root triangles, computed once at open
     int32_t H = 0, V = 0, D = 0;
     cbt_lod_params lod{};
     int32_t groups = 0, levels = 0;   // schedule (0: library default)
@@ -266,7 +267,11 @@ cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
     const double t0 = now_s();
     cbt_mesh m{I.H, I.twin.data(), I.next.data(), I.prev.data(), I.vert.data(), I.V, I.pos.data()};
     cbt_handle h = nullptr;
-    cbt_status st = cbt_init(&m, I.D, inst_ptr(s, off), bytes, s->aux, &h);
+    // an evicted instance comes back from its live records: the base mesh
+    // is not built first (the import clears and fills the pool)
+    cbt_status st = I.snap == SInst::kNoSnap
+                        ? cbt_init(&m, I.D, inst_ptr(s, off), bytes, s->aux, &h)
+                        : cbth::init_for_import(&m, I.D, inst_ptr(s, off), bytes, s->aux, I.roots.data(), &h);
     if (st) {
         arena_free(s, off, bytes);
         I.failed = true;
@@ -363,10 +368,20 @@ cbt_status launch_slot(cbt_server s, Slot& S)
     std::vector<SInst*> pick;
     std::vector<int64_t> pinned;
     uint64_t nr = 0, nw = 0, nd = 0, nl = 0;
+    // Once one admission of this pass has found no memory (after evicting
+    // every idle instance it could), the other non-resident candidates wait
+    // for a later pass; resident ones are still picked.  Without this, a
+    // backlog made every launch retry every waiting admission, each scanning
+    // all instances.
+    bool no_memory = false;
     for (SInst* I : cand) {
         if ((int32_t)pick.size() >= s->cfg.max_batch) break;
+        if (!I->h && no_memory) continue;
         cbt_status st = admit(s, *I, pinned);
-        if (st == CBT_E_BUDGET && !I->failed) continue;   // waits for memory
+        if (st == CBT_E_BUDGET && !I->failed) {   // waits for memory
+            no_memory = true;
+            continue;
+        }
         if (st) {
             while (!I->q.empty()) {
                 complete(s, *I, I->q.front(), st, nullptr, now_s(), 0, now_s());
@@ -582,6 +597,7 @@ cbt_status cbt_server_open(cbt_server s, const cbt_mesh* mesh, int32_t D, const 
     I.prev.assign(mesh->prev, mesh->prev + mesh->H);
     I.vert.assign(mesh->vert, mesh->vert + mesh->H);
     I.pos.assign(mesh->pos, mesh->pos + 3 * (size_t)mesh->V);
+    cbth::root_triangles(mesh, I.roots);
     I.last_used = now_s();
     const int64_t id = I.id;
     s->inst.emplace(id, std::move(I));
