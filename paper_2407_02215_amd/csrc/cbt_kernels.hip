@@ -296,7 +296,7 @@ struct ListShare {
 // pass leaves) are scanned the same way: obase[w] = outputs of the rank
 // workgroups before w, obase[G] = N.
 __device__ __forceinline__ ListShare list_share(const Pool& P, uint32_t blk, uint32_t* base, uint32_t* sh,
-                                                uint32_t* obase = nullptr)
+                                                uint32_t* obase = nullptr, uint32_t GL = 0)
 {
     constexpr int E = kMaxRankGroups / kBlock;
     const uint32_t G = P.G;
@@ -327,7 +327,7 @@ __device__ __forceinline__ ListShare list_share(const Pool& P, uint32_t blk, uin
         if (obase) obase[G] = otot;
     }
     __syncthreads();
-    const uint32_t GL = list_groups(P);
+    if (!GL) GL = list_groups(P);   // the workgroups sharing the list
     const uint32_t per = (tot + GL - 1) / GL;
     const uint64_t a = (uint64_t)blk * per, b = a + per;
     ListShare s;
@@ -1044,8 +1044,8 @@ __global__ void __launch_bounds__(kBlock) k_walk(Batch B, Inst one)
     __shared__ uint32_t sh[8];
     __shared__ uint32_t base[kMaxRankGroups + 1];
     Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
-    const ListShare ls = list_share(P, blk, base, sh);
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);   // G workgroups share the list
+    const ListShare ls = list_share(P, blk, base, sh, nullptr, P.G);
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
         uint32_t w;
         walk_chain(P, P.list[list_at(base, P.G, ls.chunk, i, &w)].x);
@@ -2072,7 +2072,7 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL(k_budget<kB>, g, b, 0, s, X.B, X.one);
     mark(kBudget, false);
     mark(kChain, true);
-    hipLaunchKernelGGL(k_walk<kB>, gl, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL(k_walk<kB>, g, b, 0, s, X.B, X.one);
     mark(kChain, false);
     mark(kOwners, true);
     hipLaunchKernelGGL(k_owners<kB>, g, b, 0, s, X.B, X.one);
