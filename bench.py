@@ -78,20 +78,22 @@ def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
     if stage == "fill":
         # owner entries (8 + 4); a split bisector's ID (8) and vertex record
         # (vb) read, its fate + forwarding written (20); per split output a
-        # free-list entry (4) and a vertex record (vb); a merge reads its
-        # smallest member's forwarding (16), per parent a member's ID (8),
-        # three of the children's six world positions (vb), a free-list entry
-        # (4) and writes the parent's record (vb); every merged member's
-        # fate + forwarding (20).  Flat vertices are decoded from the IDs.
-        return (12.0 * (S + C) + (28.0 + vb) * S + (4.0 + vb) * O + 16.0 * C + (12.0 + 2.0 * vb) * P
+        # free-list entry (4), a vertex record (vb) and the heap ID (8); a
+        # merge reads its smallest member's forwarding (16), per parent a
+        # member's ID (8), three of the children's six world positions (vb),
+        # a free-list entry (4) and writes the parent's record (vb) and heap
+        # ID (8); every merged member's fate + forwarding (20).  Flat
+        # vertices are decoded from the IDs.
+        return (12.0 * (S + C) + (28.0 + vb) * S + (12.0 + vb) * O + 16.0 * C + (20.0 + 2.0 * vb) * P
                 + 20.0 * M)
     if stage == "resolve":
-        # owner entries (8); a split bisector's ID, pointers, forwarding (40),
-        # its three neighbours' pointers (48), its bit (4); per output ID +
-        # pointers (24); a merge's forwarding and IDs (24 per parent), per
-        # parent the children's pointers (32) and their two outer
-        # neighbours' pointers (32), ID + pointers (24), two bits (8)
-        return 8.0 * (S + C) + 92.0 * S + 24.0 * O + 120.0 * P
+        # owner entries (8); a split bisector's pointers (16) and its
+        # outputs' free-list entries (16), its three neighbours' pointers
+        # (48), its bit (4); per output its pointers (16); per merged parent
+        # the smallest member's forwarding (16), the children's pointers
+        # (32) and their two outer neighbours' pointers (32), the parent's
+        # pointers (16), two bits (8)
+        return 8.0 * (S + C) + 84.0 * S + 16.0 * O + 104.0 * P
     if stage == "frame":
         # every stage: rank passes over L (enumerate 4, classify 8 + vb,
         # budget 8, owners 8), the fill and resolve bytes, and the bitfield +

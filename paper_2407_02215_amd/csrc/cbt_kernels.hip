@@ -720,6 +720,16 @@ __device__ __forceinline__ void store_world(const Pool& P, uint32_t s, Vec3<R> p
     store_rec(world_rec<R>(P, s), pa, pb, pc, depth, id);
 }
 
+// a new bisector's vertex record and heap ID (the pointer pass writes its
+// pointers)
+template <typename R>
+__device__ __forceinline__ void store_output(const Pool& P, uint32_t q, Vec3<R> pa, Vec3<R> pb, Vec3<R> pc, int depth,
+                                             uint64_t id)
+{
+    store_world<R>(P, q, pa, pb, pc, depth, id);
+    P.id[q] = id;
+}
+
 // ---------------------------------------------------------------------------
 // kernel: classify -> fresh command word (the vertex cache holds the world
 // positions, the depth and the parity, so no heap ID is read)
@@ -1293,21 +1303,21 @@ __device__ __forceinline__ void fill_split(const Pool& P, const LodK& K, uint32_
     const V wm = world<R>(K, m);
     // first child (v0, v2, m), or its children (v0, m, m0) and (m, v2, m0)
     if (!hp) {
-        store_world<R>(P, f.x, w0, w2, wm, d + 1, 2 * x);
+        store_output<R>(P, f.x, w0, w2, wm, d + 1, 2 * x);
     } else {
         const V m0 = mid3(v0, v2);
         const V wm0 = world<R>(K, m0);
-        store_world<R>(P, f.x, w0, wm, wm0, d + 2, 4 * x);
-        store_world<R>(P, f.y, wm, w2, wm0, d + 2, 4 * x + 1);
+        store_output<R>(P, f.x, w0, wm, wm0, d + 2, 4 * x);
+        store_output<R>(P, f.y, wm, w2, wm0, d + 2, 4 * x + 1);
     }
     // second child (v2, v1, m), or its children (v2, m, m1) and (m, v1, m1)
     if (!hn) {
-        store_world<R>(P, f.z, w2, w1, wm, d + 1, 2 * x + 1);
+        store_output<R>(P, f.z, w2, w1, wm, d + 1, 2 * x + 1);
     } else {
         const V m1 = mid3(v2, v1);
         const V wm1 = world<R>(K, m1);
-        store_world<R>(P, f.z, w2, wm, wm1, d + 2, 4 * x + 2);
-        store_world<R>(P, f.w, wm, w1, wm1, d + 2, 4 * x + 3);
+        store_output<R>(P, f.z, w2, wm, wm1, d + 2, 4 * x + 2);
+        store_output<R>(P, f.w, wm, w1, wm1, d + 2, 4 * x + 3);
     }
     P.lf[s].l.w = (int)c;
     P.lf[s].f = f;
@@ -1351,13 +1361,13 @@ __device__ __forceinline__ void fill_merge(const Pool& P, uint32_t s, uint32_t c
     }
     if (qa >= P.cap || (quad && qb >= P.cap)) { raise_err(P, kErrAlloc); return; }
     const int dp = depth_of_cmd(c) - 1;
-    store_world<R>(P, qa, ld3<R>(a0), ld3<R>(d0), ld3<R>(b0), dp, ida);
+    store_output<R>(P, qa, ld3<R>(a0), ld3<R>(d0), ld3<R>(b0), dp, ida);
     P.lf[s].l.w = (int)kMExec;
     P.lf[s].f = make_uint4(qa, m.x, m.y, m.z);
     P.lf[m.x].l.w = (int)kMExec;
     P.lf[m.x].f = make_uint4(qa, 0, 0, 0);
     if (quad) {
-        store_world<R>(P, qb, ld3<R>(a1), ld3<R>(d1), ld3<R>(b1), dp, idb);
+        store_output<R>(P, qb, ld3<R>(a1), ld3<R>(d1), ld3<R>(b1), dp, idb);
         P.lf[m.y].l.w = (int)kMExec;
         P.lf[m.y].f = make_uint4(qb, 0, 0, 0);
         P.lf[m.z].l.w = (int)kMExec;
@@ -1534,11 +1544,10 @@ __device__ __forceinline__ int32_t piece_target(const Pool& P, const Nb& nb, int
     return nb.n;
 }
 
-// a new bisector: heap ID, pointers, untouched fate
-__device__ __forceinline__ void store_new(const Pool& P, uint32_t q, uint64_t id, int32_t t, int32_t n, int32_t p)
+// a new bisector's pointers and untouched fate (the fill wrote its heap ID)
+__device__ __forceinline__ void store_new(const Pool& P, uint32_t q, int32_t t, int32_t n, int32_t p)
 {
     if (q >= P.cap) { raise_err(P, kErrAlloc); return; }
-    P.id[q] = id;
     P.lf[q].l = make_int4(t, n, p, 0);
 }
 
@@ -1585,8 +1594,7 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
 {
     const int db = depth_of_cmd(c);
     const bool hn = c & kMarkN, hp = c & kMarkP;
-    const uint64_t x = P.id[b];   // loaded with the outputs' blocks
-    const int4 lb = P.lf[b].l;
+    const int4 lb = P.lf[b].l;   // loaded with the outputs' blocks
     uint4 f;   // the outputs' blocks, from the free list as the fill took them
     if (!split_targets(P, c, base, N, &f)) return;
     const int32_t own[3] = {b, b, b};
@@ -1597,19 +1605,19 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
     const Nb& nN = nb[1];
     const Nb& nP = nb[2];
     if (!hp) {  // first child (v0, v2, m)
-        store_new(P, f.x, 2 * x, piece_target(P, nP, db, kWhole, f.x), (int32_t)f.z,
+        store_new(P, f.x, piece_target(P, nP, db, kWhole, f.x), (int32_t)f.z,
                   piece_target(P, nT, db, kHalf0, f.x));
     } else {    // its two children
-        store_new(P, f.x, 4 * x, piece_target(P, nT, db, kHalf0, f.x), (int32_t)f.y,
+        store_new(P, f.x, piece_target(P, nT, db, kHalf0, f.x), (int32_t)f.y,
                   piece_target(P, nP, db, kHalf1, f.x));
-        store_new(P, f.y, 4 * x + 1, (int32_t)f.z, piece_target(P, nP, db, kHalf0, f.y), (int32_t)f.x);
+        store_new(P, f.y, (int32_t)f.z, piece_target(P, nP, db, kHalf0, f.y), (int32_t)f.x);
     }
     if (!hn) {  // second child (v2, v1, m)
-        store_new(P, f.z, 2 * x + 1, piece_target(P, nN, db, kWhole, f.z), piece_target(P, nT, db, kHalf1, f.z),
+        store_new(P, f.z, piece_target(P, nN, db, kWhole, f.z), piece_target(P, nT, db, kHalf1, f.z),
                   (int32_t)(hp ? f.y : f.x));
     } else {    // its two children
-        store_new(P, f.z, 4 * x + 2, (int32_t)(hp ? f.y : f.x), (int32_t)f.w, piece_target(P, nN, db, kHalf1, f.z));
-        store_new(P, f.w, 4 * x + 3, piece_target(P, nT, db, kHalf1, f.w), piece_target(P, nN, db, kHalf0, f.w),
+        store_new(P, f.z, (int32_t)(hp ? f.y : f.x), (int32_t)f.w, piece_target(P, nN, db, kHalf1, f.z));
+        store_new(P, f.w, piece_target(P, nT, db, kHalf1, f.w), piece_target(P, nN, db, kHalf0, f.w),
                   (int32_t)f.z);
     }
     add_clear(P, cl, 0, (uint32_t)b);
@@ -1623,7 +1631,6 @@ __device__ __forceinline__ void resolve_split(const Pool& P, int32_t b, uint32_t
 __device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t c, Clears& cl)
 {
     const uint4 f = P.lf[b].f;   // (parent, sibling, other odd, other even)
-    const uint64_t ida = P.id[b] >> 1;
     const int d = depth_of_cmd(c);
     const bool quad = (c & kMQuad) != 0;
     // a record the fill did not rewrite (its allocation failed) is refused
@@ -1633,15 +1640,14 @@ __device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t
     }
     const uint32_t e2 = quad ? f.w : (uint32_t)b, o2 = quad ? f.z : f.y;
     const uint32_t qb = P.lf[e2].f.x;            // the second parent
-    const uint64_t idb = P.id[e2] >> 1;
     const int32_t mem[4] = {(int32_t)f.y, b, (int32_t)o2, (int32_t)e2};
     const int32_t twin[4] = {P.lf[f.y].l.x, P.lf[b].l.x, P.lf[o2].l.x, P.lf[e2].l.x};
     Nb nb[4];
     load_nbs(P, mem, twin, nb);
-    store_new(P, f.x, ida, quad ? (int32_t)qb : -1, piece_target(P, nb[0], d, kWhole, f.x),
+    store_new(P, f.x, quad ? (int32_t)qb : -1, piece_target(P, nb[0], d, kWhole, f.x),
               piece_target(P, nb[1], d, kWhole, f.x));
     if (quad) {
-        store_new(P, qb, idb, (int32_t)f.x, piece_target(P, nb[2], d, kWhole, qb), piece_target(P, nb[3], d, kWhole, qb));
+        store_new(P, qb, (int32_t)f.x, piece_target(P, nb[2], d, kWhole, qb), piece_target(P, nb[3], d, kWhole, qb));
         add_clear(P, cl, 1, f.z);
         add_clear(P, cl, 1, f.w);
     }
