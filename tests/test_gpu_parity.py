@@ -231,11 +231,13 @@ def test_restore_from_reference_state():
     inst.close()
 
 
-@pytest.mark.parametrize("groups,levels", [(16, 5), (64, 7), (2048, 10)])
+@pytest.mark.parametrize("groups,levels", [(16, 5), (17, 6), (45, 8), (64, 7), (2048, 10)])
 def test_schedule_does_not_change_results(groups, levels):
     """Launch schedules (rank workgroups, reduction levels per workgroup)
     change only how the work is cut: every schedule gives the reference's
-    state, including ragged last chunks and many empty workgroups."""
+    state, including ragged last chunks, many empty workgroups and odd
+    workgroup counts (the LOD pass takes two rank chunks per workgroup, so
+    its last workgroup then holds one)."""
     w = I.workload("planet", frames=256, table_res=64)
     inst = cbt.Instance(w.mesh, w.depth, w.lod)
     inst.set_schedule(groups, levels)
