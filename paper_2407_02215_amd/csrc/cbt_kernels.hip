@@ -735,15 +735,16 @@ __device__ __forceinline__ void store_output(const Pool& P, uint32_t q, Vec3<R> 
 // positions, the depth and the parity, so no heap ID is read)
 // ---------------------------------------------------------------------------
 
-// The even MERGE members are listed (block, depth) per workgroup in (tile,
-// wave, row, lane) order: wave ballots place them, one barrier per tile
-// exchanges the waves' counts (the vote does not depend on the order within
-// the list).
+// The even MERGE members are listed (block, depth) per workgroup in rank
+// order: wave ballots place them, one barrier per tile exchanges the waves'
+// counts per row (the vote's result does not depend on the order within the
+// list; rank order keeps neighbouring threads of the vote on neighbouring
+// blocks).
 template <bool kB, typename R>
 __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
 {
     __shared__ uint32_t sh[8];
-    __shared__ uint32_t wcnt[2][kBlock / 64];
+    __shared__ uint32_t wcnt[2][kClassRows][kBlock / 64];
     Pool P;
     LodK K;
     const uint8_t* inj;
@@ -818,28 +819,28 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
                     cand[j] = (RecId<R>::low(wb[j]) & 1u) == 0;
                 }
             }
+            // rank order within the tile: (row, wave, lane)
             uint64_t m[kClassRows];
-            uint32_t cnt = 0;
 #pragma unroll
             for (int j = 0; j < kClassRows; ++j) {
                 m[j] = __ballot(cand[j]);
-                cnt += (uint32_t)__popcll(m[j]);
+                if (lane == 0) wcnt[tile & 1][j][wv] = (uint32_t)__popcll(m[j]);
             }
-            if (lane == 0) wcnt[tile & 1][wv] = cnt;
             __syncthreads();
-            uint32_t at = r0 + nlist, ttot = 0;
-#pragma unroll
-            for (int i = 0; i < kBlock / 64; ++i) {
-                const uint32_t t = wcnt[tile & 1][i];
-                at += i < wv ? t : 0u;
-                ttot += t;
-            }
+            uint32_t at = r0 + nlist;
 #pragma unroll
             for (int j = 0; j < kClassRows; ++j) {
-                if (cand[j]) P.list[at + lanes_below(m[j])] = make_uint2(sr[j], dr[j]);
-                at += (uint32_t)__popcll(m[j]);
+                uint32_t before = 0, row = 0;
+#pragma unroll
+                for (int i = 0; i < kBlock / 64; ++i) {
+                    const uint32_t t = wcnt[tile & 1][j][i];
+                    before += i < wv ? t : 0u;
+                    row += t;
+                }
+                if (cand[j]) P.list[at + before + lanes_below(m[j])] = make_uint2(sr[j], dr[j]);
+                at += row;
             }
-            nlist += ttot;
+            nlist = at - r0;
         }
         const uint32_t c = block_sum(scost, sh);
         if (threadIdx.x == 0) {
