@@ -521,7 +521,7 @@ def main():
     ap.add_argument("--instances", type=int, default=None)
     ap.add_argument("--meshes", type=int, default=32)
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--duration", type=float, default=60.0, help="serve mode: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-batch", type=int, default=128)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
