@@ -60,6 +60,16 @@ enum StatIndex {
     kStCount
 };
 
+// Workgroups add their frame statistics into one of kStLanes copies (one
+// 128-byte line each, picked by workgroup index), not all into one word:
+// device-wide atomics on one address serialise, and a thousand workgroups
+// finishing together queued for tens of microseconds per pass.  The
+// reduction's last kernel folds the copies into Counters::stat and clears
+// them.
+constexpr int kStLanes = 64;
+constexpr int kLaneWords = 32;
+static_assert(kStCount <= kLaneWords, "statistics of one lane in one line");
+
 struct Counters {
     uint32_t L;     // live blocks at frame start (CBT root)
     uint32_t F;     // free blocks
@@ -120,6 +130,7 @@ struct Pool {
     uint32_t* lcnt;   // [kMaxRankGroups] entries in each workgroup's list
     uint2* part;       // [kMaxRankGroups] per-workgroup partial sums
     Counters* ctr;
+    uint32_t* slane;   // [kStLanes][kLaneWords] frame statistics being summed
     float* root;       // [9H] root triangle vertices (binary64 instances: double)
     int32_t D, k, H;
     uint32_t cap, W;

@@ -380,6 +380,13 @@ __device__ __forceinline__ void raise_err(const Pool& P, uint32_t e) { atomicOr(
 
 __device__ __forceinline__ bool slot_ok(const Pool& P, int32_t s) { return (uint32_t)s < P.cap; }
 
+// a workgroup's contribution to frame statistic k (one lane per workgroup
+// index modulo kStLanes)
+__device__ __forceinline__ void stat_add(const Pool& P, uint32_t blk, int k, uint32_t v)
+{
+    if (v) atomicAdd(&P.slane[(blk % kStLanes) * kLaneWords + k], v);
+}
+
 __device__ __forceinline__ int depth_of_cmd(uint32_t c) { return (int)((c & kDepthMask) >> kDepthShift); }
 
 // Number of set bits in the words before word w, read off the tree: the
@@ -852,9 +859,9 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
     const uint32_t a = block_sum(nsplit, sh);
     const uint32_t b = block_sum(nmerge, sh);
     if (threadIdx.x == 0) {
-        if (a) atomicAdd(&P.ctr->stat[kStSplitReq], a);
-        if (b) atomicAdd(&P.ctr->stat[kStMergeReq], b);
-        if (ncand) atomicAdd(&P.ctr->stat[kStMergeCand], ncand);
+        stat_add(P, blk, kStSplitReq, a);
+        stat_add(P, blk, kStMergeReq, b);
+        stat_add(P, blk, kStMergeCand, ncand);
     }
 }
 
@@ -935,7 +942,7 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
     }
     if (res) atomicAdd(&P.part[wres].x, res);
     const uint32_t u = block_sum(ncfg, sh);
-    if (threadIdx.x == 0 && u) atomicAdd(&P.ctr->stat[kStMergeCfg], u);
+    if (threadIdx.x == 0) stat_add(P, blk, kStMergeCfg, u);
 }
 
 // ---------------------------------------------------------------------------
@@ -1010,8 +1017,8 @@ __global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
     const uint32_t a = block_sum(nm, sh);
     if (threadIdx.x == 0) {
         P.lcnt[blk] = nlist;
-        if (a) atomicAdd(&P.ctr->stat[kStMergeAcc], a);
-        if (nlist) atomicAdd(&P.ctr->stat[kStSplitAcc], nlist);
+        stat_add(P, blk, kStMergeAcc, a);
+        stat_add(P, blk, kStSplitAcc, nlist);
     }
 }
 
@@ -1189,9 +1196,9 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
     if (threadIdx.x == 0) {
         P.part[blk] = make_uint2(run.y, 0);
         P.lcnt[blk] = run.x;
-        if (a) atomicAdd(&P.ctr->stat[kStMergeExec], a);
-        if (b) atomicAdd(&P.ctr->stat[kStSplitConsumed], b);
-        if (c) atomicAdd(&P.ctr->stat[kStFrees], c);
+        stat_add(P, blk, kStMergeExec, a);
+        stat_add(P, blk, kStSplitConsumed, b);
+        stat_add(P, blk, kStFrees, c);
     }
 }
 
@@ -1741,6 +1748,20 @@ __global__ void __launch_bounds__(1024) k_reduce_top(Batch B, Inst one)
         }
         __syncthreads();
     }
+    // the frame statistics: each thread folds and clears one statistic's
+    // lanes (the passes that add to them have completed)
+    if (threadIdx.x < (uint32_t)kStCount) {
+        uint32_t v[kStLanes];
+#pragma unroll
+        for (int l = 0; l < kStLanes; ++l) v[l] = P.slane[l * kLaneWords + threadIdx.x];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int l = 0; l < kStLanes; ++l) {
+            sum += v[l];
+            P.slane[l * kLaneWords + threadIdx.x] = 0u;
+        }
+        P.ctr->stat[threadIdx.x] = sum;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1792,6 +1813,7 @@ __global__ void k_clear_pool(Pool P)
             P.lcnt[g] = 0;
             P.part[g] = make_uint2(0, 0);
         }
+        for (uint32_t i = threadIdx.x; i < (uint32_t)(kStLanes * kLaneWords); i += blockDim.x) P.slane[i] = 0u;
         if (threadIdx.x == 0) *P.ctr = Counters{};
     }
 }
@@ -2000,6 +2022,7 @@ size_t workspace_layout(int32_t H, int32_t D, int32_t f64, Pool* P, char* base)
     const size_t o_bits = take(4 * W), o_tree = take(4 * TW), o_live = take(4 * cap);
     const size_t o_free = take(4 * cap), o_list = take(8 * cap), o_lpre = take(4 * cap), o_lcnt = take(4 * (size_t)kMaxRankGroups);
     const size_t o_part = take(sizeof(uint2) * kMaxRankGroups), o_ctr = take(sizeof(Counters));
+    const size_t o_slane = take(4 * (size_t)kStLanes * kLaneWords);
     const size_t o_root = take((f64 ? 72 : 36) * (size_t)H);
     if (P) {
         P->id = reinterpret_cast<uint64_t*>(base + o_id);
@@ -2015,6 +2038,7 @@ size_t workspace_layout(int32_t H, int32_t D, int32_t f64, Pool* P, char* base)
         P->lcnt = reinterpret_cast<uint32_t*>(base + o_lcnt);
         P->part = reinterpret_cast<uint2*>(base + o_part);
         P->ctr = reinterpret_cast<Counters*>(base + o_ctr);
+        P->slane = reinterpret_cast<uint32_t*>(base + o_slane);
         P->root = reinterpret_cast<float*>(base + o_root);
         P->D = D;
         P->H = H;
