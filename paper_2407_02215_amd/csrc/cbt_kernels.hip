@@ -922,7 +922,17 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
     Pool P;
     const uint32_t blk = pick<kB>(B, one, B.map_list, P);
     const ListShare ls = list_share(P, blk, base, sh);
-    uint32_t ncfg = 0, res = 0, wres = 0xffffffffu;
+    // reservations per rank workgroup: the workgroup's entries come from a
+    // few consecutive rank workgroups [w0, w0 + kVoteAcc), summed in LDS and
+    // added with one atomic each (many threads adding into the same partial
+    // serialise); entries of later ones (tiny chunks) go straight to memory
+    constexpr uint32_t kVoteAcc = 8;
+    __shared__ uint32_t acc[kVoteAcc];
+    uint32_t w0 = 0;
+    if (ls.i0 < ls.i1) (void)list_at(base, P.G, ls.chunk, ls.i0, &w0);
+    if (threadIdx.x < kVoteAcc) acc[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t ncfg = 0;
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
         uint32_t w;
         const uint2 e = P.list[list_at(base, P.G, ls.chunk, i, &w)];   // (block, depth)
@@ -932,15 +942,12 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
         if (!m) continue;
         P.cmd[s] |= kMCfg | kMMin | kMUnan | (m == 4 ? kMQuad : 0u);
         P.lf[s].f = make_uint4((uint32_t)j2, (uint32_t)j3, (uint32_t)j4, (uint32_t)m);
-        if (w != wres) {
-            if (res) atomicAdd(&P.part[wres].x, res);
-            wres = w;
-            res = 0;
-        }
-        res += (uint32_t)m / 2;
+        if (w - w0 < kVoteAcc) atomicAdd(&acc[w - w0], (uint32_t)m / 2);
+        else atomicAdd(&P.part[w].x, (uint32_t)m / 2);
         ++ncfg;
     }
-    if (res) atomicAdd(&P.part[wres].x, res);
+    __syncthreads();
+    if (threadIdx.x < kVoteAcc && acc[threadIdx.x]) atomicAdd(&P.part[w0 + threadIdx.x].x, acc[threadIdx.x]);
     const uint32_t u = block_sum(ncfg, sh);
     if (threadIdx.x == 0) stat_add(P, blk, kStMergeCfg, u);
 }
