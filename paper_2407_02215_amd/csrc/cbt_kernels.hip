@@ -352,6 +352,25 @@ __device__ __forceinline__ uint32_t list_at(const uint32_t* base, uint32_t G, ui
     return lo * chunk + (i - base[lo]);
 }
 
+// The same from a rank workgroup known not to lie after entry i's
+// (base[*w] <= i): a thread's entries increase, so its last result is the
+// next start, and the scan moves a step or two instead of a binary search.
+__device__ __forceinline__ uint32_t list_at_from(const uint32_t* base, uint32_t chunk, uint32_t i, uint32_t* w)
+{
+    uint32_t v = *w;
+    while (base[v + 1] <= i) ++v;
+    *w = v;
+    return v * chunk + (i - base[v]);
+}
+
+// the rank workgroup of this workgroup's first entry (0 for an empty share)
+__device__ __forceinline__ uint32_t share_start(const uint32_t* base, uint32_t G, const ListShare& ls)
+{
+    uint32_t w = 0;
+    if (ls.i0 < ls.i1) (void)list_at(base, G, ls.chunk, ls.i0, &w);
+    return w;
+}
+
 // block numbers of ranks [t0, t0 + kSeg); t0 is a multiple of kSeg below
 // the pool size, so the two 16-byte loads stay inside the rank list; ranks
 // from r1 on read as block 0 (in bounds, unused)
@@ -928,14 +947,14 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
     // serialise); entries of later ones (tiny chunks) go straight to memory
     constexpr uint32_t kVoteAcc = 8;
     __shared__ uint32_t acc[kVoteAcc];
-    uint32_t w0 = 0;
-    if (ls.i0 < ls.i1) (void)list_at(base, P.G, ls.chunk, ls.i0, &w0);
+    const uint32_t w0 = share_start(base, P.G, ls);
+    uint32_t wh = w0;
     if (threadIdx.x < kVoteAcc) acc[threadIdx.x] = 0;
     __syncthreads();
     uint32_t ncfg = 0;
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
-        uint32_t w;
-        const uint2 e = P.list[list_at(base, P.G, ls.chunk, i, &w)];   // (block, depth)
+        const uint2 e = P.list[list_at_from(base, ls.chunk, i, &wh)];   // (block, depth)
+        const uint32_t w = wh;
         const uint32_t s = e.x;
         int32_t j2 = -1, j3 = -1, j4 = -1;
         const int m = merge_vote_even(P, s, (int)e.y, &j2, &j3, &j4);
@@ -1071,9 +1090,9 @@ __global__ void __launch_bounds__(kBlock) k_walk(Batch B, Inst one)
     Pool P;
     const uint32_t blk = pick<kB>(B, one, B.map_rank, P);   // G workgroups share the list
     const ListShare ls = list_share(P, blk, base, sh, nullptr, P.G);
+    uint32_t wh = share_start(base, P.G, ls);
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
-        uint32_t w;
-        walk_chain(P, P.list[list_at(base, P.G, ls.chunk, i, &w)].x);
+        walk_chain(P, P.list[list_at_from(base, ls.chunk, i, &wh)].x);
     }
 }
 
@@ -1435,12 +1454,11 @@ __device__ __forceinline__ bool group_owners(OwnerStage& st, bool valid, uint3& 
 
 // the owner-list item of entry i of this workgroup's share
 __device__ __forceinline__ uint3 owner_item(const Pool& P, const uint32_t* base, const uint32_t* obase, uint32_t chunk,
-                                            uint32_t i)
+                                            uint32_t i, uint32_t* wh)
 {
-    uint32_t w;
-    const uint32_t at = list_at(base, P.G, chunk, i, &w);
+    const uint32_t at = list_at_from(base, chunk, i, wh);
     const uint2 e = P.list[at];
-    return make_uint3(e.x, e.y, obase[w] + P.lpre[at]);
+    return make_uint3(e.x, e.y, obase[*wh] + P.lpre[at]);
 }
 
 template <bool kB, typename R>
@@ -1459,10 +1477,11 @@ __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
     // free-list pass) are refused, so free-list reads stay below F
     const uint32_t N = min(obase[P.G], P.ctr->F);
     __shared__ OwnerStage st;
+    uint32_t wh = share_start(base, P.G, ls);
     for (uint32_t i0 = ls.i0; i0 < ls.i1; i0 += kBlock) {   // uniform trip count
         const uint32_t i = i0 + threadIdx.x;
         uint3 it = make_uint3(0, 0, 0);
-        if (i < ls.i1) it = owner_item(P, base, obase, ls.chunk, i);
+        if (i < ls.i1) it = owner_item(P, base, obase, ls.chunk, i, &wh);
         if (!group_owners(st, i < ls.i1, it)) continue;
         if (it.y & kMarks) fill_split<R>(P, K, it.x, it.y, it.z, N);
         else fill_merge<R>(P, it.x, it.y, it.z, N);
@@ -1683,12 +1702,13 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
     // free-list pass) are refused, so free-list reads stay below F
     const uint32_t N = min(obase[P.G], P.ctr->F);
     __shared__ OwnerStage st;
+    uint32_t wh = share_start(base, P.G, ls);
     // uniform trip count: items are regrouped across the workgroup and the
     // bit clears merged across the wave
     for (uint32_t i0 = ls.i0; i0 < ls.i1; i0 += kBlock) {
         const uint32_t i = i0 + threadIdx.x;
         uint3 it = make_uint3(0, 0, 0);
-        if (i < ls.i1) it = owner_item(P, base, obase, ls.chunk, i);
+        if (i < ls.i1) it = owner_item(P, base, obase, ls.chunk, i, &wh);
         const bool got = group_owners(st, i < ls.i1, it);
         Clears cl = {{kNoWord, kNoWord}, {0u, 0u}};
         if (got) {
