@@ -5,9 +5,10 @@ Modes
   single (default)  one instance, the terrain workload (depth-24 pool, 64x64
                     quad grid, ridged height field): a step is one frame of
                     the update (every stage of the pipeline) along the seeded
-                    flythrough.  The first W frames are warm-up (the
-                    triangulation grows from the base mesh); the next K are
-                    timed between two stream synchronisations.
+                    flythrough.  The first P frames (--preroll, 40) grow the
+                    triangulation from the base mesh to its steady state and
+                    are not counted; then W warm-up frames, then K timed
+                    frames between two stream synchronisations.
                     Bisector updates/s = sum over the timed frames of the
                     live count at frame start / elapsed time.
   batch             many instances of uneven size and depth (128 by default),
@@ -21,25 +22,37 @@ Modes
                     one request per launch; p50/p99 request latency.
 
 Single-mode protocol (the pipeline is deterministic):
-  1. warm up W frames;  2. snapshot the pool;
+  1. pre-roll P frames, warm up W frames;  2. snapshot the pool;
   3. run the K frames once with per-frame counters (untimed) for the live
-     counts and the algorithmic bytes;  4. restore;
-  5. run the K frames timed (no events);  6. restore;
-  7. run the K frames again with events around every whole frame (p50/p99
-     frame latency) and check the final state equals the timed pass's;
+     counts and the byte models;  4. restore;
+  5. run the K frames timed (no events), bracketed by two marker kernels
+     (torch's spin kernel) outside the timed region, which delimit the
+     timed pass in the byte-counter profiles;  6. restore;
+  7. run the K frames again with events around every whole frame (frame
+     latency percentiles) and check the final state equals the timed pass's;
   8. once per stage: restore and run the K frames with HIP events around
-     that stage's launches on the library's stream; the roofline is
-     reported for the longest stage with a byte model (classify, vote,
-     fill, resolve);
-  9. export the final state's triangles 20 times (HIP events).
-Every pass runs the same K frames, so each kernel's dispatches of one pass
-([W + jK, W + (j+1)K) in dispatch order) see the same work.
+     that stage's launches on the library's stream;
+  9. export the final state's triangles 20 times (HIP events);
+ 10. the CPU reference takes the GPU state at the first timed frame and runs
+     the timed frames from there, single-threaded, for about --cpu-budget
+     seconds.
+
+Two byte models.  "paper": the minimal state of the paper's method (64-bit
+ID, three 32-bit pointers, a 32-bit command, one occupancy bit; the tree
+above the 32-bit word): per frame 16 L + 48 S + 24 N + 8 hops + 3/8 2^D
+bytes for L live, S consumed by splits (each entered once by a chain: hops
+= S), N new bisectors; split by stage in paper_bytes().  "layout": what this
+library's layout must move (vertex cache, pointer/forwarding lines, work
+lists), per stage in layout_bytes().  Counted bytes come from the rocprofv3
+byte counters recorded by paper_2407_02215_amd/traffic.py for the same
+command, kernel source and schedule.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -47,23 +60,54 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# plain VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles
+# each, 2.4 GHz (64 lanes per CU per cycle)
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 METRIC = "bisector updates/s per frame (% HBM roofline); p50/p99 update latency"
+STAGES = ("enumerate", "classify", "vote", "budget", "chain", "owners", "freelist", "fill", "resolve", "reduce")
 
 
-def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
-    """Bytes a stage must move per launch, from one frame's counters.
-
-    L live bisectors, R merge requests, S bisectors consumed by splits,
-    C merge configurations executed, M merged members, P parents (M / 2),
-    O split outputs (allocations - P); vb is one vertex record (three world
-    positions with depth and parity: 48 bytes in binary32, 96 in binary64)."""
-    L = st["live_before"]
-    R = st["merge_requests"]
+def frame_counts(st: dict) -> dict:
+    """The quantities the byte models use, from one frame's counters."""
     S = st["split_consumed"]
-    C = st["merges_executed"]
-    M = st["frees"] - S
-    P = M // 2
-    O = st["allocations"] - P
+    M = st["frees"] - S             # merged members
+    return {"L": st["live_before"], "S": S, "N": st["allocations"], "R": st["merge_requests"],
+            "C": st["merges_executed"], "M": M, "P": M // 2, "O": st["allocations"] - M // 2,
+            "cand": st["merge_candidates"], "cfg": st["merge_configs"]}
+
+
+def paper_bytes(stage: str, st: dict, D: int) -> float:
+    """Paper-minimal bytes of one stage's launch (the per-frame total
+    16 L + 48 S + 24 N + 8 hops + 3/8 2^D split by where each term is
+    moved): enumerate reads the bitfield (2^D / 8); classify reads the 8-byte
+    ID and writes the 4-byte command (12 L); the rank-order scans read the
+    command (4 L, budget); the chain walk reads a twin and ORs a mark per hop
+    (8 S); the free list updates the bitfield of new blocks (4 N); the fill
+    reads each consumed record (20 S), writes its forwarding (16 S) and
+    every new record (20 N); the neighbour pass patches three pointers per
+    consumed bisector (12 S); the reduction reads the bitfield and writes the
+    tree (2^D / 4).  The vote and the owner pass have no term."""
+    c = frame_counts(st)
+    L, S, N = c["L"], c["S"], c["N"]
+    cap = float(1 << D)
+    terms = {"enumerate": cap / 8, "classify": 12.0 * L, "vote": 0.0, "budget": 4.0 * L, "chain": 8.0 * S,
+             "owners": 0.0, "freelist": 4.0 * N, "fill": 36.0 * S + 20.0 * N, "resolve": 12.0 * S,
+             "reduce": cap / 4}
+    if stage == "frame":
+        return sum(terms.values())
+    return terms[stage]
+
+
+def layout_bytes(stage: str, st: dict, D: int, vb: int = 48) -> float:
+    """Bytes a stage of this library's layout must move per launch, from one
+    frame's counters (vb: one vertex record, 48 bytes in binary32, 96 in
+    binary64)."""
+    c = frame_counts(st)
+    L, R, S, C, M, P, O = c["L"], c["R"], c["S"], c["C"], c["M"], c["P"], c["O"]
+    cap = float(1 << D)
+    if stage == "enumerate":
+        # bitfield word (4 per 32 blocks), rank-list entry per live block
+        return cap / 8 + 4.0 * L
     if stage == "classify":
         # rank -> block (4), the vertex record (vb), command write (4); even
         # merge requests are listed (8 for about half of them)
@@ -74,7 +118,17 @@ def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
         # of the twin-side member (16); per unanimous configuration the two
         # IDs each of its even members compares (32), its forwarding record
         # and command (20)
-        return 52.0 * st["merge_candidates"] + 52.0 * st["merge_configs"]
+        return 52.0 * c["cand"] + 52.0 * c["cfg"]
+    if stage in ("budget", "owners"):
+        # rank entry and command per live bisector; owners write their list
+        # entries (12 per owner)
+        return 8.0 * L + (12.0 * (S + C) if stage == "owners" else 0.0)
+    if stage == "chain":
+        # per chain member: pointer record (16) and the mark atomic (4)
+        return 20.0 * S
+    if stage == "freelist":
+        # bitfield read + write, a free-list entry per new block
+        return cap / 4 + 4.0 * c["N"]
     if stage == "fill":
         # owner entries (8 + 4); a split bisector's ID (8) and vertex record
         # (vb) read, its fate + forwarding written (20); per split output a
@@ -94,16 +148,11 @@ def algorithmic_bytes(stage: str, st: dict, vb: int = 48) -> float:
         # (32) and their two outer neighbours' pointers (32), the parent's
         # pointers (16), two bits (8)
         return 8.0 * (S + C) + 84.0 * S + 16.0 * O + 104.0 * P
+    if stage == "reduce":
+        return cap / 8 + cap / 8
     if stage == "frame":
-        # every stage: rank passes over L (enumerate 4, classify 8 + vb,
-        # budget 8, owners 8), the fill and resolve bytes, and the bitfield +
-        # tree passes (3/8 byte per pool block, taken as L here)
-        return (28.0 + vb) * L + algorithmic_bytes("fill", st, vb) + algorithmic_bytes("resolve", st, vb)
+        return sum(layout_bytes(k, st, D, vb) for k in STAGES)
     raise KeyError(stage)
-
-
-SURVEY_STAGES = ("classify", "vote", "fill", "resolve")          # stages with a byte model
-EXTRA_STAGES = ("enumerate", "budget", "chain", "owners", "freelist", "reduce")
 
 
 def random_calibration() -> dict:
@@ -148,18 +197,28 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, np.float64), q)) if len(xs) else None
 
 
-def cpu_baseline(workload: str, budget_s: float, precision: int = 32) -> dict:
-    """The CPU reference (single-threaded C) on the first frames of the same
-    workload, timed frame by frame until about budget_s seconds of work."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown CPU"
+
+
+def cpu_baseline(w, snap, first: int, last: int, budget_s: float, precision: int = 32) -> dict:
+    """The CPU reference (single-threaded C) on the timed frames: it takes
+    the GPU's state at frame `first` and runs frames first, first + 1, ...
+    (at most through `last`) until about budget_s seconds of frame work."""
     from oracle import Oracle
-    from paper_2407_02215_amd import inputs as I
-    w = I.workload(workload, frames=64)
     o = Oracle(w.mesh, w.depth, w.lod, precision=precision)
+    o.set_pool(*snap)
     total_l, total_t, frames = 0, 0.0, 0
-    lo, hi = None, None
-    for cam in w.cameras:
+    lo = hi = None
+    for f in range(first, last + 1):
         t0 = time.perf_counter()
-        st = o.frame(camera=cam)
+        st = o.frame(camera=w.cameras[f])
         dt = time.perf_counter() - t0
         total_l += st.live_before
         total_t += dt
@@ -169,8 +228,17 @@ def cpu_baseline(workload: str, budget_s: float, precision: int = 32) -> dict:
         if total_t >= budget_s:
             break
     return {"value": total_l / total_t, "unit": "bisector updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{workload} frames 0-{frames - 1} from the base mesh (live {lo}..{hi}), "
-                      f"{total_t:.1f} s single-threaded on {os.cpu_count()} host cores"}
+            "sample": f"{w.name} frames {first}-{first + frames - 1} (the first timed frames, live {lo}..{hi}), "
+                      f"replayed from the GPU state at frame {first}; {total_t:.1f} s single-threaded on 1 of "
+                      f"{os.cpu_count()} host threads, {cpu_model()}"}
+
+
+def _marker():
+    """A kernel dispatch outside the timed region that delimits the timed
+    pass in the byte-counter profiles (torch's spin kernel)."""
+    import torch
+    torch.cuda._sleep(1000)
+    torch.cuda.synchronize()
 
 
 def run_single(args) -> dict:
@@ -179,7 +247,8 @@ def run_single(args) -> dict:
     from paper_2407_02215_amd import cbt
     from paper_2407_02215_amd import inputs as I
 
-    frames = args.warmup + args.steps
+    P, W, K = args.preroll, args.warmup, args.steps
+    frames = P + W + K
     w = I.workload(args.workload, frames=max(frames, 8))
     if len(w.cameras) < frames:
         raise SystemExit(f"workload {args.workload} has {len(w.cameras)} frames, asked for {frames}")
@@ -189,25 +258,29 @@ def run_single(args) -> dict:
         import dataclasses
         w = dataclasses.replace(w, lod=dataclasses.replace(
             w.lod, split_px=w.lod.split_px ** 2 / 4, merge_px=w.lod.merge_px ** 2 / 4, criterion=I.CRIT_AREA))
+    elif args.criterion == "distance":
+        import dataclasses
+        w = dataclasses.replace(w, lod=dataclasses.replace(w.lod, criterion=I.CRIT_DISTANCE))
     inst = cbt.Instance(w.mesh, w.depth, w.lod, tuned=args.schedule is None, precision=args.precision)
     if args.schedule is not None:
         inst.set_schedule(*(int(x) for x in args.schedule.split(",")))
-    print(f"# warm-up {args.warmup} frames, schedule {inst.schedule()}", file=sys.stderr, flush=True)
-    for cam in w.cameras[:args.warmup]:
+    print(f"# pre-roll {P} + warm-up {W} frames, schedule {inst.schedule()}", file=sys.stderr, flush=True)
+    for cam in w.cameras[:P + W]:
         inst.update(cam)
     torch.cuda.synchronize()
     snap = inst.snapshot()
-    timed = w.cameras[args.warmup:frames]
-    print(f"# counting pass over {len(timed)} frames", file=sys.stderr, flush=True)
+    timed = w.cameras[P + W:frames]
+    print(f"# counting pass over frames {P + W}..{frames - 1}", file=sys.stderr, flush=True)
     stats = [inst.update(cam, stats=True) for cam in timed]
     inst.restore(*snap)
     print("# timed pass", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
+    _marker()
     t0 = time.perf_counter()
     for cam in timed:
         inst.update(cam)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    _marker()
     check = [a.copy() for a in inst.pool()]
     print("# latency pass", file=sys.stderr, flush=True)
     inst.restore(*snap)
@@ -218,11 +291,9 @@ def run_single(args) -> dict:
     inst.time_stage(None)
     again = inst.pool()
     assert all(np.array_equal(a, b) for a, b in zip(check, again)), "non-deterministic frame"
-    # stage survey: the same frames once per stage with HIP events around
-    # that stage's launches; the roofline is reported for the longest one
-    # (or the one --stage names)
+    print("# stage survey", file=sys.stderr, flush=True)
     survey = {}
-    for stage in (SURVEY_STAGES + EXTRA_STAGES if args.stage == "auto" else (args.stage,)):
+    for stage in STAGES:
         inst.restore(*snap)
         inst.time_stage(stage)
         for cam in timed:
@@ -230,58 +301,91 @@ def run_single(args) -> dict:
         n_st, ms_st = inst.stage_time()
         inst.time_stage(None)
         survey[stage] = ms_st / max(1, n_st)
-    dominant = max((k for k in survey if k in SURVEY_STAGES or k == args.stage), key=survey.get)
     # triangle export of the final state: live list (4), vertex record, 36
     # bytes written per triangle
     L = inst.live_count()
-    tri = torch.empty((L, 3, 3), dtype=torch.float32, device="cuda")
+    tri = torch.empty((max(1, L), 3, 3), dtype=torch.float32, device="cuda")
     inst.export_triangles(tri)
     inst.time_stage("export")
     for _ in range(20):
         inst.export_triangles(tri)
     n_exp, exp_ms = inst.stage_time()
     inst.time_stage(None)
-    rec = 96 if args.precision == 64 else 48
-    exp_bytes = L * (4.0 + rec + 36.0)
+    vb = 96 if args.precision == 64 else 48
+    exp_bytes = L * (4.0 + vb + 36.0)
     exp_mean = exp_ms / max(1, n_exp)
+    schedule = list(inst.schedule())
+    inst.close()
 
+    D = w.depth
+    nfr = len(stats)
+    mean = lambda f: sum(f(s) for s in stats) / nfr   # noqa: E731
     updates = sum(s["live_before"] for s in stats)
     value = updates / elapsed
-    traffic = args.traffic
-    if traffic is None and args.precision == 32 and args.workload == "terrain" and args.criterion == "edge":
-        from paper_2407_02215_amd import traffic as T
-        traffic = T.lookup(dominant, args.warmup, args.steps, inst.schedule())
-    vb = 96 if args.precision == 64 else 48
-    alg = sum(algorithmic_bytes(dominant, s, vb) for s in stats) / len(stats)
+    frame_s = elapsed / nfr
+    from paper_2407_02215_amd import traffic as T
+    rec = T.lookup(args.workload, args.criterion, args.precision, P, W, K, schedule)
+    # dominant kernel: the longest stage the paper-minimal model gives bytes
+    dominant = max((k for k in STAGES if mean(lambda s, k=k: paper_bytes(k, s, D)) > 0), key=survey.get)
     mean_ms = survey[dominant]
-    achieved = alg / (mean_ms * 1e-3) / 1e9
+    pb = mean(lambda s: paper_bytes(dominant, s, D))
+    lb = mean(lambda s: layout_bytes(dominant, s, D, vb))
+    counted = rec["kernels"].get(dominant, {}).get("bytes") if rec else None
+    frame_pb = mean(lambda s: paper_bytes("frame", s, D))
+    frame_lb = mean(lambda s: layout_bytes("frame", s, D, vb))
+    frame_counted = rec["frame_bytes"] if rec else None
+    valu = rec.get("frame_valu_insts") if rec else None
+    gbs = lambda b, t: b / t / 1e9   # noqa: E731
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "bisector updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": elapsed * 1e3 / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 64 else "f32",
         "data": "synthetic (seeded workload generator)",
-        "config": {"workload": args.workload, "criterion": args.criterion, "cbt_depth": w.depth,
-                   "halfedges": w.mesh.H,
-                   "frames": f"{args.warmup}..{frames - 1}", "mean_live": updates / len(stats),
-                   "schedule": list(inst.schedule())},
-        "latency_ms": {"p50": percentile(frame_ms, 50), "p99": percentile(frame_ms, 99),
+        "config": {"workload": args.workload, "criterion": args.criterion, "cbt_depth": D,
+                   "halfedges": w.mesh.H, "preroll": P, "frames": f"{P + W}..{frames - 1}",
+                   "mean_live": updates / nfr, "schedule": schedule},
+        "counters": {"live": mean(lambda s: s["live_before"]),
+                     "consumed_by_splits": mean(lambda s: s["split_consumed"]),
+                     "new": mean(lambda s: s["allocations"]), "freed": mean(lambda s: s["frees"]),
+                     "split_requests": mean(lambda s: s["split_requests"]),
+                     "splits_accepted": mean(lambda s: s["split_accepted"]),
+                     "merge_requests": mean(lambda s: s["merge_requests"]),
+                     "merges_executed": mean(lambda s: s["merges_executed"]),
+                     "what": "per-frame means over the timed frames"},
+        "latency_ms": {"p10": percentile(frame_ms, 10), "p50": percentile(frame_ms, 50),
+                       "p90": percentile(frame_ms, 90), "p99": percentile(frame_ms, 99),
                        "what": "GPU time of one whole update, HIP events"},
         "export": {"triangles": L, "ms": exp_mean, "alg_bytes": exp_bytes,
                    "achieved_gbs": exp_bytes / (exp_mean * 1e-3) / 1e9},
         "stage_ms": survey,
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
-                     "mean_launch_ms": mean_ms, "alg_bytes_per_launch": alg},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": gbs(pb, mean_ms * 1e-3), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs(pb, mean_ms * 1e-3) / HBM_PEAK_GBS, "traffic": counted,
+                     "traffic_unit": "HBM bytes per launch", "mean_launch_ms": mean_ms,
+                     "alg_bytes_per_launch": pb, "bytes": "paper-minimal state"},
+        "roofline_layout": {"kernel": dominant, "achieved": gbs(lb, mean_ms * 1e-3),
+                            "frac": gbs(lb, mean_ms * 1e-3) / HBM_PEAK_GBS, "alg_bytes_per_launch": lb,
+                            "bytes": "this library's layout (vertex cache, pointer and forwarding lines)"},
+        "frame": {"ms": frame_s * 1e3,
+                  "paper_bytes": frame_pb, "paper_frac": gbs(frame_pb, frame_s) / HBM_PEAK_GBS,
+                  "layout_bytes": frame_lb, "layout_frac": gbs(frame_lb, frame_s) / HBM_PEAK_GBS,
+                  "counted_bytes": frame_counted,
+                  "counted_frac": None if frame_counted is None else gbs(frame_counted, frame_s) / HBM_PEAK_GBS,
+                  "valu_frac": None if valu is None else valu / (frame_s * VALU_PEAK_WAVE_INSTS),
+                  "what": "whole update per timed frame: bytes over the timed pass's mean frame time against "
+                          "8 TB/s; counted = rocprofv3 FETCH_SIZE + WRITE_SIZE of every kernel; VALU = wave64 "
+                          "VALU instructions against 256 CUs x 4 SIMDs at 2.4 GHz"},
     }
-    inst.close()
+    if not args.no_cpu_baseline:
+        print("# CPU reference baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, snap, P + W, frames - 1, args.cpu_budget, args.precision)
     return out
 
 
@@ -510,14 +614,12 @@ def main():
                     help="vertices, world positions and size test in binary32 or binary64 (single mode)")
     ap.add_argument("--schedule", default=None,
                     help="rank workgroups,reduction levels (single mode; default: the tuned table)")
-    ap.add_argument("--criterion", default="edge", choices=["edge", "area"],
-                    help="size test of the LOD (single mode): projected base-edge length or triangle area")
+    ap.add_argument("--preroll", type=int, default=40,
+                    help="single mode: untimed frames from the base mesh to the steady state, before the warm-up")
+    ap.add_argument("--criterion", default="edge", choices=["edge", "area", "distance"],
+                    help="size test of the LOD (single mode): projected base-edge length, triangle area, or "
+                         "the cull-free distance-only variant")
     ap.add_argument("--camera", type=int, default=255, help="camera index (converge mode)")
-    ap.add_argument("--stage", default="auto", choices=["auto"] + list(SURVEY_STAGES) + ["frame"],
-                    help="kernel whose roofline is reported; auto: the longest of the surveyed stages")
-    ap.add_argument("--traffic", type=float, default=None,
-                    help="HBM bytes per launch of the profiled stage from the byte counters; by default "
-                         "the value paper_2407_02215_amd/traffic.py recorded for this kernel source")
     ap.add_argument("--instances", type=int, default=None)
     ap.add_argument("--meshes", type=int, default=32)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -549,11 +651,8 @@ def main():
         sys.exit(2)
     if args.mode == "single":
         args.steps = 200 if args.steps is None else args.steps
-        args.warmup = 40 if args.warmup is None else args.warmup
+        args.warmup = 5 if args.warmup is None else args.warmup
         out = run_single(args)
-        if not args.no_cpu_baseline:
-            print("# CPU reference baseline", file=sys.stderr, flush=True)
-            out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, args.precision)
     elif args.mode == "converge":
         out = run_converge(args)
     elif args.mode == "batch":

@@ -44,7 +44,7 @@ typedef int32_t cbt_status;
 #define CBT_OK 0
 #define CBT_E_ARG (-1)      /* null or out-of-range argument                 */
 #define CBT_E_MESH (-2)     /* mesh fails validation (see cbt_init)           */
-#define CBT_E_DEPTH (-3)    /* D < max(5, ceil(log2 H)) or D > 30             */
+#define CBT_E_DEPTH (-3)    /* D < ceil(log2 H) or D > 30                     */
 #define CBT_E_CAPACITY (-4) /* output arrays too small                        */
 #define CBT_E_DEVICE (-5)   /* HIP error or device-side check; handle failed  */
 #define CBT_E_BUDGET (-6)   /* workspace smaller than cbt_workspace_bytes     */
@@ -94,8 +94,9 @@ enum {
 /* Size criteria of the screen-space test (the paper's size target of
  * Section 3.3 kernel 4 and Section 4.1). */
 enum {
-    CBT_CRIT_EDGE = 0,  /* projected length of the base edge, thresholds in pixels      */
-    CBT_CRIT_AREA = 1   /* projected area of the triangle, thresholds in pixels^2        */
+    CBT_CRIT_EDGE = 0,     /* projected length of the base edge, thresholds in pixels      */
+    CBT_CRIT_AREA = 1,     /* projected area of the triangle, thresholds in pixels^2        */
+    CBT_CRIT_DISTANCE = 2  /* base edge over its midpoint's distance, in pixels; cull-free  */
 };
 
 /* LOD parameters.  With CBT_CRIT_EDGE a live bisector is split when the
@@ -104,8 +105,12 @@ enum {
  * the near plane is split; with CBT_CRIT_AREA the projected area of its
  * triangle is compared with split_px and merge_px (pixels^2), and one with
  * any vertex behind the near plane is split.  Either way one whose vertices
- * all lie outside one frustum plane is merged; the comparisons are strict
- * and division-free.
+ * all lie outside one frustum plane is merged.  CBT_CRIT_DISTANCE is the
+ * cull-free, distance-only variant: the base edge's length e and its
+ * midpoint's distance r from the camera give f e / r pixels (f the focal
+ * length in pixels) whatever the view direction, no frustum or near-plane
+ * test, thresholds in pixels as for CBT_CRIT_EDGE.  The comparisons are
+ * strict and division-free.
  * table is a DEVICE pointer (float32), caller-owned, that must stay valid
  * while updates run: 6 * table_res^2 texels for CBT_MODE_SPHERE (faces
  * +x,-x,+y,-y,+z,-z; texel (i,j) of a face at row j, column i) or
@@ -118,7 +123,7 @@ typedef struct {
     const float* table;
     int32_t table_res;
     float amplitude;
-    int32_t criterion;   /* CBT_CRIT_EDGE or CBT_CRIT_AREA */
+    int32_t criterion;   /* CBT_CRIT_EDGE, CBT_CRIT_AREA or CBT_CRIT_DISTANCE */
 } cbt_lod_params;
 
 /* Per-frame counters (filled when a non-NULL pointer is passed). */
@@ -141,7 +146,14 @@ typedef struct {
 
 /* Live bisectors in ascending slot order (two-call pattern: with capacity
  * smaller than the live count, only count is written and CBT_E_CAPACITY is
- * returned).  Every array pointer is a HOST pointer and may be NULL. */
+ * returned).  Every array pointer is a HOST pointer and may be NULL.
+ * root_h / subdiv_id give each bisector in the paper's notation b_j^d
+ * (Section 2.3 "Notation"): the root halfedge h it descends from and its
+ * subdivision code, a leading 1 followed by its d path bits (most
+ * significant first, 0 = first child): heap ID x of depth d has
+ * h = (x >> d) - 2^k and subdiv_id = 2^d + (x mod 2^d).  The triangulation's
+ * canonical form is the set of these pairs, which does not depend on the
+ * pool slots (sort them to compare two triangulations). */
 typedef struct {
     int64_t capacity;     /* in: entries available in the per-bisector arrays */
     int64_t count;        /* out: number of live bisectors                    */
@@ -155,6 +167,8 @@ typedef struct {
     double* vertices64;   /* out: 9 doubles per bisector, flat-domain (Alg. 2),
                              the binary64 decode of CBT_INIT_FP64 instances
                              (binary32 instances: their decode, widened)   */
+    int32_t* root_h;      /* out: root halfedge of each bisector              */
+    uint64_t* subdiv_id;  /* out: 1 followed by the bisector's path bits      */
 } cbt_bisectors;
 
 /* Device workspace needed for a mesh of H halfedges and a pool of 2^D
@@ -164,8 +178,11 @@ size_t cbt_workspace_bytes(int32_t H, int32_t D);
 /* Section 3.3 "Initialization": H root bisectors in the first H blocks,
  * their neighbours copied from the halfedge operators, the first H bits
  * set, then the sum reduction.  Validates the mesh (CBT_E_MESH), requires
- * max(5, ceil(log2 H)) <= D <= 30 (CBT_E_DEPTH) and a large enough
- * workspace (CBT_E_BUDGET).  Synchronises the stream before returning. */
+ * ceil(log2 H) <= D <= 30 (CBT_E_DEPTH; Section 3.3 "Memory
+ * Requirements": the pool must hold every root bisector; a pool of fewer
+ * than 32 blocks keeps one partial bitfield word whose count is the tree
+ * root) and a large enough workspace (CBT_E_BUDGET).  Synchronises the
+ * stream before returning. */
 cbt_status cbt_init(const cbt_mesh* mesh, int32_t D, void* device_workspace,
                     size_t workspace_bytes, void* hip_stream, cbt_handle* out);
 

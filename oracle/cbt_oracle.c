@@ -37,7 +37,8 @@
 enum { DEC_KEEP = 0, DEC_SPLIT = 1, DEC_MERGE = 2 };
 enum { MARK_B = 1, MARK_N = 2, MARK_P = 4 };   /* split marks: base, Next, Prev edge */
 enum { MODE_FLAT = 0, MODE_SPHERE = 1, MODE_HEIGHTFIELD = 2 };
-enum { CRIT_EDGE = 0, CRIT_AREA = 1 };   /* projected base-edge length / triangle area */
+enum { CRIT_EDGE = 0, CRIT_AREA = 1, CRIT_DISTANCE = 2 };   /* projected base-edge length / triangle area /
+                                                               base edge over its distance, no culling */
 
 static char g_err[1024];
 
@@ -288,7 +289,8 @@ int32_t orc_set_lod(orc_state* s, int32_t mode, float split_px, float merge_px,
 
 int32_t orc_set_criterion(orc_state* s, int32_t criterion)
 {
-    if (criterion != CRIT_EDGE && criterion != CRIT_AREA) return fail("unknown size criterion %d", criterion);
+    if (criterion != CRIT_EDGE && criterion != CRIT_AREA && criterion != CRIT_DISTANCE)
+        return fail("unknown size criterion %d", criterion);
     s->criterion = criterion;
     return 0;
 }
@@ -468,6 +470,29 @@ int32_t orc_frame_constants(const orc_state* s, const float* camera, float* out)
 static int classify(const orc_state* s, const lod_consts* K, const float* v,
                     float* oA, float* oBs, float* oBm)
 {
+    if (s->criterion == CRIT_DISTANCE) {
+        /* Cull-free, distance-only variant of the size target (Section 3.3
+         * kernel 4 without the frustum adaptation of Section 4.1): the base
+         * edge's length e seen face-on from the distance r of its midpoint,
+         * f e / r pixels, whatever the view direction.  Compared squared:
+         * A = f^2 |p1 - p0|^2 against tau^2 |m - c|^2, m = (p0 + p1) / 2. */
+        float p0[3], p1[3];
+        world_position(s, v, p0);
+        world_position(s, v + 3, p1);
+        float mx = (p0[0] + p1[0]) * 0.5f, my = (p0[1] + p1[1]) * 0.5f, mz = (p0[2] + p1[2]) * 0.5f;
+        float qx = mx - K->cam[0], qy = my - K->cam[1], qz = mz - K->cam[2];
+        float r2 = (qx * qx + qy * qy) + qz * qz;
+        float ex = p1[0] - p0[0], ey = p1[1] - p0[1], ez = p1[2] - p0[2];
+        float A = K->f2 * ((ex * ex + ey * ey) + ez * ez);
+        float Bs = K->t2s * r2;
+        float Bm = K->t2m * r2;
+        *oA = A;
+        *oBs = Bs;
+        *oBm = Bm;
+        if (A > Bs) return DEC_SPLIT;
+        if (A < Bm) return DEC_MERGE;
+        return DEC_KEEP;
+    }
     float vx[3], vy[3], vz[3];
     for (int i = 0; i < 3; ++i) {
         float p[3];
@@ -690,6 +715,23 @@ static void make_consts64(const orc_state* s, const float* camera, lod_consts64*
 static int classify64(const orc_state* s, const lod_consts64* K, const double* v, float* oA, float* oBs,
                       float* oBm)
 {
+    if (s->criterion == CRIT_DISTANCE) {   /* as in classify(), in binary64 */
+        double p0[3], p1[3];
+        world_position64(s, v, p0);
+        world_position64(s, v + 3, p1);
+        double mx = (p0[0] + p1[0]) * 0.5, my = (p0[1] + p1[1]) * 0.5, mz = (p0[2] + p1[2]) * 0.5;
+        double qx = mx - K->cam[0], qy = my - K->cam[1], qz = mz - K->cam[2];
+        double r2 = (qx * qx + qy * qy) + qz * qz;
+        double ex = p1[0] - p0[0], ey = p1[1] - p0[1], ez = p1[2] - p0[2];
+        double A = K->f2 * ((ex * ex + ey * ey) + ez * ez);
+        double Bs = K->t2s * r2, Bm = K->t2m * r2;
+        *oA = (float)A;
+        *oBs = (float)Bs;
+        *oBm = (float)Bm;
+        if (A > Bs) return DEC_SPLIT;
+        if (A < Bm) return DEC_MERGE;
+        return DEC_KEEP;
+    }
     double vx[3], vy[3], vz[3];
     for (int i = 0; i < 3; ++i) {
         double p[3];

@@ -52,7 +52,9 @@ void    orc_destroy(orc_state* s);
 int32_t orc_set_lod(orc_state* s, int32_t mode, float split_px, float merge_px,
                     const float* table, int32_t res, float amplitude);
 /* size criterion: 0 projected base-edge length (thresholds in pixels, the
- * default), 1 projected triangle area (thresholds in pixels^2) */
+ * default), 1 projected triangle area (thresholds in pixels^2), 2 the base
+ * edge's length over the distance of its midpoint, in pixels, without
+ * frustum culling (cull-free, distance-only) */
 int32_t orc_set_criterion(orc_state* s, int32_t criterion);
 /* precision of root triangles, decode, world position and the size test:
  * 32 (binary32, the default) or 64 (binary64) */

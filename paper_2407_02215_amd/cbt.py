@@ -67,7 +67,8 @@ class FrameStats(C.Structure):
 class Bisectors(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("count", C.c_int64), ("slot", C.c_void_p), ("heap_id", C.c_void_p),
                 ("twin", C.c_void_p), ("next", C.c_void_p), ("prev", C.c_void_p), ("vertices", C.c_void_p),
-                ("tree", C.c_void_p), ("vertices64", C.c_void_p)]
+                ("tree", C.c_void_p), ("vertices64", C.c_void_p), ("root_h", C.c_void_p),
+                ("subdiv_id", C.c_void_p)]
 
 
 def load_library():
@@ -144,15 +145,6 @@ def make_camera(cam) -> Camera:
     c.height = int(cam.height)
     c.znear = float(np.float32(cam.znear))
     return c
-
-
-def canonical(heap_ids, k: int):
-    """Sorted (root halfedge, 1 followed by the path bits) pairs."""
-    out = []
-    for x in np.asarray(heap_ids, np.uint64).tolist():
-        d = int(x).bit_length() - 1 - k
-        out.append(((x >> d) - (1 << k), (1 << d) | (x & ((1 << d) - 1))))
-    return sorted(out)
 
 
 class Instance:
@@ -315,7 +307,10 @@ class Instance:
         tw = np.zeros(L, np.int32)
         nx = np.zeros(L, np.int32)
         pv = np.zeros(L, np.int32)
-        b2 = Bisectors(L, 0, _ptr(slot), _ptr(ids), _ptr(tw), _ptr(nx), _ptr(pv), None, None)
+        rh = np.zeros(L, np.int32)
+        code = np.zeros(L, np.uint64)
+        b2 = Bisectors(L, 0, _ptr(slot), _ptr(ids), _ptr(tw), _ptr(nx), _ptr(pv), None, None, None, _ptr(rh),
+                       _ptr(code))
         verts = verts64 = None
         if vertices:
             verts = np.zeros((L, 9), np.float32)
@@ -324,7 +319,7 @@ class Instance:
             verts64 = np.zeros((L, 9), np.float64)
             b2.vertices64 = _ptr(verts64)
         self._check(self.lib.cbt_query(self.h, C.byref(b2)))
-        out.update(slot=slot, heap_id=ids, twin=tw, next=nx, prev=pv)
+        out.update(slot=slot, heap_id=ids, twin=tw, next=nx, prev=pv, root_h=rh, subdiv_id=code)
         if vertices:
             out["vertices"] = verts
         if vertices64:
@@ -393,7 +388,10 @@ class Instance:
         return int(g.value), int(r.value)
 
     def canonical(self):
-        return canonical(self.query()["heap_id"], self.k)
+        """The triangulation as the sorted (root halfedge, subdivision code)
+        pairs the library reports (cbt_query's root_h / subdiv_id)."""
+        q = self.query()
+        return sorted(zip(q["root_h"].tolist(), q["subdiv_id"].tolist()))
 
 
 BATCH_GRAPH = 1
@@ -610,13 +608,17 @@ class Server:
         tw = np.zeros(L, np.int32)
         nx = np.zeros(L, np.int32)
         pv = np.zeros(L, np.int32)
-        b2 = Bisectors(L, 0, _ptr(slot), _ptr(ids), _ptr(tw), _ptr(nx), _ptr(pv), None, None)
+        rh = np.zeros(L, np.int32)
+        code = np.zeros(L, np.uint64)
+        b2 = Bisectors(L, 0, _ptr(slot), _ptr(ids), _ptr(tw), _ptr(nx), _ptr(pv), None, None, None, _ptr(rh),
+                       _ptr(code))
         heap = None
         if tree:
             heap = np.zeros(2 << D, np.uint32)
             b2.tree = _ptr(heap)
         self._check(self.lib.cbt_server_query(self.h, int(iid), C.byref(b2)))
-        out = {"count": L, "slot": slot, "heap_id": ids, "twin": tw, "next": nx, "prev": pv}
+        out = {"count": L, "slot": slot, "heap_id": ids, "twin": tw, "next": nx, "prev": pv, "root_h": rh,
+               "subdiv_id": code}
         if tree:
             out["tree"] = heap
         return out

@@ -117,7 +117,7 @@ cbt_status check_lod(cbt_handle h, const cbt_camera* c, const cbt_lod_params* lp
 {
     if (!c || !lp) return fail(h, CBT_E_ARG, "camera and LOD parameters are required");
     if (lp->mode < CBT_MODE_FLAT || lp->mode > CBT_MODE_HEIGHTFIELD) return fail(h, CBT_E_ARG, "unknown LOD mode %d", lp->mode);
-    if (lp->criterion != CBT_CRIT_EDGE && lp->criterion != CBT_CRIT_AREA)
+    if (lp->criterion != CBT_CRIT_EDGE && lp->criterion != CBT_CRIT_AREA && lp->criterion != CBT_CRIT_DISTANCE)
         return fail(h, CBT_E_ARG, "unknown size criterion %d", lp->criterion);
     if (lp->mode != CBT_MODE_FLAT && (!lp->table || lp->table_res < 2))
         return fail(h, CBT_E_ARG, "LOD mode %d needs a device table of resolution >= 2", lp->mode);
@@ -296,7 +296,7 @@ extern "C" {
 
 size_t cbt_workspace_bytes_ex(int32_t H, int32_t D, uint32_t flags)
 {
-    if (H < 3 || D < 5 || D > 30 || D < ceil_log2(H) || (flags & ~(uint32_t)CBT_INIT_FP64)) return 0;
+    if (H < 3 || D > 30 || D < ceil_log2(H) || (flags & ~(uint32_t)CBT_INIT_FP64)) return 0;
     return cbtk::workspace_layout(H, D, (flags & CBT_INIT_FP64) ? 1 : 0, nullptr, nullptr);
 }
 
@@ -327,7 +327,7 @@ static cbt_status init_impl(const cbt_mesh* mesh, int32_t D, uint32_t flags, voi
         if (st) return st;
     }
     const int k = ceil_log2(mesh->H);
-    if (D < 5 || D > 30 || D < k) return fail(nullptr, CBT_E_DEPTH, "depth %d outside [max(5, ceil(log2 H)=%d), 30]", D, k);
+    if (D > 30 || D < k) return fail(nullptr, CBT_E_DEPTH, "depth %d outside [ceil(log2 H)=%d, 30]", D, k);
     const size_t need = cbtk::workspace_layout(mesh->H, D, f64, nullptr, nullptr);
     if (!device_workspace) return fail(nullptr, CBT_E_ARG, "device workspace is NULL");
     if (reinterpret_cast<uintptr_t>(device_workspace) & 255) return fail(nullptr, CBT_E_ARG, "workspace must be 256-byte aligned");
@@ -604,7 +604,8 @@ cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
     if (st) return st;
     const uint32_t L = h->hctr->L;
     out->count = L;
-    const bool per = out->slot || out->heap_id || out->twin || out->next || out->prev || out->vertices || out->vertices64;
+    const bool per = out->slot || out->heap_id || out->twin || out->next || out->prev || out->vertices || out->vertices64 ||
+                     out->root_h || out->subdiv_id;
     if (per && out->capacity < (int64_t)L) return fail(h, CBT_E_CAPACITY, "capacity %lld < %u live bisectors", (long long)out->capacity, L);
     size_t scratch_bytes;
     char* scratch = list_scratch(P, &scratch_bytes);
@@ -613,6 +614,16 @@ cbt_status cbt_query(cbt_handle h, cbt_bisectors* out)
     if (out->heap_id && L) {
         HIP_TRY(h, cbtk::launch_gather_ids(P, 0, L, reinterpret_cast<uint64_t*>(scratch), s), "gather IDs");
         HIP_TRY(h, hipMemcpyAsync(out->heap_id, scratch, sizeof(uint64_t) * L, hipMemcpyDeviceToHost, s), "copy IDs");
+        HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+    }
+    if (out->root_h && L) {
+        HIP_TRY(h, cbtk::launch_gather_canonical(P, 0, L, reinterpret_cast<int32_t*>(scratch), nullptr, s), "gather roots");
+        HIP_TRY(h, hipMemcpyAsync(out->root_h, scratch, sizeof(int32_t) * L, hipMemcpyDeviceToHost, s), "copy roots");
+        HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
+    }
+    if (out->subdiv_id && L) {
+        HIP_TRY(h, cbtk::launch_gather_canonical(P, 0, L, nullptr, reinterpret_cast<uint64_t*>(scratch), s), "gather codes");
+        HIP_TRY(h, hipMemcpyAsync(out->subdiv_id, scratch, sizeof(uint64_t) * L, hipMemcpyDeviceToHost, s), "copy codes");
         HIP_TRY(h, hipStreamSynchronize(s), "synchronise");
     }
     if ((out->twin || out->next || out->prev) && L) {

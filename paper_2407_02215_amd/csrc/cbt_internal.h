@@ -111,14 +111,16 @@ struct LinkFwd {
 struct Pool {
     uint64_t* id;      // [cap] heap ID per block (stale when free)
     LinkFwd* lf;       // [cap] pointer and forwarding records, side by side
-    float4* vworld;    // [3 cap] world positions of the three vertices; w of
-                       //         the first holds the subdivision depth, of the
-                       //         second the parity of the heap ID (as integers);
-                       //         binary64 instances: [3 cap] double4, depth and
-                       //         parity as exact doubles
+    float4* vworld;    // [3 cap] world positions of the three vertices; the w
+                       //         components hold raw bits: the subdivision depth
+                       //         (first vertex), the heap ID's low and high words
+                       //         (second and third); binary64 instances: [3 cap]
+                       //         double4 with the depth and the whole heap ID
     uint32_t* cmd;     // [cap] command word, rewritten every frame
-    uint32_t* bits;    // [W]   occupancy bitfield, bit s&31 of word s>>5
-    uint32_t* tree;    // [2^(D-4)] sum-reduction tree down to word level
+    uint32_t* bits;    // [W]   occupancy bitfield, bit s&31 of word s>>5 (one
+                       //       word, partly used, when D < 5)
+    uint32_t* tree;    // [2^(LW+1)] sum-reduction tree down to the word level
+                       //       LW = word_level(D); node 1 is the root
     uint32_t* live;    // [cap] rank -> block, ascending
     uint32_t* freel;   // [cap] first N free blocks of the pre-frame bitfield
     uint2* list;       // [cap] per-workgroup compacted work lists, each
@@ -170,6 +172,10 @@ struct Launch {
     uint32_t grid_rank, grid_word, grid_red, grid_list;
 };
 
+// Tree level of the bitfield words: D - 5 (32 blocks per word), and 0 for a
+// pool of fewer than 32 blocks, whose single partial word is the root.
+__host__ __device__ inline int word_level(int D) { return D > 5 ? D - 5 : 0; }
+
 // per-instance grid sizes
 uint32_t word_groups(const Pool& P);
 // workgroups of the passes over the compacted work lists (and of the LOD
@@ -215,6 +221,10 @@ hipError_t launch_clear_pool(const Pool& P, hipStream_t s);
 hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s);
 hipError_t launch_gather_ids(const Pool& P, uint32_t r0, uint32_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_gather_links(const Pool& P, uint32_t r0, uint32_t n, int32_t* out3, hipStream_t s);
+// root halfedge and subdivision code (1 followed by the path bits) of ranks
+// [r0, r0 + n); either output may be NULL
+hipError_t launch_gather_canonical(const Pool& P, uint32_t r0, uint32_t n, int32_t* root_h, uint64_t* code,
+                                   hipStream_t s);
 hipError_t launch_gather_vertices(const Pool& P, uint32_t r0, uint32_t n, float* out9, hipStream_t s);
 // binary64 decode (binary32 instances: their decode, widened)
 hipError_t launch_gather_vertices64(const Pool& P, uint32_t r0, uint32_t n, double* out9, hipStream_t s);

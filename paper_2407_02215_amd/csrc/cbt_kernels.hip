@@ -408,6 +408,14 @@ __device__ __forceinline__ void stat_add(const Pool& P, uint32_t blk, int k, uin
 
 __device__ __forceinline__ int depth_of_cmd(uint32_t c) { return (int)((c & kDepthMask) >> kDepthShift); }
 
+// The blocks of a bitfield word that exist: all 32, or the first 2^D of the
+// single word of a pool smaller than one word (D < 5).  Bits past the pool
+// never count as live and are never handed out as free.
+__device__ __forceinline__ uint32_t word_valid(const Pool& P)
+{
+    return P.cap >= 32u ? 0xffffffffu : ((1u << P.cap) - 1u);
+}
+
 // Number of set bits in the words before word w, read off the tree: the
 // left siblings along w's path from the root.  Their indices follow from
 // w's bits alone, so the lanes of the first wave load one level each, all
@@ -416,7 +424,7 @@ __device__ __forceinline__ int depth_of_cmd(uint32_t c) { return (int)((c & kDep
 __device__ uint32_t ones_before_word(const Pool& P, uint32_t w, uint32_t* sh_out)
 {
     if (threadIdx.x < 64) {
-        const int LW = P.D - 5;   // the word level; LW <= 25 < 64
+        const int LW = word_level(P.D);   // LW <= 25 < 64
         const int l = (int)threadIdx.x;
         uint32_t v = 0;
         if (l < LW && ((w >> l) & 1u)) {
@@ -464,10 +472,11 @@ __global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
     // all of this workgroup's words in flight while the tree is descended
     constexpr int kSteps = kWordsPerBlock / kBlock;
     uint32_t words[kSteps];
+    const uint32_t valid = word_valid(P);
 #pragma unroll
     for (int j = 0; j < kSteps; ++j) {
         const uint32_t w = w0 + j * kBlock + threadIdx.x;
-        words[j] = (w < P.W) ? P.bits[w] : 0u;
+        words[j] = (w < P.W) ? (P.bits[w] & valid) : 0u;
     }
     __shared__ uint32_t sb;
     uint32_t base = ones_before_word(P, w0, &sb);
@@ -666,8 +675,21 @@ __device__ __forceinline__ Vec3<R> world(const LodK& K, Vec3<R> v)
 template <typename R>
 __device__ __forceinline__ uint32_t lod_decide(const LodK& K, Vec3<R> p0, Vec3<R> p1, Vec3<R> p2)
 {
-    const Vec3<R> p[3] = {p0, p1, p2};
     const R cam[3] = {(R)K.cam[0], (R)K.cam[1], (R)K.cam[2]};
+    if (K.crit == 2) {
+        // cull-free, distance-only: the base edge seen face-on from its
+        // midpoint's distance r, f |p1 - p0| / r pixels, compared squared;
+        // no frustum test, whatever the view direction
+        const R h = (R)0.5;
+        const R qx = (p0.x + p1.x) * h - cam[0], qy = (p0.y + p1.y) * h - cam[1], qz = (p0.z + p1.z) * h - cam[2];
+        const R r2 = (qx * qx + qy * qy) + qz * qz;
+        const R ex = p1.x - p0.x, ey = p1.y - p0.y, ez = p1.z - p0.z;
+        const R A = (R)K.f2 * ((ex * ex + ey * ey) + ez * ez);
+        if (A > (R)K.t2s * r2) return kSplit;
+        if (A < (R)K.t2m * r2) return kMerge;
+        return kKeep;
+    }
+    const Vec3<R> p[3] = {p0, p1, p2};
     const R rt[3] = {(R)K.right[0], (R)K.right[1], (R)K.right[2]};
     const R up[3] = {(R)K.up[0], (R)K.up[1], (R)K.up[2]};
     const R fw[3] = {(R)K.fwd[0], (R)K.fwd[1], (R)K.fwd[2]};
@@ -1253,13 +1275,15 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
     __shared__ uint32_t sb;
     uint32_t zb = 32u * w0 - ones_before_word(P, w0, &sb);
     if (zb >= N) return;
+    const uint32_t valid = word_valid(P);
     for (uint32_t it = 0; it < kWordsPerBlock; it += kBlock) {
         const uint32_t w = w0 + it + threadIdx.x;
-        const uint32_t word = (w < P.W) ? P.bits[w] : 0xffffffffu;
+        const uint32_t raw = (w < P.W) ? P.bits[w] : 0xffffffffu;
+        const uint32_t word = raw | ~valid;   // blocks past a one-word pool read as taken
         uint32_t tot;
         uint32_t o = block_excl_scan(__popc(~word), sh, &tot);
         if (w < P.W && zb + o < N) {
-            uint32_t inv = ~word, nw = word;
+            uint32_t inv = ~word, nw = raw;
             while (inv && zb + o < N) {
                 const int j = __ffs(inv) - 1;
                 stage[o++] = w * 32u + (uint32_t)j;
@@ -1727,7 +1751,7 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
 
 __device__ __forceinline__ int sub_levels(const Pool& P)
 {
-    const int LW = P.D - 5;
+    const int LW = word_level(P.D);
     return LW < P.sub ? LW : P.sub;
 }
 
@@ -1737,12 +1761,13 @@ __global__ void __launch_bounds__(kBlock) k_reduce_sub(Batch B, Inst one)
     __shared__ uint32_t buf[2][1 << kMaxReduceSub];
     Pool P;
     const uint32_t blk = pick<kB>(B, one, B.map_red, P);
-    const int LW = P.D - 5;
+    const int LW = word_level(P.D);
     const int SUB = sub_levels(P);
     const uint32_t wpb = 1u << SUB;
     const uint32_t w0 = blk * wpb;
+    const uint32_t valid = word_valid(P);
     for (uint32_t i = threadIdx.x; i < wpb; i += kBlock) {
-        const uint32_t c = __popc(P.bits[w0 + i]);
+        const uint32_t c = __popc(P.bits[w0 + i] & valid);
         buf[0][i] = c;
         P.tree[(1u << LW) + w0 + i] = c;
     }
@@ -1766,7 +1791,7 @@ __global__ void __launch_bounds__(1024) k_reduce_top(Batch B, Inst one)
 {
     Pool P;
     pick_inst<kB>(B, one, P);
-    const int top = (P.D - 5) - sub_levels(P);   // levels [0, top) remain
+    const int top = word_level(P.D) - sub_levels(P);   // levels [0, top) remain
     for (int lvl = top - 1; lvl >= 0; --lvl) {
         const uint32_t n = 1u << lvl;
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -1849,8 +1874,9 @@ __global__ void k_bits_from_ids(Pool P)
 {
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= P.W) return;
+    const uint32_t n = P.cap - w * 32u < 32u ? P.cap - w * 32u : 32u;   // a one-word pool holds fewer
     uint32_t word = 0;
-    for (int j = 0; j < 32; ++j)
+    for (uint32_t j = 0; j < n; ++j)
         if (P.id[w * 32u + j] != 0) word |= 1u << j;
     P.bits[w] = word;
 }
@@ -1860,6 +1886,27 @@ __global__ void k_gather_ids(Pool P, uint32_t r0, uint32_t n, uint64_t* out)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     out[i] = P.id[P.live[r0 + i]];
+}
+
+// The bisector of rank r0 + i in the paper's notation b_j^d: its root
+// halfedge and its subdivision code (a leading 1, then the d path bits).
+__global__ void k_gather_canonical(Pool P, uint32_t r0, uint32_t n, int32_t* root_h, uint64_t* code)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t id = P.id[P.live[r0 + i]];
+    int32_t h = -1;
+    uint64_t c = 0;
+    if (valid_id(P, id)) {
+        const int d = ilog2_64(id) - P.k;
+        h = (int32_t)((int64_t)(id >> d) - ((int64_t)1 << P.k));
+        const uint64_t one = 1ull << d;
+        c = one | (id & (one - 1ull));
+    } else {
+        raise_err(P, kErrPointer);
+    }
+    if (root_h) root_h[i] = h;
+    if (code) code[i] = c;
 }
 
 __global__ void k_gather_links(Pool P, uint32_t r0, uint32_t n, int32_t* out)
@@ -1908,7 +1955,7 @@ __global__ void k_gather_decisions(Pool P, uint32_t L, uint8_t* out)
 __global__ void k_export_heap(Pool P, uint32_t* out)
 {
     const uint64_t total = 2ull * P.cap;
-    const int LW = P.D - 5;
+    const int LW = word_level(P.D);
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
          i += (uint64_t)gridDim.x * blockDim.x) {
         if (i == 0) { out[0] = 0; continue; }
@@ -2026,7 +2073,7 @@ uint32_t word_groups(const Pool& P) { return cdiv(P.W, kWordsPerBlock); }
 
 int reduce_levels(const Pool& P)
 {
-    const int LW = P.D - 5;
+    const int LW = word_level(P.D);
     return LW < P.sub ? LW : P.sub;
 }
 
@@ -2035,8 +2082,8 @@ uint32_t reduce_groups(const Pool& P) { return P.W >> reduce_levels(P); }
 size_t workspace_layout(int32_t H, int32_t D, int32_t f64, Pool* P, char* base)
 {
     const uint64_t cap = 1ull << D;
-    const uint64_t W = cap / 32;
-    const uint64_t TW = 1ull << (D - 4);
+    const uint64_t W = cap >= 32 ? cap / 32 : 1;                 // a pool below 32 blocks has one partial word
+    const uint64_t TW = 2ull << word_level(D);                   // tree nodes 1 .. 2^(LW+1) - 1
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -2225,6 +2272,13 @@ hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s)
 hipError_t launch_gather_ids(const Pool& P, uint32_t r0, uint32_t n, uint64_t* out, hipStream_t s)
 {
     if (n) hipLaunchKernelGGL(k_gather_ids, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, P, r0, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_canonical(const Pool& P, uint32_t r0, uint32_t n, int32_t* root_h, uint64_t* code,
+                                  hipStream_t s)
+{
+    if (n) hipLaunchKernelGGL(k_gather_canonical, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, P, r0, n, root_h, code);
     return hipGetLastError();
 }
 

@@ -490,7 +490,7 @@ uint64_t grid_need(int32_t D, int32_t groups, int32_t levels)
     cbtk::Pool P{};
     P.D = D;
     P.cap = (uint32_t)(1ull << D);
-    P.W = (uint32_t)((1ull << D) / 32);
+    P.W = D >= 5 ? (uint32_t)((1ull << D) / 32) : 1u;
     P.G = groups ? (uint32_t)groups : cbth::default_rank_groups(D);
     P.sub = levels ? levels : cbtk::kMaxReduceSub;
     return (uint64_t)P.G + cbtk::word_groups(P) + cbtk::reduce_groups(P) + cbtk::list_groups(P);

@@ -28,8 +28,10 @@ MODE_HEIGHTFIELD = 2  # p = v + (0, 0, amp * grid(v.x, v.y))
 DEC_KEEP, DEC_SPLIT, DEC_MERGE = 0, 1, 2
 
 # size criteria of the screen-space test: projected base-edge length
-# (thresholds in pixels) or projected triangle area (thresholds in pixels^2)
-CRIT_EDGE, CRIT_AREA = 0, 1
+# (thresholds in pixels), projected triangle area (thresholds in pixels^2), or
+# the cull-free distance-only variant (base edge over its midpoint's
+# distance, in pixels, no frustum test)
+CRIT_EDGE, CRIT_AREA, CRIT_DISTANCE = 0, 1, 2
 
 
 @dataclasses.dataclass

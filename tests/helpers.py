@@ -73,8 +73,10 @@ def exact_root_triangles(mesh, lift: bool = False):
         pts = [F3(mesh.pos[mesh.vert[x]]) for x in ring]
         c = tuple(sum(p[i] for p in pts) / len(pts) for i in range(3))
         if lift:
+            # an offset in all three coordinates with coprime denominators,
+            # so that no lifted mean lands on a point of another face
             f = face_of.setdefault(min(ring), len(face_of) + 1)
-            c = (c[0], c[1], c[2] + Fraction(f, 3))
+            c = (c[0] + Fraction(f, 101), c[1] + Fraction(2 * f, 103), c[2] + Fraction(3 * f, 107))
         out.append((F3(mesh.pos[mesh.vert[h]]), F3(mesh.pos[mesh.vert[mesh.next[h]]]), c))
     return out
 

@@ -119,3 +119,47 @@ def test_status_strings():
     lib = _lib()
     for code in range(-7, 1):
         assert lib.cbt_status_string(code)
+
+
+def _header_structs():
+    """Field names, in order, of every typedef'd struct of include/cbt.h."""
+    header = open(os.path.join(ROOT, "include", "cbt.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(\w+)\s*;", header, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            names = decl.split(",")
+            first = re.sub(r"\[.*?\]", "", names[0]).replace("*", " ").split()[-1]
+            fields.append(first)
+            fields += [re.sub(r"\[.*?\]", "", n).replace("*", " ").strip() for n in names[1:]]
+        out[name] = fields
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("cbt_mesh", "Mesh"), ("cbt_camera", "Camera"),
+                                          ("cbt_lod_params", "LodParams"), ("cbt_frame_stats", "FrameStats"),
+                                          ("cbt_bisectors", "Bisectors"), ("cbt_server_config", "ServerConfig"),
+                                          ("cbt_completion", "Completion"), ("cbt_server_stats", "ServerStats")])
+def test_binding_structs_follow_the_header(cname, pyname):
+    """The binding's ctypes structures have the header's fields in the
+    header's order (including cbt_bisectors' canonical root_h / subdiv_id
+    outputs)."""
+    fields = _header_structs()[cname]
+    assert [f for f, _ in getattr(cbt, pyname)._fields_] == fields
+    if cname == "cbt_bisectors":
+        assert fields[-2:] == ["root_h", "subdiv_id"]
+
+
+def test_small_depths_accepted():
+    """Section 3.3: any D >= ceil(log2 H) holds the roots; pools of fewer
+    than 32 blocks keep one partial bitfield word."""
+    _lib()
+    assert cbt.workspace_bytes(12, 4) > 0          # the halfedge-table mesh at D = ceil(log2 12)
+    assert cbt.workspace_bytes(6, 3) > 0           # two triangles at D = 3
+    assert cbt.workspace_bytes(12, 3) == 0
+    st, msg = _init(we1_mesh(), 4, cbt.workspace_bytes(12, 4) - 1)
+    assert st == -6, msg                           # validated up to the workspace size, no device access

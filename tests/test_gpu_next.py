@@ -105,3 +105,32 @@ def test_area_criterion_lockstep():
     log(f"[area] live {inst.live_count()}")
     assert inst.live_count() > 10 * w.mesh.H
     inst.close()
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_distance_criterion_lockstep(precision):
+    """The cull-free distance-only criterion (no frustum merge: bisectors
+    behind the camera refine by distance too) drives a small pool to
+    saturation; frame by frame against the reference."""
+    import dataclasses
+    w = I.workload("planet", frames=256, table_res=64)
+    lod = dataclasses.replace(w.lod, split_px=6.0, merge_px=3.0, criterion=I.CRIT_DISTANCE)
+    D = 15
+    inst = cbt.Instance(w.mesh, D, lod, precision=precision)
+    orc = Oracle(w.mesh, D, lod, precision=precision)
+    rejected = 0
+    for f, cam in enumerate(w.cameras[:90:3]):
+        gst = inst.update(cam, stats=True)
+        ost = orc.frame(camera=cam)
+        gdec = inst.decisions()
+        odec = orc.decisions()[0]
+        was_live = gdec != 255
+        assert was_live.sum() == ost.live_before
+        assert np.array_equal(gdec[was_live], odec[was_live]), f"distance frame {f}: decisions differ"
+        assert gst["allocations"] == ost.allocations and gst["live_after"] == ost.live_after
+        rejected += ost.split_requests - ost.split_accepted
+        assert_same_state(inst, orc, f"distance frame {f}")
+    assert_same_tree(inst, orc, "distance")
+    log(f"[distance] live {inst.live_count()} of {1 << D}, rejected splits {rejected}")
+    assert rejected > 0                      # the pool saturated
+    inst.close()

@@ -3,11 +3,13 @@ interleaved order, are batched continuously (batches of varying membership,
 two launch slots in flight), with a memory budget small enough that idle
 instances are evicted (their live records kept in the arena or on the host)
 and re-admitted.  Every instance
-must end in exactly the state it reaches alone with the same cameras."""
+must end in exactly the state it reaches alone with the same cameras, and
+in the CPU reference's state for those cameras."""
 import numpy as np
 import pytest
 import torch  # noqa: F401
 
+from oracle import Oracle
 from paper_2407_02215_amd import cbt
 from paper_2407_02215_amd import inputs as I
 from tests.gpu_checks import log
@@ -22,6 +24,17 @@ def _alone(w, frames):
     q = inst.query(tree=True)
     inst.close()
     return q
+
+
+def _reference(w, frames):
+    """The CPU reference's state after the same cameras, in query form."""
+    orc = Oracle(w.mesh, w.depth, w.lod)
+    for cam in w.cameras[:frames]:
+        orc.frame(camera=cam)
+    ids, tw, nx, pv = orc.pool()
+    live = np.nonzero(ids)[0]
+    return {"slot": live.astype(np.int32), "heap_id": ids[live], "twin": tw[live], "next": nx[live],
+            "prev": pv[live], "tree": orc.heap()}
 
 
 @pytest.mark.parametrize("room", ["three", "one"])
@@ -62,9 +75,11 @@ def test_served_results_equal_alone(room):
         assert max(sizes_seen) > 1
     for i, w in enumerate(ws):
         ref = _alone(w, len(w.cameras))
+        orc = _reference(w, len(w.cameras))
         got = srv.query(ids[i], tree=True)
         for key in ("slot", "heap_id", "twin", "next", "prev", "tree"):
-            assert np.array_equal(got[key], ref[key]), f"instance {i}: {key} differs"
+            assert np.array_equal(got[key], ref[key]), f"instance {i}: {key} differs from the instance alone"
+            assert np.array_equal(got[key], orc[key]), f"instance {i}: {key} differs from the reference"
     srv.close()
 
 

@@ -8,6 +8,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 from paper_2407_02215_amd import inputs as I
 from paper_2407_02215_amd import traffic
@@ -32,50 +33,81 @@ def _write_counters(path, counter, rows):
 
 
 def test_traffic_from_counter_csvs(tmp_path):
-    """Dispatches of the stage's kernel in protocol order: W warm-up, then
-    the K counted and the K timed ones; the timed pass's mean KiB, scaled by
-    the copy calibration (copy bytes / the copy's counter reading), is the
-    result.  Rows of one dispatch are summed (one per XCD)."""
-    W, K = 2, 3
-    kern = "void cbtk::k_resolve<false>(cbtk::Batch, cbtk::Inst)"
-    other = "void cbtk::k_fill<false, float>(cbtk::Batch, cbtk::Inst)"
-    fetch, write = [], []
+    """Every frame kernel dispatched between the two marker kernels belongs
+    to the timed pass: per stage the counters summed over those dispatches
+    and divided by the timed frames, scaled by the copy calibration (copy
+    bytes / the copy's counter reading); rows of one dispatch (one per XCD)
+    are summed; dispatches outside the markers do not count."""
+    K = 3
+    res = "void cbtk::k_resolve<false>(cbtk::Batch, cbtk::Inst)"
+    fill = "void cbtk::k_fill<false, float>(cbtk::Batch, cbtk::Inst)"
+    red = "void cbtk::k_reduce_top<false>(cbtk::Batch, cbtk::Inst)"
+    spin = "spin_kernel(long)"
+    fetch, write, valu = [], [], []
     d = 0
-    for i in range(W + 2 * K + 1):
-        d += 1
-        fetch += [(d, kern, 100.0 * (i + 1)), (d, kern, 100.0 * (i + 1))]   # two rows: 200 (i+1) KiB
-        write += [(d, kern, 50.0)]
-        d += 1
-        fetch += [(d, other, 1e6)]
-        write += [(d, other, 1e6)]
-    _write_counters(tmp_path / "f.csv", "FETCH_SIZE", fetch)
-    _write_counters(tmp_path / "w.csv", "WRITE_SIZE", write)
+
+    def frame(scale_):
+        nonlocal d
+        for name, f, w in ((res, 100.0, 50.0), (fill, 30.0, 20.0), (red, 1.0, 1.0)):
+            d += 1
+            fetch.extend([(d, name, f * scale_ / 2), (d, name, f * scale_ / 2)])
+            write.append((d, name, w * scale_))
+            valu.append((d, name, 10.0))
+
+    frame(99.0)                      # before the timed pass
+    d += 1
+    fetch.append((d, spin, 5.0)); write.append((d, spin, 5.0)); valu.append((d, spin, 1.0))
+    for _ in range(K):
+        frame(1.0)
+    d += 1
+    fetch.append((d, spin, 5.0)); write.append((d, spin, 5.0)); valu.append((d, spin, 1.0))
+    frame(77.0)                      # after it
+    for n, c, rows in (("f", "FETCH_SIZE", fetch), ("w", "WRITE_SIZE", write), ("v", "SQ_INSTS_VALU", valu)):
+        _write_counters(tmp_path / f"{n}.csv", c, rows)
     copy_kib = traffic.COPY_BYTES / 1024.0
     _write_counters(tmp_path / "cf.csv", "FETCH_SIZE", [(1, "copyBuffer", copy_kib / 2), (2, "copyBuffer", 1.0)])
     _write_counters(tmp_path / "cw.csv", "WRITE_SIZE", [(1, "copyBuffer", copy_kib)])
+    key = traffic.key_of("terrain", "edge", 32, 40, 5, K, [1024, 10])
     t = traffic.measure(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "cf.csv"),
-                        str(tmp_path / "cw.csv"), "resolve", W, K, [1024, 10])
-    timed = [200.0 * (i + 1) for i in range(W + K, W + 2 * K)]
+                        str(tmp_path / "cw.csv"), key, valu=str(tmp_path / "v.csv"))
     assert t["fetch_scale"] == 2.0 and t["write_scale"] == 1.0
-    assert t["fetch_bytes"] == sum(timed) / K * 1024.0 * 2.0
-    assert t["write_bytes"] == 50.0 * 1024.0
-    assert t["bytes_per_launch"] == t["fetch_bytes"] + t["write_bytes"]
+    assert t["kernels"]["resolve"]["fetch_bytes"] == 100.0 * 1024.0 * 2.0
+    assert t["kernels"]["resolve"]["write_bytes"] == 50.0 * 1024.0
+    assert t["kernels"]["fill"]["bytes"] == (30.0 * 2.0 + 20.0) * 1024.0
+    assert t["kernels"]["reduce"]["valu_insts"] == pytest.approx(10.0)
+    assert t["frame_bytes"] == pytest.approx(((100 + 30 + 1) * 2.0 + (50 + 20 + 1)) * 1024.0)
+    assert t["frame_valu_insts"] == pytest.approx(30.0)
     assert t["source_sha256"] == traffic.source_digest()
 
 
-def test_traffic_lookup_requires_same_source_and_schedule(tmp_path, monkeypatch):
+def test_traffic_lookup_requires_same_command_source_and_schedule(tmp_path, monkeypatch):
     table = tmp_path / "traffic.json"
-    rec = {"kernel": "resolve", "bytes_per_launch": 123.0, "warmup": 40, "steps": 200, "schedule": [1024, 10],
-           "source_sha256": traffic.source_digest()}
-    table.write_text(json.dumps(rec))
     monkeypatch.setattr(traffic, "TABLE", str(table))
-    assert traffic.lookup("resolve", 40, 200, [1024, 10]) == 123.0
-    assert traffic.lookup("resolve", 40, 200, [512, 10]) is None
-    assert traffic.lookup("fill", 40, 200, [1024, 10]) is None
-    assert traffic.lookup("resolve", 40, 100, [1024, 10]) is None
-    rec["source_sha256"] = "0" * 64
-    table.write_text(json.dumps(rec))
-    assert traffic.lookup("resolve", 40, 200, [1024, 10]) is None
+    key = traffic.key_of("terrain", "edge", 32, 40, 5, 20, [1024, 10])
+    rec = dict(key, kernels={"resolve": {"bytes": 123.0}}, frame_bytes=456.0, source_sha256=traffic.source_digest())
+    traffic.record(rec)
+    traffic.record(dict(rec, steps=200, frame_bytes=789.0))
+    assert traffic.lookup("terrain", "edge", 32, 40, 5, 20, [1024, 10])["frame_bytes"] == 456.0
+    assert traffic.lookup("terrain", "edge", 32, 40, 5, 200, [1024, 10])["frame_bytes"] == 789.0
+    assert traffic.lookup("terrain", "edge", 32, 40, 5, 20, [512, 10]) is None
+    assert traffic.lookup("terrain", "area", 32, 40, 5, 20, [1024, 10]) is None
+    assert traffic.lookup("terrain", "edge", 32, 0, 5, 20, [1024, 10]) is None
+    traffic.record(dict(rec, frame_bytes=1.0))                # same key: replaced
+    assert len(json.loads(table.read_text())) == 2
+    traffic.record(dict(rec, source_sha256="0" * 64))
+    assert traffic.lookup("terrain", "edge", 32, 40, 5, 20, [1024, 10]) is None
+
+
+def test_byte_models_follow_the_paper_minimal_total():
+    """The paper-minimal per-stage bytes add up to 16 L + 48 S + 24 N +
+    8 hops + 3/8 2^D with hops = S."""
+    sys.path.insert(0, ROOT)
+    import bench
+    st = {"live_before": 1000, "split_consumed": 70, "allocations": 150, "frees": 90, "merge_requests": 300,
+          "merges_executed": 5, "merge_candidates": 120, "merge_configs": 12}
+    D = 14
+    assert bench.paper_bytes("frame", st, D) == 16 * 1000 + 48 * 70 + 24 * 150 + 8 * 70 + 3 / 8 * (1 << D)
+    assert bench.layout_bytes("frame", st, D) > bench.paper_bytes("frame", st, D)
 
 
 def test_input_generators_are_seeded():

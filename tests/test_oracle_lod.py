@@ -265,3 +265,82 @@ def test_area_criterion_closed_form():
         # root 0 sits in block 0 (roots never merge; a split is not overridden)
         assert dec[0] == want
         assert abs(float(A[0]) / (2.0 * area * float(Bs[0]) / (2.0 * np.float32(thr))) - 1.0) < 1e-5
+
+
+def _distance_decide64(p, cam_pos, split_px, merge_px, f):
+    """Cull-free distance-only decision in float64: the base edge's length
+    over its midpoint's distance, in pixels (f e / r)."""
+    e = np.linalg.norm(p[1] - p[0])
+    r = np.linalg.norm(0.5 * (p[0] + p[1]) - cam_pos)
+    px = f * e / r
+    margin = min(abs(px - split_px) / split_px, abs(px - merge_px) / merge_px)
+    if px > split_px:
+        return I.DEC_SPLIT, margin
+    if px < merge_px:
+        return I.DEC_MERGE, margin
+    return I.DEC_KEEP, margin
+
+
+def test_distance_criterion_closed_form():
+    """Base edge of length e whose midpoint is at distance r from the camera
+    subtends f e / r pixels whatever the view direction: with the camera
+    looking away from the mesh (every vertex behind it, which the frustum
+    criteria would merge) the root still splits just below that threshold
+    and keeps just above it."""
+    pos = np.array([[-0.25, 0.0, 4.0], [0.25, 0.0, 4.0], [0.0, 0.5, 4.0]], np.float32)
+    m = I.halfedge_from_faces([[0, 1, 2]], pos)
+    f = 0.5 * 600 / math.tan(math.radians(30.0))
+    e, r = 0.5, 4.0                      # root 0: v0 = (-0.25, 0, 4), v1 = (0.25, 0, 4)
+    px = f * e / r
+    for fwd in ((0, 0, 1), (0, 0, -1), (1, 0, 0)):
+        cam = _cam(60.0, 800, 600, 0.05, pos=(0, 0, 0), fwd=fwd, up=(0, 1, 0))
+        for thr, want in ((px * 0.999, I.DEC_SPLIT), (px * 1.001, I.DEC_KEEP)):
+            o = Oracle(m, 4, I.LodParams(I.MODE_FLAT, thr, thr / 4, criterion=I.CRIT_DISTANCE))
+            o.frame(camera=cam)
+            dec, A, Bs, _ = o.decisions()
+            assert dec[0] == want, (fwd, thr)
+            # A / Bs = (f e)^2 / (thr r)^2
+            assert abs(float(A[0]) / float(Bs[0]) / (px / float(np.float32(thr))) ** 2 - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_distance_decisions_match_float64(seed):
+    """The distance-only criterion agrees with a float64 evaluation of
+    f |p1 - p0| / |m - c| outside a 1e-4 relative band, for bisectors in
+    front of and behind the camera alike (no frustum merge)."""
+    m = _flat_mesh_in_front(seed)
+    o = Oracle(m, 12, I.LodParams(I.MODE_FLAT, 30.0, 12.0, criterion=I.CRIT_DISTANCE))
+    for _ in range(4):
+        o.frame(decisions=np.ones(o.cap, np.uint8))
+    cam = _cam(70.0, 640, 480, 0.05, pos=(0.1, -0.2, 2.1), fwd=(0.3, 0.05, 1.0), up=(0.0, 1.0, 0.1))
+    th = math.tan(0.5 * cam.fovy)
+    f = 0.5 * cam.height / th
+    ids = o.pool()[0]
+    verts = o.vertices()
+    live = np.nonzero(ids)[0]
+    cpos = cam.pos.astype(np.float64)
+    px = []
+    for s in live:
+        v = verts[s].reshape(3, 3).astype(np.float64)
+        px.append(f * np.linalg.norm(v[1] - v[0]) / np.linalg.norm(0.5 * (v[0] + v[1]) - cpos))
+    split_px, merge_px = float(np.quantile(px, 0.7)), float(np.quantile(px, 0.3))
+    o.set_lod(I.LodParams(I.MODE_FLAT, split_px, merge_px, criterion=I.CRIT_DISTANCE))
+    o.frame(camera=cam)
+    dec = o.decisions()[0]
+    split_px, merge_px = float(np.float32(split_px)), float(np.float32(merge_px))
+    behind = 0
+    kinds = set()
+    n_checked = 0
+    K = o.frame_constants(cam)
+    for s in live:
+        v = verts[s].reshape(3, 3).astype(np.float64)
+        want, margin = _distance_decide64(v, cpos, split_px, merge_px, f)
+        if margin < 1e-4:
+            continue
+        assert dec[s] == want, (s, dec[s], want)
+        kinds.add(want)
+        n_checked += 1
+        behind += int(((v - K[0:3].astype(np.float64)) @ K[9:12].astype(np.float64) < 0).all())
+    assert n_checked > 0.9 * live.size
+    assert kinds == {I.DEC_SPLIT, I.DEC_MERGE, I.DEC_KEEP}
+    assert behind > 0          # bisectors behind the camera are decided by size, not culled
