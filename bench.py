@@ -425,7 +425,7 @@ def run_batch(args) -> dict:
 
     frames = args.warmup + args.steps
     print(f"# building {args.instances} instances", file=sys.stderr, flush=True)
-    ws = I.batched_workloads(args.instances, frames=frames, seed=4)
+    ws = I.batched_workloads(args.instances, frames=frames, seed=4, workers=16)
     insts = [cbt.Instance(w.mesh, w.depth, w.lod, tuned=True) for w in ws]
     print(f"# warm-up {args.warmup} frames (one launch sequence per instance)", file=sys.stderr, flush=True)
     for f in range(args.warmup):
@@ -500,19 +500,29 @@ def run_serve(args) -> dict:
     gaps = rng.exponential(1.0 / args.rate, n_req)
     arrivals = np.cumsum(gaps)
     new_frac = 0.10
-    base = I.batched_workloads(args.meshes, frames=64, seed=4)
     depth_lo, depth_hi = 14, 22
-    specs = []   # (workload, depth, cameras) per instance, resident ones first
+    # resident instances: members 0 .. n-1 of a batched configuration (each
+    # its own mesh, depth and camera path); arriving instances: the next
+    # new_pool members, in turn, then the same meshes again with a fresh
+    # depth and camera path
+    print(f"# building {args.instances} + {args.new_pool} instances", file=sys.stderr, flush=True)
+    resident = I.batched_workloads(args.instances, frames=64, seed=1000, workers=16)
+    pool = I.batched_workloads(args.new_pool, frames=64, seed=1000, first=args.instances, workers=16)
+    specs = [(w, w.depth, w.cameras) for w in resident]   # (workload, depth, cameras) per instance
+    n_new = 0
 
     def new_spec():
-        w = base[int(rng.integers(len(base)))]
-        D = I.depth_for(w.mesh.H, int(rng.integers(depth_lo, depth_hi + 1)))
-        cams = I.camera_path_orbit(64, int(rng.integers(1 << 30)))
+        nonlocal n_new
+        w = pool[n_new % len(pool)]
+        if n_new < len(pool):
+            D, cams = w.depth, w.cameras
+        else:
+            D = I.depth_for(w.mesh.H, int(rng.integers(depth_lo, depth_hi + 1)))
+            cams = I.camera_path_orbit(64, int(rng.integers(1 << 30)))
+        n_new += 1
         specs.append((w, D, cams))
         return len(specs) - 1
 
-    for _ in range(args.instances):
-        new_spec()
     trace = []   # (arrival, spec index, camera index)
     counts = {}
     for t in arrivals:
@@ -599,7 +609,9 @@ def run_serve(args) -> dict:
         "data": "synthetic (seeded workload generator)",
         "config": {"workload": "served", "rate_per_s": args.rate, "duration_s": args.duration,
                    "resident_instances": args.instances, "new_instance_fraction": new_frac,
-                   "distinct_meshes": args.meshes, "arena_gib": arena / 2**30},
+                   "instances_opened": len(specs), "distinct_meshes": args.instances + min(n_new, args.new_pool),
+                   "arena_gib": arena / 2**30,
+                   "admission_footprint": "workspace bytes per instance (about 112 per pool block)"},
     }
 
 
@@ -621,7 +633,8 @@ def main():
                          "the cull-free distance-only variant")
     ap.add_argument("--camera", type=int, default=255, help="camera index (converge mode)")
     ap.add_argument("--instances", type=int, default=None)
-    ap.add_argument("--meshes", type=int, default=32)
+    ap.add_argument("--new-pool", type=int, default=1024,
+                    help="serve mode: distinct meshes for arriving instances (reused in turn after that)")
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=60.0, help="serve mode: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0)

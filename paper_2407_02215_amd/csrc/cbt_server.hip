@@ -16,6 +16,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -58,6 +59,11 @@ struct SInst {
     int slot = -1;
     double last_used = 0.0;
     bool failed = false;
+    int64_t live = 0;          // live bisectors after its last frame (the export's size)
+    bool in_idle = false;      // listed in the server's idle set
+    bool in_ready = false;     // listed in the server's ready set
+    double idle_key = 0.0;     // its key in the idle set (last use)
+    double ready_key = 0.0;    // arrival time of the request it is listed with
 };
 
 struct Slot {
@@ -84,6 +90,12 @@ struct cbt_server_s {
     size_t inst_base = 0, inst_bytes = 0, budget = 0, used = 0;
     std::map<size_t, size_t> free_;    // offset -> length, within the instance area
     hipStream_t aux = nullptr;         // admission, eviction and queries
+    hipEvent_t aux_done = nullptr;     // the auxiliary stream's work so far (batches wait on it)
+    bool aux_pending = false;          // work was queued on it since the last event
+    // instances with a queued request and none in flight, by the arrival of
+    // their oldest request; resident idle instances (nothing queued or in
+    // flight) by last use -- the eviction order
+    std::set<std::pair<double, int64_t>> ready, idle;
     std::vector<Slot> slots;
     std::unordered_map<int64_t, SInst> inst;
     int64_t next_id = 1;
@@ -156,10 +168,6 @@ void arena_free(cbt_server s, size_t off, size_t bytes)
 
 char* inst_ptr(cbt_server s, size_t off) { return s->arena + s->inst_base + off; }
 
-// Evicts a resident instance: its live records (24 bytes per live bisector)
-// are exported into its own vertex cache (48 bytes per block), copied to
-// the arena's top end (or to the host when that is full) and the workspace
-// is released.  Ordered on the auxiliary stream before any reuse.
 void add_time(double* total, double* longest, double t0)
 {
     const double ms = (now_s() - t0) * 1e3;
@@ -167,18 +175,57 @@ void add_time(double* total, double* longest, double t0)
     *longest = ms > *longest ? ms : *longest;
 }
 
+// Keeps the instance's entries in the ready set (a queued request, none in
+// flight) and the idle set (resident, nothing queued or in flight, not
+// failed) in step with its state; called after every change of I.h,
+// I.slot, I.q, I.last_used or I.failed.
+void refresh_sets(cbt_server s, SInst& I)
+{
+    if (I.in_idle) {
+        s->idle.erase({I.idle_key, I.id});
+        I.in_idle = false;
+    }
+    if (I.h && I.slot < 0 && I.q.empty() && !I.failed) {
+        I.idle_key = I.last_used;
+        s->idle.insert({I.idle_key, I.id});
+        I.in_idle = true;
+    }
+    if (I.in_ready) {
+        s->ready.erase({I.ready_key, I.id});
+        I.in_ready = false;
+    }
+    if (!I.q.empty() && I.slot < 0) {
+        I.ready_key = I.q.front().t_arrive;
+        s->ready.insert({I.ready_key, I.id});
+        I.in_ready = true;
+    }
+}
+
+// Releases a handle without waiting: every later use of its workspace range
+// (an admission's set-up, a snapshot copy) is queued on the same auxiliary
+// stream, and an idle instance has no batch in flight.
+void release_handle(cbt_handle h)
+{
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    cbth::release_counters(h->hctr);
+    delete h;
+}
+
+// Evicts a resident idle instance: its live records (24 bytes per live
+// bisector; their number is known from its last frame) are exported into
+// its own vertex cache (48 bytes per block), copied to the arena's top end
+// (or to the host when that is full) and the workspace is released.  All on
+// the auxiliary stream, which only the host-snapshot path waits for.
 cbt_status evict(cbt_server s, SInst& I)
 {
     if (!I.h) return CBT_OK;
     const double t0 = now_s();
-    const cbtk::Pool& P = I.h->P;
+    cbt_handle h = I.h;
+    const cbtk::Pool& P = h->P;
     uint32_t* rec = reinterpret_cast<uint32_t*>(P.vworld);
-    int64_t n = 0;
-    cbt_status st = cbt_export_live(I.h, rec, 2 * (int64_t)P.cap, &n);
-    if (st) {
-        I.failed = true;
-        return st;
-    }
+    const uint32_t n = (uint32_t)I.live;
+    HIP_TRY(nullptr, cbtk::launch_enumerate(cbtk::single_launch(P, h->wk, nullptr), s->aux), "enumerate");
+    HIP_TRY(nullptr, cbtk::launch_export_live(P, n, rec, s->aux), "export live records");
     const size_t bytes = sizeof(uint32_t) * 6 * (size_t)n;
     size_t off = 0;
     if (arena_alloc_top(s, bytes, &off)) {
@@ -189,16 +236,19 @@ cbt_status evict(cbt_server s, SInst& I)
     } else {
         I.snap_host.resize(6 * (size_t)n);
         HIP_TRY(nullptr, hipMemcpyAsync(I.snap_host.data(), rec, bytes, hipMemcpyDeviceToHost, s->aux), "snapshot copy");
+        HIP_TRY(nullptr, hipStreamSynchronize(s->aux), "snapshot copy");
         I.snap = SInst::kHostSnap;
         s->st.host_snapshots++;
     }
     I.snap_n = n;
-    cbt_destroy(I.h);   // synchronises the auxiliary stream
+    release_handle(h);
     I.h = nullptr;
     arena_free(s, I.off, I.bytes);
+    s->aux_pending = true;
     s->st.evictions++;
     s->st.resident--;
     s->st.bytes_resident = (int64_t)s->used;
+    refresh_sets(s, I);
     add_time(&s->st.evict_ms, &s->st.evict_ms_max, t0);
     return CBT_OK;
 }
@@ -226,10 +276,32 @@ void drop_snapshot(cbt_server s, SInst& I)
     s->st.bytes_resident = (int64_t)s->used;
 }
 
+// The state of a handle set up for an import, from live records in device
+// memory, queued on the handle's stream without waiting: the pool cleared,
+// the records scattered, the bitfield, the sum-reduction tree and the
+// vertex cache rebuilt.  A record out of range raises the device error flag,
+// which the instance's next frame reports.
+cbt_status import_async(cbt_handle h, const uint32_t* records, uint32_t n)
+{
+    const cbtk::Pool& P = h->P;
+    hipStream_t st = h->stream;
+    const cbtk::Launch X = cbtk::single_launch(P, h->wk, nullptr);
+    HIP_TRY(h, cbtk::launch_clear_pool(P, st), "clear pool");
+    HIP_TRY(h, cbtk::launch_import_live(P, n, records, st), "import live records");
+    HIP_TRY(h, cbtk::launch_bits_from_ids(P, st), "bitfield");
+    HIP_TRY(h, cbtk::launch_reduce(X, st), "sum reduction");
+    HIP_TRY(h, cbtk::launch_refresh(X, st), "vertex cache");
+    h->last_frame_valid = 0;
+    return CBT_OK;
+}
+
 // Makes I resident: allocates its workspace, initialises it and imports its
 // records.  When the budget is exhausted, idle resident instances are
 // evicted, least recently used first, then the oldest snapshots in the arena
-// move to the host.  CBT_E_BUDGET: cannot fit now.
+// move to the host.  CBT_E_BUDGET: cannot fit now.  The set-up of an
+// evicted instance from its records in the arena is queued on the auxiliary
+// stream without waiting (batches wait for that stream's event); a new
+// instance (the base mesh) and records on the host are set up synchronously.
 cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
 {
     if (I.h) return CBT_OK;
@@ -237,17 +309,18 @@ cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
     if (!bytes) return cbth::fail(nullptr, CBT_E_DEPTH, "instance %lld: invalid depth", (long long)I.id);
     if (round_up(bytes) > s->budget) {
         I.failed = true;
+        refresh_sets(s, I);
         return cbth::fail(nullptr, CBT_E_BUDGET, "instance %lld needs %zu bytes, budget %zu", (long long)I.id, bytes,
                           s->budget);
     }
     size_t off = 0;
     while (!arena_alloc(s, bytes, &off)) {
         SInst* victim = nullptr;
-        for (auto& kv : s->inst) {
-            SInst& J = kv.second;
-            if (!J.h || J.slot >= 0 || &J == &I || !J.q.empty()) continue;
-            if (std::find(pinned.begin(), pinned.end(), J.id) != pinned.end()) continue;
-            if (!victim || J.last_used < victim->last_used) victim = &J;
+        for (const auto& e : s->idle) {
+            SInst& J = s->inst[e.second];
+            if (&J == &I || std::find(pinned.begin(), pinned.end(), J.id) != pinned.end()) continue;
+            victim = &J;
+            break;
         }
         if (victim) {
             cbt_status st = evict(s, *victim);
@@ -275,26 +348,37 @@ cbt_status admit(cbt_server s, SInst& I, const std::vector<int64_t>& pinned)
     if (st) {
         arena_free(s, off, bytes);
         I.failed = true;
+        refresh_sets(s, I);
         return st;
     }
     if (I.groups) st = cbt_set_schedule(h, I.groups, I.levels);
+    if (!st && I.snap != SInst::kNoSnap) {
+        // the vertex cache is rebuilt with the instance's own world-position
+        // parameters (the camera does not enter them)
+        const cbt_camera probe{{0, 0, 1}, {0, 0, -1}, {0, 1, 0}, 1.0f, 16, 16, 1e-3f};
+        cbth::make_lodk(&probe, &I.lod, &h->wk);
+    }
     if (!st && I.snap == SInst::kDevSnap)
-        st = cbt_import_live(h, reinterpret_cast<const uint32_t*>(inst_ptr(s, I.snap_off)), I.snap_n, 0);
+        st = import_async(h, reinterpret_cast<const uint32_t*>(inst_ptr(s, I.snap_off)), (uint32_t)I.snap_n);
     else if (!st && I.snap == SInst::kHostSnap)
         st = cbt_import_live(h, I.snap_host.data(), I.snap_n, 1);
     if (st) {
         cbt_destroy(h);
         arena_free(s, off, bytes);
         I.failed = true;
+        refresh_sets(s, I);
         return st;
     }
+    I.live = I.snap == SInst::kNoSnap ? I.H : I.snap_n;
     drop_snapshot(s, I);
     I.h = h;
     I.off = off;
     I.bytes = bytes;
+    s->aux_pending = true;
     s->st.admissions++;
     s->st.resident++;
     s->st.bytes_resident = (int64_t)s->used;
+    refresh_sets(s, I);
     add_time(&s->st.admit_ms, &s->st.admit_ms_max, t0);
     return CBT_OK;
 }
@@ -316,6 +400,16 @@ void complete(cbt_server s, SInst& I, const Req& r, cbt_status status, const Cou
     s->done_q.push_back(o);
 }
 
+// Completes the queued requests of a failed instance.
+void fail_queued(cbt_server s, SInst& I, cbt_status st)
+{
+    while (!I.q.empty()) {
+        complete(s, I, I.q.front(), st, nullptr, now_s(), 0, now_s());
+        I.q.pop_front();
+    }
+    refresh_sets(s, I);
+}
+
 // Collects a finished batch.
 void harvest(cbt_server s, Slot& S)
 {
@@ -333,12 +427,14 @@ void harvest(cbt_server s, Slot& S)
             if (I.h) I.h->failed = 1;
         } else if (I.h) {
             I.h->last_frame_valid = 1;
+            I.live = (int64_t)c.L + c.N - c.stat[cbtk::kStFrees];
         }
         I.slot = -1;
         I.last_used = t;
         s->st.frames++;
         s->st.bisector_updates += c.L;
         complete(s, I, S.reqs[i], status, &c, S.t_launch, n, t);
+        refresh_sets(s, I);
     }
     S.ids.clear();
     S.reqs.clear();
@@ -348,56 +444,41 @@ void harvest(cbt_server s, Slot& S)
 
 cbt_status launch_slot(cbt_server s, Slot& S)
 {
-    // candidates: queued, idle, not failed; oldest request first
-    std::vector<SInst*> cand;
-    for (auto& kv : s->inst) {
-        SInst& I = kv.second;
-        if (I.q.empty() || I.slot >= 0) continue;
-        if (I.failed) {
-            while (!I.q.empty()) {
-                complete(s, I, I.q.front(), CBT_E_STATE, nullptr, now_s(), 0, now_s());
-                I.q.pop_front();
-            }
-            continue;
-        }
-        cand.push_back(&I);
-    }
-    if (cand.empty()) return CBT_OK;
-    std::sort(cand.begin(), cand.end(),
-              [](const SInst* a, const SInst* b) { return a->q.front().t_arrive < b->q.front().t_arrive; });
+    if (s->ready.empty()) return CBT_OK;
+    // candidates: the ready set, oldest request first
     std::vector<SInst*> pick;
     std::vector<int64_t> pinned;
     uint64_t nr = 0, nw = 0, nd = 0, nl = 0;
     // Once one admission of this pass has found no memory (after evicting
     // every idle instance it could), the other non-resident candidates wait
-    // for a later pass; resident ones are still picked.  Without this, a
-    // backlog made every launch retry every waiting admission, each scanning
-    // all instances.
+    // for a later pass; resident ones are still picked.
     bool no_memory = false;
-    for (SInst* I : cand) {
-        if ((int32_t)pick.size() >= s->cfg.max_batch) break;
-        if (!I->h && no_memory) continue;
-        cbt_status st = admit(s, *I, pinned);
-        if (st == CBT_E_BUDGET && !I->failed) {   // waits for memory
+    for (auto it = s->ready.begin(); it != s->ready.end() && (int32_t)pick.size() < s->cfg.max_batch;) {
+        SInst& I = s->inst[it->second];
+        ++it;   // I's own entry may be re-inserted below; the next one stays valid
+        if (I.failed) {
+            fail_queued(s, I, CBT_E_STATE);
+            continue;
+        }
+        if (!I.h && no_memory) continue;
+        cbt_status st = admit(s, I, pinned);
+        if (st == CBT_E_BUDGET && !I.failed) {   // waits for memory
             no_memory = true;
             continue;
         }
         if (st) {
-            while (!I->q.empty()) {
-                complete(s, *I, I->q.front(), st, nullptr, now_s(), 0, now_s());
-                I->q.pop_front();
-            }
+            fail_queued(s, I, st);
             continue;
         }
-        const cbtk::Pool& P = I->h->P;
+        const cbtk::Pool& P = I.h->P;
         const uint64_t r = P.G, w = cbtk::word_groups(P), d = cbtk::reduce_groups(P), l = cbtk::list_groups(P);
         if ((nr + r) + (nw + w) + (nd + d) + (nl + l) > (uint64_t)s->cfg.map_capacity) break;
         nr += r;
         nw += w;
         nd += d;
         nl += l;
-        pick.push_back(I);
-        pinned.push_back(I->id);
+        pick.push_back(&I);
+        pinned.push_back(I.id);
     }
     if (pick.empty()) return CBT_OK;
     const int n = (int)pick.size();
@@ -417,7 +498,8 @@ cbt_status launch_slot(cbt_server s, Slot& S)
         cbt_handle h = I.h;
         if (cbth::world_changed(K, h->wk)) {
             h->wk = K;
-            HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), S.stream), "vertex cache");
+            HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), s->aux), "vertex cache");
+            s->aux_pending = true;
         }
         S.h_inst[i].P = h->P;
         S.h_inst[i].K = K;
@@ -428,6 +510,7 @@ cbt_status launch_slot(cbt_server s, Slot& S)
         for (uint32_t g = 0; g < cbtk::reduce_groups(h->P); ++g) md[ad++] = tag | g;
         for (uint32_t g = 0; g < cbtk::list_groups(h->P); ++g) ml[al++] = tag | g;
         I.slot = (int)(&S - s->slots.data());
+        refresh_sets(s, I);
         S.ids.push_back(I.id);
         S.reqs.push_back(r);
     }
@@ -445,6 +528,13 @@ cbt_status launch_slot(cbt_server s, Slot& S)
     X.grid_red = (uint32_t)nd;
     X.grid_list = (uint32_t)nl;
     hipStream_t st = S.stream;
+    // admissions, evictions and cache refreshes queued on the auxiliary
+    // stream come first
+    if (s->aux_pending) {
+        HIP_TRY(nullptr, hipEventRecord(s->aux_done, s->aux), "auxiliary event");
+        s->aux_pending = false;
+    }
+    HIP_TRY(nullptr, hipStreamWaitEvent(st, s->aux_done, 0), "wait for admissions");
     HIP_TRY(nullptr, hipMemcpyAsync(S.d_inst, S.h_inst, sizeof(Inst) * (size_t)n, hipMemcpyHostToDevice, st), "descriptors");
     HIP_TRY(nullptr, hipMemcpyAsync(S.d_map, S.h_map, 4 * (size_t)(nr + nw + nd + nl), hipMemcpyHostToDevice, st),
             "block maps");
@@ -546,7 +636,9 @@ cbt_status cbt_server_create(const cbt_server_config* cfg, void* device_arena, s
                                                                                       : s->inst_bytes;
     s->free_[0] = s->inst_bytes;
     s->st.bytes_budget = (int64_t)s->budget;
-    bool ok = hipStreamCreate(&s->aux) == hipSuccess;
+    bool ok = hipStreamCreate(&s->aux) == hipSuccess &&
+              hipEventCreateWithFlags(&s->aux_done, hipEventDisableTiming) == hipSuccess &&
+              hipEventRecord(s->aux_done, s->aux) == hipSuccess;
     s->slots.resize(cfg->slots);
     for (int i = 0; i < cfg->slots && ok; ++i) {
         Slot& S = s->slots[i];
@@ -566,6 +658,7 @@ cbt_status cbt_server_create(const cbt_server_config* cfg, void* device_arena, s
     }
     if (!ok) {
         destroy_slots(s);
+        if (s->aux_done) (void)hipEventDestroy(s->aux_done);
         if (s->aux) (void)hipStreamDestroy(s->aux);
         delete s;
         return cbth::fail(nullptr, CBT_E_DEVICE, "stream, event or pinned allocation failed");
@@ -650,6 +743,7 @@ cbt_status cbt_server_submit(cbt_server s, int64_t instance_id, const cbt_camera
     cbt_status st = cbth::check_lod(nullptr, camera, &I.lod);
     if (st) return st;
     I.q.push_back(Req{tag, *camera, now_s()});
+    refresh_sets(s, I);
     s->st.requests++;
     return CBT_OK;
 }
@@ -715,7 +809,8 @@ cbt_status cbt_server_query(cbt_server s, int64_t instance_id, cbt_bisectors* ou
     cbt_status st = admit(s, I, none);
     if (st) return st;
     I.last_used = now_s();
-    return cbt_query(I.h, out);
+    refresh_sets(s, I);
+    return cbt_query(I.h, out);   // on the auxiliary stream, after the admission
 }
 
 cbt_status cbt_server_close(cbt_server s, int64_t instance_id)
@@ -733,6 +828,8 @@ cbt_status cbt_server_close(cbt_server s, int64_t instance_id)
         complete(s, I, I.q.front(), CBT_E_STATE, nullptr, now_s(), 0, now_s());
         I.q.pop_front();
     }
+    if (I.in_idle) s->idle.erase({I.idle_key, I.id});
+    if (I.in_ready) s->ready.erase({I.ready_key, I.id});
     if (I.h) {
         cbt_destroy(I.h);
         arena_free(s, I.off, I.bytes);
@@ -765,6 +862,7 @@ cbt_status cbt_server_destroy(cbt_server s)
         (void)hipStreamSynchronize(s->aux);
         (void)hipStreamDestroy(s->aux);
     }
+    if (s->aux_done) (void)hipEventDestroy(s->aux_done);
     delete s;
     return CBT_OK;
 }

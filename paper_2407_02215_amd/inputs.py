@@ -530,23 +530,37 @@ def workload(name: str, frames: int | None = None, table_res: int | None = None)
     raise KeyError(name)
 
 
+def _batched_member(args) -> tuple:
+    """Mesh, depth and camera path of member i of a batched configuration,
+    drawn from a generator seeded by (seed, i) alone, so that members can be
+    built in any order or in parallel."""
+    i, seed, frames, h_range, d_range = args
+    rng = np.random.default_rng([seed, i])
+    lo, hi = math.log(h_range[0]), math.log(h_range[1])
+    target = int(round(math.exp(rng.uniform(lo, hi))))
+    mesh = random_mesh_of_size(max(24, target), int(rng.integers(1 << 30)))
+    D = depth_for(mesh.H, int(rng.integers(d_range[0], d_range[1] + 1)))
+    cams = camera_path_orbit(frames, int(rng.integers(1 << 30)))
+    return mesh, D, cams
+
+
 def batched_workloads(n: int, frames: int = 64, seed: int = 4, h_range=(24, 50000), d_range=(14, 22),
-                      table_res: int = 256) -> List[Workload]:
+                      table_res: int = 256, first: int = 0, workers: int = 1) -> List[Workload]:
     """Independent instances for the batched configuration: closed tri/quad
     sphere meshes with a log-uniform halfedge count in h_range, CBT depth
     uniform in d_range (raised to ceil(log2 H) where needed), sphere
     projection with one shared seeded fBm cube map (amplitude 1e-3 radius),
     and a seeded orbit camera path of its own per instance (4 -> 1.05 radii,
-    split above 4 px, merge below 2 px at 1920x1080)."""
-    rng = np.random.default_rng(seed)
+    split above 4 px, merge below 2 px at 1920x1080).  Members first ..
+    first + n - 1 of the configuration seeded by seed; workers > 1 builds
+    them in that many processes."""
     table = fbm_cubemap(table_res, seed=seed + 101)
     lod = LodParams(MODE_SPHERE, 4.0, 2.0, table, 1e-3)
-    out = []
-    lo, hi = math.log(h_range[0]), math.log(h_range[1])
-    for i in range(n):
-        target = int(round(math.exp(rng.uniform(lo, hi))))
-        mesh = random_mesh_of_size(max(24, target), int(rng.integers(1 << 30)))
-        D = depth_for(mesh.H, int(rng.integers(d_range[0], d_range[1] + 1)))
-        cams = camera_path_orbit(frames, int(rng.integers(1 << 30)))
-        out.append(Workload(f"batched-{i}", mesh, D, lod, cams))
-    return out
+    jobs = [(i, seed, frames, tuple(h_range), tuple(d_range)) for i in range(first, first + n)]
+    if workers > 1 and n > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, n)) as pool:
+            members = pool.map(_batched_member, jobs, chunksize=max(1, n // (4 * workers)))
+    else:
+        members = [_batched_member(j) for j in jobs]
+    return [Workload(f"batched-{i}", mesh, D, lod, cams) for (i, *_), (mesh, D, cams) in zip(jobs, members)]
