@@ -336,6 +336,14 @@ cbt_status cbt_get_schedule(cbt_handle h, int32_t* rank_groups, int32_t* reduce_
  *    descriptors (outside the graph) and replay it. */
 typedef struct cbt_batch_s* cbt_batch;
 #define CBT_BATCH_GRAPH 1
+/* One persistent launch per frame instead of one launch per stage: the
+ * resident workgroups take (stage, instance, workgroup) items in order from
+ * a counter and each item waits until its instance has finished the
+ * previous stage (per-instance counters), so instances proceed through the
+ * pipeline independently (Section 3.3's nine kernels fused).  Same results
+ * bit for bit.  A wait that exceeds its bound is reported as CBT_E_DEVICE
+ * by the next update that reads statistics. */
+#define CBT_BATCH_PERSISTENT 2
 
 /* 0 when the member list is invalid (NULL, repeated or failed handles,
  * members of both precisions, n outside [1, 4096]). */

@@ -395,13 +395,15 @@ class Instance:
 
 
 BATCH_GRAPH = 1
+BATCH_PERSISTENT = 2
 
 
 class Batch:
     """Instances advanced together: one launch per pipeline stage for all of
-    them, optionally replayed from a captured HIP graph (cbt_batch_*)."""
+    them, or one persistent launch per frame (persistent=True), optionally
+    replayed from a captured HIP graph (cbt_batch_*)."""
 
-    def __init__(self, instances, graph: bool = True, stream=None):
+    def __init__(self, instances, graph: bool = True, stream=None, persistent: bool = False):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -416,7 +418,8 @@ class Batch:
         self.stream = stream if stream is not None else torch.cuda.Stream(dev)
         h = C.c_void_p()
         st = self.lib.cbt_batch_create(self._handles, n, C.c_void_p(self.workspace.data_ptr()), nbytes,
-                                       C.c_void_p(self.stream.cuda_stream), BATCH_GRAPH if graph else 0,
+                                       C.c_void_p(self.stream.cuda_stream),
+                                       (BATCH_GRAPH if graph else 0) | (BATCH_PERSISTENT if persistent else 0),
                                        C.byref(h))
         if st != CBT_OK:
             raise CbtError(st, self.lib.cbt_last_error(None).decode())

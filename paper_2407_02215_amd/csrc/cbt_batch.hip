@@ -41,12 +41,13 @@ struct cbt_batch_s {
 namespace {
 
 struct Layout {
-    size_t inst, ctr, map_rank, map_word, map_red, map_list, total;
+    size_t inst, ctr, map_rank, map_word, map_red, map_list, ticket, done, pmap, total;
 };
 
-// workgroups of the batched grids: rank, bitfield-word, reduction and list
+// workgroups of the batched grids: rank, bitfield-word, reduction and
+// list; items of the persistent frame
 struct Grids {
-    uint64_t nr, nw, nd, nl;
+    uint64_t nr, nw, nd, nl, items;
 };
 
 Layout batch_layout(int n, const Grids& g)
@@ -64,6 +65,9 @@ Layout batch_layout(int n, const Grids& g)
     L.map_word = take(4 * g.nw);
     L.map_red = take(4 * g.nd);
     L.map_list = take(4 * g.nl);
+    L.ticket = take(4);
+    L.done = take(4 * (size_t)n * cbtk::kPhCount);
+    L.pmap = take(4 * g.items);
     L.total = off;
     return L;
 }
@@ -85,13 +89,14 @@ cbt_status check_members(const cbt_handle* members, int32_t n)
 
 Grids grid_totals(const cbt_handle* members, int32_t n)
 {
-    Grids g{0, 0, 0, 0};
+    Grids g{0, 0, 0, 0, 0};
     for (int i = 0; i < n; ++i) {
         const Pool& P = members[i]->P;
         g.nr += P.G;
         g.nw += cbtk::word_groups(P);
         g.nd += cbtk::reduce_groups(P);
         g.nl += cbtk::list_groups(P);
+        for (int p = 0; p < cbtk::kPhCount; ++p) g.items += cbtk::persist_items_host(cbtk::phase_groups_host(P, p));
     }
     return g;
 }
@@ -188,7 +193,8 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
     *out = nullptr;
     cbt_status st = check_members(members, n);
     if (st) return st;
-    if (flags & ~CBT_BATCH_GRAPH) return cbth::fail(nullptr, CBT_E_ARG, "unknown batch flags 0x%x", flags);
+    if (flags & ~(CBT_BATCH_GRAPH | CBT_BATCH_PERSISTENT))
+        return cbth::fail(nullptr, CBT_E_ARG, "unknown batch flags 0x%x", flags);
     if ((flags & CBT_BATCH_GRAPH) && !hip_stream)
         return cbth::fail(nullptr, CBT_E_ARG, "graph capture needs a stream other than the null stream");
     const Grids gt = grid_totals(members, n);
@@ -283,6 +289,35 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
     X.grid_word = (uint32_t)gt.nw;
     X.grid_red = (uint32_t)gt.nd;
     X.grid_list = (uint32_t)gt.nl;
+    if (flags & CBT_BATCH_PERSISTENT) {
+        // items phase by phase, in each phase instance by instance; an item
+        // is a span of the instance's workgroups for the phase
+        std::vector<uint32_t> pm;
+        pm.reserve(gt.items);
+        uint64_t at = 0;
+        for (int p = 0; p < cbtk::kPhCount; ++p) {
+            X.W.first[p] = (uint32_t)at;
+            for (int i = 0; i < n; ++i) {
+                const uint32_t k = cbtk::persist_items_host(cbtk::phase_groups_host(b->pools[i], p));
+                for (uint32_t t = 0; t < k; ++t) pm.push_back(((uint32_t)i << cbtk::kMapShift) | t);
+                at += k;
+            }
+        }
+        X.W.first[cbtk::kPhCount] = (uint32_t)at;
+        uint32_t* d_pmap = reinterpret_cast<uint32_t*>(ws + L.pmap);
+        if (hipMemcpyAsync(d_pmap, pm.data(), 4 * pm.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+            hipStreamSynchronize(b->stream) != hipSuccess) {
+            cbt_status st2 = cbth::fail(nullptr, CBT_E_DEVICE, "persistent work list upload failed");
+            cbt_batch_destroy(b);
+            return st2;
+        }
+        X.W.map = d_pmap;
+        X.W.ticket = reinterpret_cast<uint32_t*>(ws + L.ticket);
+        X.W.done = reinterpret_cast<uint32_t*>(ws + L.done);
+        const uint32_t resident = cbtk::persist_resident_groups(X.f64);
+        X.persistent = true;
+        X.persist_groups = resident == 0 ? 256u : (resident < at ? resident : (uint32_t)at);
+    }
     *out = b;
     return CBT_OK;
 }

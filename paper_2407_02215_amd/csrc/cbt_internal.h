@@ -45,6 +45,7 @@ enum : uint32_t {
     kErrAlloc = 4u,      // allocation beyond the free blocks
     kErrDecision = 8u,   // injected decision code > 2
     kErrEdge = 16u,      // edge pieces do not match across a shared edge
+    kErrSpin = 32u,      // a persistent frame's wait for an earlier phase gave up
 };
 
 enum StatIndex {
@@ -161,6 +162,24 @@ struct Batch {
     const uint32_t* map_list;
 };
 
+// Phases of one frame, in pipeline order (the persistent batched frame
+// numbers its work items phase by phase).
+enum Phase { kPhEnum = 0, kPhClass, kPhVote, kPhBudget, kPhWalk, kPhOwners, kPhFree, kPhFill, kPhResolve, kPhRedSub,
+             kPhRedTop, kPhCount };
+
+// Work list of a persistent batched frame: items [first[p], first[p+1])
+// are phase p's items of every instance, instance by instance; an item is a
+// span of consecutive workgroups of the instance's grid for the phase
+// (persist_items_host); ticket hands the items out, done[i * kPhCount + p]
+// counts instance i's finished items of phase p.  Both are cleared before
+// each launch.
+struct Persist {
+    uint32_t* ticket;
+    uint32_t* done;
+    const uint32_t* map;   // per item: instance << kMapShift | span index
+    uint32_t first[kPhCount + 1];
+};
+
 // Everything a launch sequence needs: either one instance passed by value
 // (batched = false) or a batch in device memory, and the grid sizes.
 struct Launch {
@@ -170,6 +189,9 @@ struct Launch {
     Batch B;
     uint32_t n_inst;
     uint32_t grid_rank, grid_word, grid_red, grid_list;
+    bool persistent;           // batched: one persistent launch per frame
+    Persist W;
+    uint32_t persist_groups;   // workgroups of that launch
 };
 
 // Tree level of the bitfield words: D - 5 (32 blocks per word), and 0 for a
@@ -202,6 +224,13 @@ struct StageEvents {
 };
 
 hipError_t launch_frame(const Launch& X, hipStream_t s, const StageEvents* ev);
+// workgroups of the persistent frame kernel that fit on the device at once (0
+// on error)
+uint32_t persist_resident_groups(bool f64);
+// workgroups of instance P's grid in phase ph, and the persistent frame's
+// items for them
+uint32_t phase_groups_host(const Pool& P, int ph);
+uint32_t persist_items_host(uint32_t groups);
 hipError_t launch_reduce(const Launch& X, hipStream_t s);
 hipError_t launch_enumerate(const Launch& X, hipStream_t s);
 // rebuild the vertex cache of every live block: world positions (with the

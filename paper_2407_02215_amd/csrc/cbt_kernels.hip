@@ -449,13 +449,17 @@ __device__ uint32_t ones_before_word(const Pool& P, uint32_t w, uint32_t* sh_out
 // list is written coalesced.
 // ---------------------------------------------------------------------------
 
-template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
+struct Lds_enumerate {
+    uint32_t sh[8];
+    uint32_t stage[kBlock * 32];
+    uint32_t sb;
+};
+
+__device__ __forceinline__ void run_enumerate(const Pool& P, uint32_t blk, Lds_enumerate& S_)
 {
-    __shared__ uint32_t sh[8];
-    __shared__ uint32_t stage[kBlock * 32];
-    Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_word, P);
+    auto& sh = S_.sh;
+    auto& stage = S_.stage;
+    auto& sb = S_.sb;
     if (blk == 0) {
         // frame set-up (kernel 1): L = the CBT root, F = 2^D - L, counters
         // cleared; no other workgroup reads the counters
@@ -478,7 +482,6 @@ __global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
         const uint32_t w = w0 + j * kBlock + threadIdx.x;
         words[j] = (w < P.W) ? (P.bits[w] & valid) : 0u;
     }
-    __shared__ uint32_t sb;
     uint32_t base = ones_before_word(P, w0, &sb);
 #pragma unroll
     for (int j = 0; j < kSteps; ++j) {
@@ -498,6 +501,15 @@ __global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
         __syncthreads();
         base += tot;
     }
+}
+
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_enumerate(Batch B, Inst one)
+{
+    __shared__ Lds_enumerate S_;
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_word, P);
+    run_enumerate(P, blk, S_);
 }
 
 // ---------------------------------------------------------------------------
@@ -788,17 +800,18 @@ __device__ __forceinline__ void store_output(const Pool& P, uint32_t q, Vec3<R> 
 // counts per row (the vote's result does not depend on the order within the
 // list; rank order keeps neighbouring threads of the vote on neighbouring
 // blocks).
-template <bool kB, typename R>
-__global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
+struct Lds_classify {
+    uint32_t sh[8];
+    uint32_t wcnt[2][kClassRows][kBlock / 64];
+};
+
+template <typename R>
+__device__ __forceinline__ void run_classify(const Pool& P, const LodK& K, const uint8_t* inj, uint32_t blk, Lds_classify& S_)
 {
-    __shared__ uint32_t sh[8];
-    __shared__ uint32_t wcnt[2][kClassRows][kBlock / 64];
-    Pool P;
-    LodK K;
-    const uint8_t* inj;
+    auto& sh = S_.sh;
+    auto& wcnt = S_.wcnt;
     // each workgroup classifies kClassChunks consecutive rank chunks (the
     // grid of the list passes), each chunk with its own partial and list
-    const uint32_t blk = pick_k<kB>(B, one, B.map_list, P, K, inj);
     const int maxd = 63 - P.k;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t nsplit = 0, nmerge = 0, ncand = 0, tile = 0;
@@ -906,6 +919,17 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
     }
 }
 
+template <bool kB, typename R>
+__global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
+{
+    __shared__ Lds_classify S_;
+    Pool P;
+    LodK K;
+    const uint8_t* inj;
+    const uint32_t blk = pick_k<kB>(B, one, B.map_list, P, K, inj);
+    run_classify<R>(P, K, inj, blk, S_);
+}
+
 // ---------------------------------------------------------------------------
 // kernel: merge configurations (list of even MERGE members)
 // ---------------------------------------------------------------------------
@@ -955,20 +979,25 @@ __device__ __forceinline__ int merge_vote_even(const Pool& P, uint32_t s, int d,
 // A unanimous configuration's reservation, one block per parent, is charged
 // to the smallest member (added to the partial of the rank workgroup that
 // holds it).
-template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
+// rank workgroups whose merge reservations a vote workgroup sums in LDS
+constexpr uint32_t kVoteAcc = 8;
+
+struct Lds_vote {
+    uint32_t sh[8];
+    uint32_t base[kMaxRankGroups + 1];
+    uint32_t acc[kVoteAcc];
+};
+
+__device__ __forceinline__ void run_vote(const Pool& P, uint32_t blk, Lds_vote& S_)
 {
-    __shared__ uint32_t sh[8];
-    __shared__ uint32_t base[kMaxRankGroups + 1];
-    Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
+    auto& sh = S_.sh;
+    auto& base = S_.base;
+    auto& acc = S_.acc;
     const ListShare ls = list_share(P, blk, base, sh);
     // reservations per rank workgroup: the workgroup's entries come from a
     // few consecutive rank workgroups [w0, w0 + kVoteAcc), summed in LDS and
     // added with one atomic each (many threads adding into the same partial
     // serialise); entries of later ones (tiny chunks) go straight to memory
-    constexpr uint32_t kVoteAcc = 8;
-    __shared__ uint32_t acc[kVoteAcc];
     const uint32_t w0 = share_start(base, P.G, ls);
     uint32_t wh = w0;
     if (threadIdx.x < kVoteAcc) acc[threadIdx.x] = 0;
@@ -993,6 +1022,15 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
     if (threadIdx.x == 0) stat_add(P, blk, kStMergeCfg, u);
 }
 
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
+{
+    __shared__ Lds_vote S_;
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
+    run_vote(P, blk, S_);
+}
+
 // ---------------------------------------------------------------------------
 // kernel: reservation cut
 // ---------------------------------------------------------------------------
@@ -1001,13 +1039,15 @@ __global__ void __launch_bounds__(kBlock) k_vote(Batch B, Inst one)
 // inclusive merge prefix fits in F; the split reservation (3d + 4) when all
 // merge reservations plus the inclusive split prefix fit in F.  Accepted
 // initiators are listed for the chain walk.
-template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
+struct Lds_budget {
+    uint2 sh2[8];
+    uint32_t sh[8];
+};
+
+__device__ __forceinline__ void run_budget(const Pool& P, uint32_t blk, Lds_budget& S_)
 {
-    __shared__ uint2 sh2[8];
-    __shared__ uint32_t sh[8];
-    Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    auto& sh2 = S_.sh2;
+    auto& sh = S_.sh;
     uint32_t r0, r1;
     rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     // reservations (merge, split) of the rank workgroups before this one,
@@ -1070,6 +1110,15 @@ __global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
     }
 }
 
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_budget(Batch B, Inst one)
+{
+    __shared__ Lds_budget S_;
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    run_budget(P, blk, S_);
+}
+
 // ---------------------------------------------------------------------------
 // kernel: compatibility chains (list of accepted initiators)
 // ---------------------------------------------------------------------------
@@ -1104,18 +1153,29 @@ __device__ void walk_chain(const Pool& P, uint32_t s)
     raise_err(P, kErrChain);
 }
 
-template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_walk(Batch B, Inst one)
+struct Lds_walk {
+    uint32_t sh[8];
+    uint32_t base[kMaxRankGroups + 1];
+};
+
+__device__ __forceinline__ void run_walk(const Pool& P, uint32_t blk, Lds_walk& S_)
 {
-    __shared__ uint32_t sh[8];
-    __shared__ uint32_t base[kMaxRankGroups + 1];
-    Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);   // G workgroups share the list
+    auto& sh = S_.sh;
+    auto& base = S_.base;
     const ListShare ls = list_share(P, blk, base, sh, nullptr, P.G);
     uint32_t wh = share_start(base, P.G, ls);
     for (uint32_t i = ls.i0 + threadIdx.x; i < ls.i1; i += kBlock) {
         walk_chain(P, P.list[list_at_from(base, ls.chunk, i, &wh)].x);
     }
+}
+
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_walk(Batch B, Inst one)
+{
+    __shared__ Lds_walk S_;
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);   // G workgroups share the list
+    run_walk(P, blk, S_);
 }
 
 // ---------------------------------------------------------------------------
@@ -1140,13 +1200,15 @@ __device__ __forceinline__ uint32_t merge_vetoed(const Pool& P, uint4 m)
     return ((a | b | c) & kMarks) ? 1u : 0u;
 }
 
-template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
+struct Lds_owners {
+    uint32_t sh[8];
+    uint2 sh2[8];
+};
+
+__device__ __forceinline__ void run_owners(const Pool& P, uint32_t blk, Lds_owners& S_)
 {
-    __shared__ uint32_t sh[8];
-    __shared__ uint2 sh2[8];
-    Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    auto& sh = S_.sh;
+    auto& sh2 = S_.sh2;
     uint32_t r0, r1;
     rank_range(P.ctr->L, P.G, blk, &r0, &r1);
     uint32_t nexec = 0, nsc = 0, nfree = 0;
@@ -1250,18 +1312,31 @@ __global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
     }
 }
 
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_owners(Batch B, Inst one)
+{
+    __shared__ Lds_owners S_;
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
+    run_owners(P, blk, S_);
+}
+
 // ---------------------------------------------------------------------------
 // kernel: the first N free blocks (ZeroToBitID(0..N-1) of the pre-frame
 // tree, Alg. 8), marked occupied; staged in LDS for coalesced writes
 // ---------------------------------------------------------------------------
 
-template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
+struct Lds_freelist {
+    uint32_t sh[8];
+    uint32_t stage[kBlock * 32];
+    uint32_t sb;
+};
+
+__device__ __forceinline__ void run_freelist(const Pool& P, uint32_t blk, Lds_freelist& S_)
 {
-    __shared__ uint32_t sh[8];
-    __shared__ uint32_t stage[kBlock * 32];
-    Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_word, P);
+    auto& sh = S_.sh;
+    auto& stage = S_.stage;
+    auto& sb = S_.sb;
     // N = the outputs of every owner (the sum of the owners' partials)
     uint32_t n = 0;
     for (uint32_t g = threadIdx.x; g < P.G; g += kBlock) n += P.part[g].x;
@@ -1272,7 +1347,6 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
     }
     const uint32_t w0 = blk * kWordsPerBlock;
     if (w0 >= P.W || N == 0) return;
-    __shared__ uint32_t sb;
     uint32_t zb = 32u * w0 - ones_before_word(P, w0, &sb);
     if (zb >= N) return;
     const uint32_t valid = word_valid(P);
@@ -1299,6 +1373,15 @@ __global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
         zb += tot;
         if (zb >= N) break;
     }
+}
+
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_freelist(Batch B, Inst one)
+{
+    __shared__ Lds_freelist S_;
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_word, P);
+    run_freelist(P, blk, S_);
 }
 
 // ---------------------------------------------------------------------------
@@ -1485,22 +1568,25 @@ __device__ __forceinline__ uint3 owner_item(const Pool& P, const uint32_t* base,
     return make_uint3(e.x, e.y, obase[*wh] + P.lpre[at]);
 }
 
-template <bool kB, typename R>
-__global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
+struct Lds_fill {
+    uint32_t sh[8];
+    uint32_t base[kMaxRankGroups + 1];
+    uint32_t obase[kMaxRankGroups + 1];
+    OwnerStage st;
+};
+
+template <typename R>
+__device__ __forceinline__ void run_fill(const Pool& P, const LodK& K, const uint8_t* inj, uint32_t blk, Lds_fill& S_)
 {
-    __shared__ uint32_t sh[8];
-    __shared__ uint32_t base[kMaxRankGroups + 1];
-    Pool P;
-    LodK K;
-    const uint8_t* inj;
-    const uint32_t blk = pick_k<kB>(B, one, B.map_list, P, K, inj);
+    auto& sh = S_.sh;
+    auto& base = S_.base;
+    auto& obase = S_.obase;
+    auto& st = S_.st;
     (void)inj;
-    __shared__ uint32_t obase[kMaxRankGroups + 1];
     const ListShare ls = list_share(P, blk, base, sh, obase);
     // outputs past the free blocks (an over-committed frame, flagged by the
     // free-list pass) are refused, so free-list reads stay below F
     const uint32_t N = min(obase[P.G], P.ctr->F);
-    __shared__ OwnerStage st;
     uint32_t wh = share_start(base, P.G, ls);
     for (uint32_t i0 = ls.i0; i0 < ls.i1; i0 += kBlock) {   // uniform trip count
         const uint32_t i = i0 + threadIdx.x;
@@ -1510,6 +1596,17 @@ __global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
         if (it.y & kMarks) fill_split<R>(P, K, it.x, it.y, it.z, N);
         else fill_merge<R>(P, it.x, it.y, it.z, N);
     }
+}
+
+template <bool kB, typename R>
+__global__ void __launch_bounds__(kBlock) k_fill(Batch B, Inst one)
+{
+    __shared__ Lds_fill S_;
+    Pool P;
+    LodK K;
+    const uint8_t* inj;
+    const uint32_t blk = pick_k<kB>(B, one, B.map_list, P, K, inj);
+    run_fill<R>(P, K, inj, blk, S_);
 }
 
 // ---------------------------------------------------------------------------
@@ -1713,19 +1810,23 @@ __device__ __forceinline__ void resolve_merge(const Pool& P, int32_t b, uint32_t
     add_clear(P, cl, 0, f.y);
 }
 
-template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
+struct Lds_resolve {
+    uint32_t sh[8];
+    uint32_t base[kMaxRankGroups + 1];
+    uint32_t obase[kMaxRankGroups + 1];
+    OwnerStage st;
+};
+
+__device__ __forceinline__ void run_resolve(const Pool& P, uint32_t blk, Lds_resolve& S_)
 {
-    __shared__ uint32_t sh[8];
-    __shared__ uint32_t base[kMaxRankGroups + 1];
-    Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
-    __shared__ uint32_t obase[kMaxRankGroups + 1];
+    auto& sh = S_.sh;
+    auto& base = S_.base;
+    auto& obase = S_.obase;
+    auto& st = S_.st;
     const ListShare ls = list_share(P, blk, base, sh, obase);
     // outputs past the free blocks (an over-committed frame, flagged by the
     // free-list pass) are refused, so free-list reads stay below F
     const uint32_t N = min(obase[P.G], P.ctr->F);
-    __shared__ OwnerStage st;
     uint32_t wh = share_start(base, P.G, ls);
     // uniform trip count: items are regrouped across the workgroup and the
     // bit clears merged across the wave
@@ -1744,6 +1845,15 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
     }
 }
 
+template <bool kB>
+__global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
+{
+    __shared__ Lds_resolve S_;
+    Pool P;
+    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
+    run_resolve(P, blk, S_);
+}
+
 // ---------------------------------------------------------------------------
 // kernels: sum-reduction tree (down to the word level; the levels below a
 // word are popcounts of the bitfield and are never stored)
@@ -1755,12 +1865,13 @@ __device__ __forceinline__ int sub_levels(const Pool& P)
     return LW < P.sub ? LW : P.sub;
 }
 
-template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_reduce_sub(Batch B, Inst one)
+struct Lds_reduce_sub {
+    uint32_t buf[2][1 << kMaxReduceSub];
+};
+
+__device__ __forceinline__ void run_reduce_sub(const Pool& P, uint32_t blk, Lds_reduce_sub& S_)
 {
-    __shared__ uint32_t buf[2][1 << kMaxReduceSub];
-    Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_red, P);
+    auto& buf = S_.buf;
     const int LW = word_level(P.D);
     const int SUB = sub_levels(P);
     const uint32_t wpb = 1u << SUB;
@@ -1785,12 +1896,18 @@ __global__ void __launch_bounds__(kBlock) k_reduce_sub(Batch B, Inst one)
     }
 }
 
-// the levels above the workgroup subtrees (one workgroup per instance)
 template <bool kB>
-__global__ void __launch_bounds__(1024) k_reduce_top(Batch B, Inst one)
+__global__ void __launch_bounds__(kBlock) k_reduce_sub(Batch B, Inst one)
 {
+    __shared__ Lds_reduce_sub S_;
     Pool P;
-    pick_inst<kB>(B, one, P);
+    const uint32_t blk = pick<kB>(B, one, B.map_red, P);
+    run_reduce_sub(P, blk, S_);
+}
+
+// the levels above the workgroup subtrees (one workgroup per instance)
+__device__ __forceinline__ void run_reduce_top(const Pool& P)
+{
     const int top = word_level(P.D) - sub_levels(P);   // levels [0, top) remain
     for (int lvl = top - 1; lvl >= 0; --lvl) {
         const uint32_t n = 1u << lvl;
@@ -1816,19 +1933,225 @@ __global__ void __launch_bounds__(1024) k_reduce_top(Batch B, Inst one)
     }
 }
 
+template <bool kB>
+__global__ void __launch_bounds__(1024) k_reduce_top(Batch B, Inst one)
+{
+    Pool P;
+    pick_inst<kB>(B, one, P);
+    run_reduce_top(P);
+}
+
+// ---------------------------------------------------------------------------
+// persistent batched frame: the whole pipeline of every member instance in
+// one launch.  The work items (phase, instance, workgroup of that
+// instance's grid for the phase) are numbered phase by phase; resident
+// workgroups take them in increasing order from one ticket counter.  An
+// item of phase p waits until every item of phase p - 1 of its own
+// instance has finished (a per-instance counter per phase), so instances
+// move through the pipeline at their own pace: a small instance's later
+// phases run while a large one is still in an early phase, and no phase
+// ends in a device-wide drain.  An item depends only on items with smaller
+// numbers, which were handed to workgroups already running, so the waits
+// always end; each is also bounded (kSpinLimit polls), after which the
+// item is skipped and the instance's error flag raised.
+// ---------------------------------------------------------------------------
+
+// workgroups of instance P's grid in phase ph
+__device__ __forceinline__ uint32_t phase_groups(const Pool& P, int ph)
+{
+    switch (ph) {
+    case kPhEnum:
+    case kPhFree: return (P.W + kWordsPerBlock - 1) / kWordsPerBlock;
+    case kPhClass:
+    case kPhVote:
+    case kPhFill:
+    case kPhResolve: return list_groups(P);
+    case kPhBudget:
+    case kPhWalk:
+    case kPhOwners: return P.G;
+    case kPhRedSub: return P.W >> sub_levels(P);
+    default: return 1u;
+    }
+}
+
+// work items of one instance's phase, at most
+constexpr uint32_t kPersistItems = 64;
+
+// Each item of the persistent frame runs a span of consecutive workgroups
+// of its instance's grid for the phase, so that a phase of an instance is
+// at most kPersistItems items: the synchronisation a work item pays (one
+// L2 write-back on its die, one counter update) is paid per span.
+__device__ __forceinline__ uint32_t persist_span(uint32_t groups)
+{
+    return (groups + kPersistItems - 1) / kPersistItems;
+}
+
+__device__ __forceinline__ uint32_t persist_items(uint32_t groups)
+{
+    const uint32_t sp = persist_span(groups);
+    return (groups + sp - 1) / sp;
+}
+
+union LdsAny {
+    Lds_enumerate e;
+    Lds_classify c;
+    Lds_vote v;
+    Lds_budget b;
+    Lds_walk w;
+    Lds_owners o;
+    Lds_freelist f;
+    Lds_fill fl;
+    Lds_resolve r;
+    Lds_reduce_sub rs;
+};
+
+// polls of one wait (a few microseconds each): about two seconds, far
+// beyond any phase of a depth-30 instance
+constexpr uint32_t kSpinLimit = 1u << 20;
+// consecutive work items a workgroup takes per ticket
+constexpr uint32_t kPersistChunk = 4;
+
+// The loop state lives in LDS (the launch arguments are copied there once
+// and each item's decode is kept there), so nothing but the LDS base stays
+// in registers across a phase body: the bodies get the registers they have
+// as separate kernels.
+//
+// Synchronisation costs are what decide this kernel on a GPU of several
+// dies: an agent-scope acquire invalidates the die's L2 and an agent-scope
+// release writes it back.  So the waits poll with plain coherent loads and
+// acquire once, a finished item releases once (every wave first waits for
+// its own stores, then one thread writes the L2 back and counts the item),
+// and a workgroup takes kPersistChunk consecutive items per ticket.
+struct PersistState {
+    Batch B;
+    Persist W;
+    uint32_t item, end, inst, blk, ph, go;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
+k_persist(Batch B, Persist W)
+{
+    __shared__ LdsAny S_;
+    __shared__ PersistState Z;
+    if (threadIdx.x == 0) {
+        Z.B = B;
+        Z.W = W;
+        Z.item = 0;
+        Z.end = 0;
+    }
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t item = Z.item + 1;
+            if (item >= Z.end) {
+                item = atomicAdd(Z.W.ticket, kPersistChunk);
+                Z.end = item + kPersistChunk;
+            }
+            Z.item = item;
+            if (item < Z.W.first[kPhCount]) {
+                int ph = 0;
+                uint32_t f = 0;   // first[0] = 0
+                for (int q = 1; q < kPhCount; ++q) {
+                    if (item >= Z.W.first[q]) {
+                        ph = q;
+                        f = Z.W.first[q];
+                    }
+                }
+                (void)f;
+                const uint32_t e = Z.W.map[item];
+                const uint32_t in = e >> kMapShift;
+                Z.inst = in;
+                Z.blk = e & ((1u << kMapShift) - 1u);   // the span's index
+                Z.ph = (uint32_t)ph;
+                uint32_t go = 1;
+                if (ph > 0) {
+                    // the previous phase of this instance has finished
+                    const Pool& Pq = Z.B.inst[in].P;
+                    const uint32_t want = persist_items(phase_groups(Pq, ph - 1));
+                    const uint32_t* dp = Z.W.done + (size_t)in * kPhCount + (ph - 1);
+                    uint32_t n = 0;
+                    while (__hip_atomic_load(dp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                        // give up after kSpinLimit polls, or at once when an
+                        // earlier wait of this instance gave up
+                        if (++n >= kSpinLimit ||
+                            (__hip_atomic_load(&Pq.ctr->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrSpin)) {
+                            raise_err(Pq, kErrSpin);
+                            go = 0;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    // one acquire for the whole wait: the die's caches
+                    // are invalidated once the earlier phase is complete
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+                Z.go = go;
+            }
+        }
+        __syncthreads();
+        // uniform values: the bodies see their instance through scalar loads
+        const uint32_t item = __builtin_amdgcn_readfirstlane(Z.item);
+        if (item >= Z.W.first[kPhCount]) break;
+        if (__builtin_amdgcn_readfirstlane(Z.go)) {
+            const Inst* I = B.inst + __builtin_amdgcn_readfirstlane(Z.inst);
+            const uint32_t ph = __builtin_amdgcn_readfirstlane(Z.ph);
+            const uint32_t groups = phase_groups(I->P, (int)ph);
+            const uint32_t sp = persist_span(groups);
+            const uint32_t b0 = __builtin_amdgcn_readfirstlane(Z.blk) * sp;
+            const uint32_t b1 = b0 + sp < groups ? b0 + sp : groups;
+            for (uint32_t blk = b0; blk < b1; ++blk) {
+            if (blk > b0) __syncthreads();   // the previous body's LDS reads are done
+            // each body loads its instance through its own opaque copy of
+            // the pointer, so no load is shared between bodies and hoisted
+            // above the switch (which would keep it live through every body)
+#define CBT_OPAQUE(J) const Inst* J = I; asm volatile("" : "+s"(J))
+            switch (ph) {
+            case kPhEnum: { CBT_OPAQUE(J); run_enumerate(J->P, blk, S_.e); } break;
+            case kPhClass: { CBT_OPAQUE(J); run_classify<R>(J->P, J->K, J->inj, blk, S_.c); } break;
+            case kPhVote: { CBT_OPAQUE(J); run_vote(J->P, blk, S_.v); } break;
+            case kPhBudget: { CBT_OPAQUE(J); run_budget(J->P, blk, S_.b); } break;
+            case kPhWalk: { CBT_OPAQUE(J); run_walk(J->P, blk, S_.w); } break;
+            case kPhOwners: { CBT_OPAQUE(J); run_owners(J->P, blk, S_.o); } break;
+            case kPhFree: { CBT_OPAQUE(J); run_freelist(J->P, blk, S_.f); } break;
+            case kPhFill: { CBT_OPAQUE(J); run_fill<R>(J->P, J->K, J->inj, blk, S_.fl); } break;
+            case kPhResolve: { CBT_OPAQUE(J); run_resolve(J->P, blk, S_.r); } break;
+            case kPhRedSub: { CBT_OPAQUE(J); run_reduce_sub(J->P, blk, S_.rs); } break;
+            default: { CBT_OPAQUE(J); run_reduce_top(J->P); } break;
+            }
+#undef CBT_OPAQUE
+            }
+        }
+        // every wave's memory operations complete (its stores in the L2)
+        // before the barrier; then one release writes the L2 back and the
+        // item is counted
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(Z.W.done + (size_t)Z.inst * kPhCount + Z.ph, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ticket and phase counters of a persistent frame -> zero
+__global__ void k_persist_clear(Persist W, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *W.ticket = 0;
+    if (i < n) W.done[i] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // kernels: vertex-cache refresh, queries, snapshot and restore
 // ---------------------------------------------------------------------------
 
 // Rebuild the cache of every live block: world positions of the Alg. 2
 // decode of its heap ID.
-template <bool kB, typename R>
-__global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
+template <typename R>
+__device__ __forceinline__ void run_refresh(const Pool& P, const LodK& K, const uint8_t* inj, uint32_t blk)
 {
-    Pool P;
-    LodK K;
-    const uint8_t* inj;
-    const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
     (void)inj;
     const uint32_t L = P.ctr->L;
     for (uint32_t r = blk * kBlock + threadIdx.x; r < L; r += P.G * kBlock) {
@@ -1844,6 +2167,16 @@ __global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
         }
         store_world<R>(P, s, world<R>(K, a), world<R>(K, b), world<R>(K, c), d, id);
     }
+}
+
+template <bool kB, typename R>
+__global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
+{
+    Pool P;
+    LodK K;
+    const uint8_t* inj;
+    const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
+    run_refresh<R>(P, K, inj, blk);
 }
 
 // Clears a pool before it is filled: heap IDs, pointer and forwarding
@@ -2079,6 +2412,29 @@ int reduce_levels(const Pool& P)
 
 uint32_t reduce_groups(const Pool& P) { return P.W >> reduce_levels(P); }
 
+uint32_t phase_groups_host(const Pool& P, int ph)
+{
+    switch (ph) {
+    case kPhEnum:
+    case kPhFree: return word_groups(P);
+    case kPhClass:
+    case kPhVote:
+    case kPhFill:
+    case kPhResolve: return list_groups(P);
+    case kPhBudget:
+    case kPhWalk:
+    case kPhOwners: return P.G;
+    case kPhRedSub: return reduce_groups(P);
+    default: return 1u;
+    }
+}
+
+uint32_t persist_items_host(uint32_t groups)
+{
+    const uint32_t sp = (groups + kPersistItems - 1) / kPersistItems;
+    return (groups + sp - 1) / sp;
+}
+
 size_t workspace_layout(int32_t H, int32_t D, int32_t f64, Pool* P, char* base)
 {
     const uint64_t cap = 1ull << D;
@@ -2198,8 +2554,29 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     return e;
 }
 
+template <typename R>
+static hipError_t persist_seq(const Launch& X, hipStream_t s)
+{
+    const uint32_t n = X.n_inst * (uint32_t)kPhCount;
+    hipLaunchKernelGGL(k_persist_clear, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, X.W, n);
+    hipLaunchKernelGGL(k_persist<R>, dim3(X.persist_groups), dim3(kBlock), 0, s, X.B, X.W);
+    return hipGetLastError();
+}
+
+uint32_t persist_resident_groups(bool f64)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const hipError_t e = f64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persist<double>, kBlock, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persist<float>, kBlock, 0);
+    if (e != hipSuccess || per < 1 || cus < 1) return 0;
+    return (uint32_t)cus * (uint32_t)per;
+}
+
 hipError_t launch_frame(const Launch& X, hipStream_t s, const StageEvents* ev)
 {
+    if (X.batched && X.persistent) return X.f64 ? persist_seq<double>(X, s) : persist_seq<float>(X, s);
     if (X.f64) return X.batched ? frame_seq<true, double>(X, s, ev) : frame_seq<false, double>(X, s, ev);
     return X.batched ? frame_seq<true, float>(X, s, ev) : frame_seq<false, float>(X, s, ev);
 }

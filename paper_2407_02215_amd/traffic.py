@@ -19,6 +19,11 @@ while all of them match.
 
     python -m paper_2407_02215_amd.traffic --fetch F.csv --write W.csv [--valu V.csv] \\
         --copy-fetch CF.csv --copy-write CW.csv --bench-log F.log
+
+A kernel trace of the same command (``rocprofv3 --kernel-trace``) gives the
+timed pass's launch durations per stage:
+
+    python -m paper_2407_02215_amd.traffic trace --trace T_kernel_trace.csv --steps K
 """
 from __future__ import annotations
 
@@ -27,6 +32,7 @@ import csv
 import hashlib
 import json
 import os
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "traffic.json")
@@ -170,7 +176,39 @@ def lookup(workload, criterion, precision, preroll, warmup, steps, schedule):
     return None
 
 
+def trace_window(path: str, steps: int) -> dict:
+    """From a rocprofv3 kernel trace of the benchmark: per stage, the mean
+    duration (microseconds) of its launches in the timed pass (between the
+    two marker kernels) and their number per frame."""
+    rows = []
+    for r in csv.DictReader(open(path)):
+        rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    marks = sorted(d for d, name, _ in rows if MARKER in name)
+    if len(marks) < 2:
+        raise SystemExit(f"expected two marker dispatches, found {len(marks)}")
+    lo, hi = marks[0], marks[1]
+    acc = {}
+    for d, name, ns in rows:
+        if not lo < d < hi:
+            continue
+        st = stage_of(name)
+        if st is None:
+            raise SystemExit(f"unexpected kernel in the timed window: {name}")
+        n, t = acc.get(st, (0, 0))
+        acc[st] = (n + 1, t + ns)
+    return {st: {"launches_per_frame": n / steps, "mean_us": t / n / 1e3, "us_per_frame": t / steps / 1e3}
+            for st, (n, t) in sorted(acc.items())}
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "trace":
+        tp = argparse.ArgumentParser(description="timed-window kernel durations from a kernel trace")
+        tp.add_argument("cmd")
+        tp.add_argument("--trace", required=True)
+        tp.add_argument("--steps", type=int, required=True)
+        t = tp.parse_args()
+        print(json.dumps(trace_window(t.trace, t.steps), indent=1))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)

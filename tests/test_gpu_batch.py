@@ -1,7 +1,7 @@
 """Batched update (cbt_batch_*): many instances of uneven mesh size and
-depth advanced by shared launches, eagerly or from a captured HIP graph,
-must give every member exactly the state it gets alone (and the CPU
-reference's state)."""
+depth advanced by shared launches (one per stage, or one persistent launch
+per frame), eagerly or from a captured HIP graph, must give every member
+exactly the state it gets alone (and the CPU reference's state)."""
 import numpy as np
 import pytest
 import torch  # noqa: F401
@@ -23,21 +23,23 @@ def _same_pool(a, b, label):
     assert np.array_equal(ta, tb), f"{label}: trees differ"
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batched_matches_single_instances(graph):
+@pytest.mark.parametrize("graph,persistent", [(True, False), (False, False), (True, True), (False, True)])
+def test_batched_matches_single_instances(graph, persistent):
     ws = I.batched_workloads(10, frames=14, seed=5, h_range=(24, 4000), d_range=(12, 16), table_res=64)
-    log(f"[batch graph={graph}] H={[w.mesh.H for w in ws]} D={[w.depth for w in ws]}")
+    log(f"[batch graph={graph} persistent={persistent}] H={[w.mesh.H for w in ws]} D={[w.depth for w in ws]}")
     alone = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
     members = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
     # uneven schedules inside one batch: the smallest grid, and the default
     for i, m in enumerate(members):
         if i % 3 == 0:
             m.set_schedule(16, 5)
-    batch = cbt.Batch(members, graph=graph)
+    batch = cbt.Batch(members, graph=graph, persistent=persistent)
     for f in range(len(ws[0].cameras)):
         for a, w in zip(alone, ws):
             a.update(w.cameras[f])
-        batch.update([w.cameras[f] for w in ws])
+        st = batch.update([w.cameras[f] for w in ws], stats=(f % 4 == 3))
+        if st:
+            assert all(s["live_after"] > 0 for s in st)
     batch.synchronize()
     torch.cuda.synchronize()
     grew = 0
@@ -50,11 +52,13 @@ def test_batched_matches_single_instances(graph):
         x.close()
 
 
-def test_batched_members_match_reference():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_members_match_reference(persistent):
     ws = I.batched_workloads(4, frames=10, seed=9, h_range=(24, 600), d_range=(12, 14), table_res=64)
     members = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
     orcs = [Oracle(w.mesh, w.depth, w.lod) for w in ws]
-    batch = cbt.Batch(members, graph=True)
+    log(f"[batch reference persistent={persistent}]")
+    batch = cbt.Batch(members, graph=True, persistent=persistent)
     for f in range(len(ws[0].cameras)):
         stats = batch.update([w.cameras[f] for w in ws], stats=True)
         for i, (o, w) in enumerate(zip(orcs, ws)):
@@ -68,12 +72,14 @@ def test_batched_members_match_reference():
     batch.close()
 
 
-def test_batched_injected_decisions_match_reference():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_injected_decisions_match_reference(persistent):
     meshes = [(I.mesh_cube(), 10), (I.mesh_icosahedron(), 12), (I.mesh_quad_sphere(3, 0.5, 11), 11),
-              (I.mesh_two_triangles(False), 8)]
+              (I.mesh_two_triangles(False), 8), (I.mesh_two_triangles(True), 3)]
     members = [cbt.Instance(m, D) for m, D in meshes]
     orcs = [Oracle(m, D) for m, D in meshes]
-    batch = cbt.Batch(members, graph=True)
+    log(f"[batch injected persistent={persistent}]")
+    batch = cbt.Batch(members, graph=True, persistent=persistent)
     rng = np.random.default_rng(21)
     for f in range(12):
         ps, pm = (0.5, 0.1) if f < 6 else (0.1, 0.6)
@@ -86,3 +92,33 @@ def test_batched_injected_decisions_match_reference():
         assert_same_state(m, o, f"member {i}")
         assert_same_tree(m, o, f"member {i}")
     batch.close()
+
+
+def test_persistent_spans_match_single_instances():
+    """Pools large enough that the persistent frame runs several workgroups
+    per work item (the depth-20 planet: 2048 rank workgroups, 128 bitfield
+    workgroups) beside small ones, against the same instances alone."""
+    planet = I.workload("planet", frames=24, table_res=128)
+    cube = I.workload("cube", frames=8)
+    ws = [planet, cube, planet]
+    alone = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
+    members = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
+    members[2].set_schedule(100, 7)
+    alone[2].set_schedule(100, 7)
+    log("[batch spans] planet D=20 x2, cube D=16")
+    batch = cbt.Batch(members, graph=True, persistent=True)
+    for f in range(20):
+        cams = [w.cameras[min(f, len(w.cameras) - 1)] for w in ws]
+        for a, c in zip(alone, cams):
+            a.update(c)
+        st = batch.update(cams, stats=(f % 5 == 4))
+        if st:
+            assert all(s["live_after"] > 0 for s in st)
+    batch.synchronize()
+    torch.cuda.synchronize()
+    for i, (a, m) in enumerate(zip(alone, members)):
+        _same_pool(a, m, f"member {i}")
+    assert alone[0].live_count() > 10_000
+    batch.close()
+    for x in alone + members:
+        x.close()

@@ -127,11 +127,13 @@ def test_fp64_deep_planet_descent(criterion):
     inst.close()
 
 
-def test_fp64_batch_matches_single_instances():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_fp64_batch_matches_single_instances(persistent):
     ws = I.batched_workloads(4, frames=10, seed=21, h_range=(24, 800), d_range=(12, 14), table_res=64)
     alone = [cbt.Instance(w.mesh, w.depth, w.lod, precision=64) for w in ws]
     members = [cbt.Instance(w.mesh, w.depth, w.lod, precision=64) for w in ws]
-    batch = cbt.Batch(members, graph=True)
+    log(f"[fp64 batch persistent={persistent}]")
+    batch = cbt.Batch(members, graph=True, persistent=persistent)
     for f in range(len(ws[0].cameras)):
         for a, w in zip(alone, ws):
             a.update(w.cameras[f])
