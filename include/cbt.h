@@ -220,6 +220,29 @@ cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_para
 cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisions,
                                      cbt_frame_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * frame as cbt_update, with the same result, but the frame's scratch arrays
+ * (rank list, free list, work lists, owner offsets, list lengths, partial
+ * sums, statistics lanes) are taken from a static device array of
+ * cbt_noalloc_scratch_bytes() bytes (about 20 MiB, one copy per GPU, held
+ * until the process ends) instead of the handle's workspace.  The handle's
+ * workspace still holds the state (IDs, pointer records, vertex cache,
+ * commands, bitfield, tree, counters).  Limits and errors: pools of depth
+ * D <= 20 only (CBT_E_CAPACITY beyond); the handle's device must be current
+ * (CBT_E_ARG otherwise).  Allocates nothing: no hipMalloc, hipFree or event
+ * creation; the static array's address is looked up once per device on the
+ * first call.  Every call on one GPU shares that GPU's array: calls whose
+ * work overlaps on the device (different streams, or different host threads
+ * without ordering) race and corrupt each other's frames; serialise them on
+ * one stream.  The array keeps the last call's contents; the accumulators
+ * that must start at zero are cleared on the stream by each call.  After
+ * it, cbt_query_decisions reports CBT_E_STATE (the rank list it needs is in
+ * the shared array).  Asynchronous unless stats is non-NULL, as cbt_update. */
+cbt_status cbt_update_noalloc(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod,
+                              cbt_frame_stats* stats);
+size_t cbt_noalloc_scratch_bytes(void);
+
 /* Multi-pass mode: the update repeated with the same camera until a pass
  * changes nothing (no allocation, no release) or max_passes passes ran, for
  * cold starts and camera cuts (the single pass per frame of Section 3.3

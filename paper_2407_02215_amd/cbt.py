@@ -25,7 +25,8 @@ EXPORTED = ["cbt_workspace_bytes", "cbt_init", "cbt_update", "cbt_update_with_de
             "cbt_destroy", "cbt_status_string", "cbt_last_error", "cbt_time_stage", "cbt_stage_time",
             "cbt_set_schedule", "cbt_get_schedule", "cbt_stage_times", "cbt_batch_workspace_bytes", "cbt_batch_create",
             "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
-            "cbt_export_triangles", "cbt_workspace_bytes_ex", "cbt_init_ex", "cbt_export_live", "cbt_import_live"]
+            "cbt_export_triangles", "cbt_workspace_bytes_ex", "cbt_init_ex", "cbt_export_live", "cbt_import_live",
+            "cbt_update_noalloc", "cbt_noalloc_scratch_bytes"]
 
 INIT_FP64 = 1
 
@@ -88,6 +89,9 @@ def load_library():
     lib.cbt_init_ex.argtypes = [C.POINTER(Mesh), C.c_int32, C.c_uint32, vp, C.c_size_t, vp, C.POINTER(vp)]
     lib.cbt_update.argtypes = [vp, C.POINTER(Camera), C.POINTER(LodParams), C.POINTER(FrameStats)]
     lib.cbt_update_with_decisions.argtypes = [vp, vp, C.POINTER(FrameStats)]
+    lib.cbt_update_noalloc.argtypes = [vp, C.POINTER(Camera), C.POINTER(LodParams), C.POINTER(FrameStats)]
+    lib.cbt_noalloc_scratch_bytes.argtypes = []
+    lib.cbt_noalloc_scratch_bytes.restype = C.c_size_t
     lib.cbt_query.argtypes = [vp, C.POINTER(Bisectors)]
     lib.cbt_query_decisions.argtypes = [vp, vp]
     lib.cbt_snapshot.argtypes = [vp, vp, vp, vp, vp]
@@ -119,7 +123,7 @@ def load_library():
               "cbt_snapshot", "cbt_restore", "cbt_frame_constants", "cbt_live_count", "cbt_destroy",
               "cbt_time_stage", "cbt_stage_time", "cbt_stage_times", "cbt_set_schedule", "cbt_get_schedule", "cbt_batch_create",
               "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
-              "cbt_export_triangles", "cbt_init_ex", "cbt_export_live", "cbt_import_live"):
+              "cbt_export_triangles", "cbt_init_ex", "cbt_export_live", "cbt_import_live", "cbt_update_noalloc"):
         getattr(lib, f).restype = C.c_int32
     _LIB = lib
     return lib
@@ -225,6 +229,17 @@ class Instance:
         cam = make_camera(camera)
         st = FrameStats() if stats else None
         self._check(self.lib.cbt_update(self.h, C.byref(cam), C.byref(self._lodp), C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def update_noalloc(self, camera, stats: bool = False):
+        """cbt_update_noalloc: the same frame with the scratch arrays in the
+        library's static device array (pools of depth 20 at most)."""
+        if self.lod is None:
+            raise CbtError(-1, "no LOD parameters")
+        cam = make_camera(camera)
+        st = FrameStats() if stats else None
+        self._check(self.lib.cbt_update_noalloc(self.h, C.byref(cam), C.byref(self._lodp),
+                                                C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def update_converge(self, camera, max_passes: int = 64):

@@ -336,6 +336,10 @@ static cbt_status init_impl(const cbt_mesh* mesh, int32_t D, uint32_t flags, voi
 
     cbt_instance* h = new (std::nothrow) cbt_instance();
     if (!h) return fail(nullptr, CBT_E_ARG, "out of host memory");
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(nullptr, CBT_E_DEVICE, "no current HIP device");
+    }
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     h->ws = reinterpret_cast<char*>(device_workspace);
     h->ws_bytes = workspace_bytes;
@@ -474,6 +478,95 @@ cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_para
     }
     HIP_TRY(h, cbtk::launch_frame(cbtk::single_launch(h->P, K, nullptr), h->stream, next_events(h)), "frame launch");
     return finish_frame(h, stats);
+}
+
+// ---------------------------------------------------------------------------
+// cbt_update_noalloc: the frame with its scratch arrays (rank list, free
+// list, work lists, owner offsets, list lengths, partial sums, statistics
+// lanes) in static device memory instead of the handle's workspace, so the
+// call allocates nothing.  One copy per GPU, kept until the process ends.
+// ---------------------------------------------------------------------------
+
+static constexpr int32_t kNoallocMaxD = 20;
+static constexpr size_t kNoallocBlocks = size_t(1) << kNoallocMaxD;
+static constexpr size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+static constexpr size_t kNoallocLive = 0;
+static constexpr size_t kNoallocFree = kNoallocLive + al256(4 * kNoallocBlocks);
+static constexpr size_t kNoallocList = kNoallocFree + al256(4 * kNoallocBlocks);
+static constexpr size_t kNoallocLpre = kNoallocList + al256(8 * kNoallocBlocks);
+static constexpr size_t kNoallocLcnt = kNoallocLpre + al256(4 * kNoallocBlocks);
+static constexpr size_t kNoallocPart = kNoallocLcnt + al256(4 * (size_t)cbtk::kMaxRankGroups);
+static constexpr size_t kNoallocLane = kNoallocPart + al256(sizeof(uint2) * cbtk::kMaxRankGroups);
+static constexpr size_t kNoallocBytes = kNoallocLane + al256(4 * (size_t)cbtk::kStLanes * cbtk::kLaneWords);
+
+// In host code this name is a stand-in, not a device address: kernels and
+// copies get the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+static constexpr int kNoallocDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kNoallocDevices];
+
+// the device address of this GPU's scratch array, looked up once per device
+// with that device current
+static hipError_t noalloc_scratch(int dev, char** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t cbt_noalloc_scratch_bytes(void) { return kNoallocBytes; }
+
+cbt_status cbt_update_noalloc(cbt_handle h, const cbt_camera* camera, const cbt_lod_params* lod,
+                              cbt_frame_stats* stats)
+{
+    if (!h) return fail(nullptr, CBT_E_ARG, "NULL handle");
+    if (h->failed) return fail(h, CBT_E_STATE, "handle failed earlier: %s", h->err);
+    if (h->P.D > kNoallocMaxD)
+        return fail(h, CBT_E_CAPACITY, "cbt_update_noalloc: depth %d exceeds its static scratch (depth <= %d, %zu bytes)",
+                    h->P.D, kNoallocMaxD, kNoallocBytes);
+    cbt_status st = cbth::check_lod(h, camera, lod);
+    if (st) return st;
+    int dev = -1;
+    HIP_TRY(h, hipGetDevice(&dev), "current device");
+    if (dev != h->device)
+        return fail(h, CBT_E_ARG, "cbt_update_noalloc: device %d is current, the handle's is %d", dev, h->device);
+    if (dev < 0 || dev >= kNoallocDevices)
+        return fail(h, CBT_E_ARG, "cbt_update_noalloc: device %d beyond the %d supported", dev, kNoallocDevices);
+    char* base = nullptr;
+    HIP_TRY(h, noalloc_scratch(dev, &base), "static scratch address");
+    Pool Q = h->P;
+    Q.live = reinterpret_cast<uint32_t*>(base + kNoallocLive);
+    Q.freel = reinterpret_cast<uint32_t*>(base + kNoallocFree);
+    Q.list = reinterpret_cast<uint2*>(base + kNoallocList);
+    Q.lpre = reinterpret_cast<uint32_t*>(base + kNoallocLpre);
+    Q.lcnt = reinterpret_cast<uint32_t*>(base + kNoallocLcnt);
+    Q.part = reinterpret_cast<uint2*>(base + kNoallocPart);
+    Q.slane = reinterpret_cast<uint32_t*>(base + kNoallocLane);
+    LodK K;
+    cbth::make_lodk(camera, lod, &K);
+    // the statistics lanes must start at zero; the last call on this GPU may
+    // have been another instance's, or may have stopped part way
+    HIP_TRY(h, cbtk::launch_clear_frame_scratch(Q, h->stream), "clear scratch");
+    if (cbth::world_changed(K, h->wk)) {
+        h->wk = K;
+        HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(Q, K, nullptr), h->stream), "vertex cache");
+    }
+    HIP_TRY(h, cbtk::launch_frame(cbtk::single_launch(Q, K, nullptr), h->stream, nullptr), "frame launch");
+    // the frame's rank list lives in the shared scratch, not in the handle
+    h->last_frame_valid = 0;
+    if (!stats) return CBT_OK;
+    st = read_counters(h);
+    if (st) return st;
+    return cbth::stats_from_counters(h, *h->hctr, stats);
 }
 
 cbt_status cbt_update_with_decisions(cbt_handle h, const uint8_t* device_decisions, cbt_frame_stats* stats)
@@ -678,9 +771,9 @@ cbt_status cbt_query_decisions(cbt_handle h, uint8_t* per_slot)
     const Pool& P = h->P;
     cbt_status st = read_counters(h);
     if (st) return st;
-    uint8_t* scratch = reinterpret_cast<uint8_t*>(P.freel);   // 4 * cap bytes, free between frames
-    HIP_TRY(h, cbtk::launch_gather_decisions(P, h->hctr->L, scratch, h->stream), "gather decisions");
-    HIP_TRY(h, hipMemcpyAsync(per_slot, scratch, P.cap, hipMemcpyDeviceToHost, h->stream), "copy decisions");
+    uint8_t* dec = reinterpret_cast<uint8_t*>(P.freel);   // 4 * cap bytes, free between frames
+    HIP_TRY(h, cbtk::launch_gather_decisions(P, h->hctr->L, dec, h->stream), "gather decisions");
+    HIP_TRY(h, hipMemcpyAsync(per_slot, dec, P.cap, hipMemcpyDeviceToHost, h->stream), "copy decisions");
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
     return CBT_OK;
 }

@@ -12,6 +12,7 @@ struct cbt_instance {
     hipStream_t stream;
     char* ws;
     size_t ws_bytes;
+    int device;             // HIP device current at initialisation
     int failed;
     int last_frame_valid;   // the live list still describes the last frame
     cbtk::Counters* hctr;   // pinned host mirror of the device counters

@@ -247,6 +247,9 @@ hipError_t launch_gather_counters(const Launch& X, Counters* out, hipStream_t s)
 // single-instance helpers for queries, snapshot and restore
 // IDs, pointer and forwarding records, commands, partials, counters -> cleared
 hipError_t launch_clear_pool(const Pool& P, hipStream_t s);
+// list lengths, partial sums and statistics lanes -> zero (frame scratch
+// shared with other instances)
+hipError_t launch_clear_frame_scratch(const Pool& P, hipStream_t s);
 hipError_t launch_bits_from_ids(const Pool& P, hipStream_t s);
 hipError_t launch_gather_ids(const Pool& P, uint32_t r0, uint32_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_gather_links(const Pool& P, uint32_t r0, uint32_t n, int32_t* out3, hipStream_t s);

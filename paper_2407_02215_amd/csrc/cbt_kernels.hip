@@ -2203,6 +2203,18 @@ __global__ void k_clear_pool(Pool P)
     }
 }
 
+// The frame's accumulators that must start at zero (list lengths, partial
+// sums, statistics lanes) -> cleared, for frame scratch that another
+// instance's frame may have used last.
+__global__ void k_clear_frame_scratch(Pool P)
+{
+    for (uint32_t g = threadIdx.x; g < (uint32_t)kMaxRankGroups; g += blockDim.x) {
+        P.lcnt[g] = 0;
+        P.part[g] = make_uint2(0, 0);
+    }
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(kStLanes * kLaneWords); i += blockDim.x) P.slane[i] = 0u;
+}
+
 __global__ void k_bits_from_ids(Pool P)
 {
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2637,6 +2649,12 @@ hipError_t launch_clear_pool(const Pool& P, hipStream_t s)
 {
     const uint32_t blocks = cdiv(P.cap, kBlock) < 4096u ? cdiv(P.cap, kBlock) : 4096u;
     hipLaunchKernelGGL(k_clear_pool, dim3(blocks), dim3(kBlock), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_frame_scratch(const Pool& P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_frame_scratch, dim3(1), dim3(kBlock), 0, s, P);
     return hipGetLastError();
 }
 
