@@ -79,19 +79,22 @@ def frame_counts(st: dict) -> dict:
 def paper_bytes(stage: str, st: dict, D: int) -> float:
     """Paper-minimal bytes of one stage's launch (the per-frame total
     16 L + 48 S + 24 N + 8 hops + 3/8 2^D split by where each term is
-    moved): enumerate reads the bitfield (2^D / 8); classify reads the 8-byte
-    ID and writes the 4-byte command (12 L); the rank-order scans read the
-    command (4 L, budget); the chain walk reads a twin and ORs a mark per hop
-    (8 S); the free list updates the bitfield of new blocks (4 N); the fill
-    reads each consumed record (20 S), writes its forwarding (16 S) and
-    every new record (20 N); the neighbour pass patches three pointers per
+    moved, to the stage of this pipeline that moves it): enumerate reads the
+    bitfield (2^D / 8); classify reads the 8-byte ID and writes the 4-byte
+    command (12 L); the rank-order scans read the command (4 L, budget); the
+    chain walk reads a twin and ORs a mark per hop (8 S); the free list
+    updates the bitfield of new blocks (4 N); of a consumed bisector's
+    20-byte record the fill reads the ID (8 S) and the pointer pass the three
+    pointers (12 S); the fill writes its forwarding (16 S); of a new 20-byte
+    record the fill writes the ID (8 N) and the pointer pass the three
+    pointers (12 N); the pointer pass patches three neighbour pointers per
     consumed bisector (12 S); the reduction reads the bitfield and writes the
     tree (2^D / 4).  The vote and the owner pass have no term."""
     c = frame_counts(st)
     L, S, N = c["L"], c["S"], c["N"]
     cap = float(1 << D)
     terms = {"enumerate": cap / 8, "classify": 12.0 * L, "vote": 0.0, "budget": 4.0 * L, "chain": 8.0 * S,
-             "owners": 0.0, "freelist": 4.0 * N, "fill": 36.0 * S + 20.0 * N, "resolve": 12.0 * S,
+             "owners": 0.0, "freelist": 4.0 * N, "fill": 24.0 * S + 8.0 * N, "resolve": 24.0 * S + 12.0 * N,
              "reduce": cap / 4}
     if stage == "frame":
         return sum(terms.values())
