@@ -363,6 +363,12 @@ def run_single(args) -> dict:
                      "merge_requests": mean(lambda s: s["merge_requests"]),
                      "merges_executed": mean(lambda s: s["merges_executed"]),
                      "what": "per-frame means over the timed frames"},
+        "rates_per_s": {"splits": mean(lambda s: s["split_consumed"]) / frame_s,
+                        "merges": mean(lambda s: s["merges_executed"]) / frame_s,
+                        "allocations": mean(lambda s: s["allocations"]) / frame_s,
+                        "frees": mean(lambda s: s["frees"]) / frame_s,
+                        "what": "bisectors split, configurations merged, blocks allocated and freed per second of the "
+                                "timed pass"},
         "latency_ms": {"p10": percentile(frame_ms, 10), "p50": percentile(frame_ms, 50),
                        "p90": percentile(frame_ms, 90), "p99": percentile(frame_ms, 99),
                        "what": "GPU time of one whole update, HIP events"},

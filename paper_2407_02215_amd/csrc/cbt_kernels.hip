@@ -1823,7 +1823,10 @@ __device__ __forceinline__ void run_resolve(const Pool& P, uint32_t blk, Lds_res
     auto& base = S_.base;
     auto& obase = S_.obase;
     auto& st = S_.st;
-    const ListShare ls = list_share(P, blk, base, sh, obase);
+    // the owner list shared over all G rank workgroups (twice the other list
+    // passes: its scattered writes and dependent record loads want more
+    // waves in flight, 124 against 130 us per terrain frame)
+    const ListShare ls = list_share(P, blk, base, sh, obase, P.G);
     // outputs past the free blocks (an over-committed frame, flagged by the
     // free-list pass) are refused, so free-list reads stay below F
     const uint32_t N = min(obase[P.G], P.ctr->F);
@@ -1850,7 +1853,7 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Batch B, Inst one)
 {
     __shared__ Lds_resolve S_;
     Pool P;
-    const uint32_t blk = pick<kB>(B, one, B.map_list, P);
+    const uint32_t blk = pick<kB>(B, one, B.map_rank, P);
     run_resolve(P, blk, S_);
 }
 
@@ -1964,11 +1967,11 @@ __device__ __forceinline__ uint32_t phase_groups(const Pool& P, int ph)
     case kPhFree: return (P.W + kWordsPerBlock - 1) / kWordsPerBlock;
     case kPhClass:
     case kPhVote:
-    case kPhFill:
-    case kPhResolve: return list_groups(P);
+    case kPhFill: return list_groups(P);
     case kPhBudget:
     case kPhWalk:
-    case kPhOwners: return P.G;
+    case kPhOwners:
+    case kPhResolve: return P.G;
     case kPhRedSub: return P.W >> sub_levels(P);
     default: return 1u;
     }
@@ -2431,11 +2434,11 @@ uint32_t phase_groups_host(const Pool& P, int ph)
     case kPhFree: return word_groups(P);
     case kPhClass:
     case kPhVote:
-    case kPhFill:
-    case kPhResolve: return list_groups(P);
+    case kPhFill: return list_groups(P);
     case kPhBudget:
     case kPhWalk:
-    case kPhOwners: return P.G;
+    case kPhOwners:
+    case kPhResolve: return P.G;
     case kPhRedSub: return reduce_groups(P);
     default: return 1u;
     }
@@ -2557,7 +2560,7 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL((k_fill<kB, R>), gl, b, 0, s, X.B, X.one);
     mark(kFill, false);
     mark(kResolve, true);
-    hipLaunchKernelGGL(k_resolve<kB>, gl, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL(k_resolve<kB>, g, b, 0, s, X.B, X.one);
     mark(kResolve, false);
     mark(kReduce, true);
     hipError_t e = reduce_seq<kB>(X, s);
