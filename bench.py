@@ -268,7 +268,14 @@ def run_single(args) -> dict:
     if args.schedule is not None:
         inst.set_schedule(*(int(x) for x in args.schedule.split(",")))
     print(f"# pre-roll {P} + warm-up {W} frames, schedule {inst.schedule()}", file=sys.stderr, flush=True)
-    for cam in w.cameras[:P + W]:
+    for cam in w.cameras[:P]:
+        inst.update(cam)
+    if args.schedule is None:
+        # the tuned schedule for this depth at the live count the timed
+        # window starts from
+        inst.apply_tuned()
+        print(f"# schedule {inst.schedule()} at {inst.live_count()} live", file=sys.stderr, flush=True)
+    for cam in w.cameras[P:P + W]:
         inst.update(cam)
     torch.cuda.synchronize()
     snap = inst.snapshot()
@@ -441,6 +448,9 @@ def run_batch(args) -> dict:
         for x, w in zip(insts, ws):
             x.update(w.cameras[f])
     torch.cuda.synchronize()
+    # each member's tuned schedule for the live count it has reached
+    for x in insts:
+        x.apply_tuned()
     snaps = [x.snapshot() for x in insts]
     timed = range(args.warmup, frames)
     print("# counting pass", file=sys.stderr, flush=True)

@@ -189,10 +189,7 @@ class Instance:
         if lod is not None:
             self.set_lod(lod)
         if tuned:
-            from . import tune
-            entry = tune.lookup(self.D, tune.load_table())
-            if entry is not None:
-                self.set_schedule(*entry)
+            self.apply_tuned(live=None)
 
     # -- lifecycle --------------------------------------------------------
     def close(self):
@@ -401,6 +398,18 @@ class Instance:
         r = C.c_int32()
         self._check(self.lib.cbt_get_schedule(self.h, C.byref(g), C.byref(r)))
         return int(g.value), int(r.value)
+
+    def apply_tuned(self, live: int | None = -1):
+        """Applies the tuned schedule of this depth for a live count: the
+        instance's current one by default, the depth's busiest tuned state
+        with live=None.  Returns the schedule, or None without a table."""
+        from . import tune
+        if live is not None and live < 0:
+            live = self.live_count()
+        entry = tune.lookup(self.D, tune.load_table(), live)
+        if entry is not None:
+            self.set_schedule(*entry)
+        return entry
 
     def canonical(self):
         """The triangulation as the sorted (root halfedge, subdivision code)

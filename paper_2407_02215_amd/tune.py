@@ -2,13 +2,19 @@
 
 For each CBT depth it builds a busy instance (a seeded closed sphere mesh
 whose halfedge count grows with the depth, sphere projection with fBm
-displacement, an orbit camera path run until the pool is well used),
-snapshots it, and then times the same frames under every candidate
-schedule -- rank workgroups G (each owns a contiguous chunk of ceil(L/G)
-ranks) and tree levels per reduction workgroup -- restoring the snapshot
-before each candidate.  Frame time is read from HIP events around the whole
-update.  The fastest schedule per depth is written to a JSON table that
-``cbt.Instance`` applies when it is created (``tuned=True``).
+displacement, an orbit camera path that refines it frame by frame) and
+snapshots it at several live counts on the way (when the live count first
+passes 1/256, 1/32 and 1/8 of the pool, and at the end of the path).  At
+each snapshot it times the same frames under every candidate schedule --
+rank workgroups G (each owns a contiguous chunk of ceil(L/G) ranks) and
+tree levels per reduction workgroup -- restoring the snapshot before each
+candidate.  Frame time is read from HIP events around the whole update.
+The fastest schedule per (depth, live count) is written to a JSON table;
+``cbt.Instance`` applies the entry of the nearest depth and live count
+(``tuned=True`` at creation, the busiest entry of the depth;
+``Instance.apply_tuned()`` for its current live count).  The workgroup
+size is not a candidate: the kernels' scans, LDS staging and wave counts
+are built for four wave64 per workgroup.
 
 Schedules change only how work is cut into workgroups, never results (the
 GPU tests check several schedules against the CPU reference).
@@ -17,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -46,13 +53,11 @@ def _time_frames(inst, cams) -> float:
     return ms / max(1, n)
 
 
-def tune_depth(D: int, seed: int = 17, warm: int = 40, timed: int = 8, verbose: bool = True) -> dict:
-    inst, w = _busy_instance(D, seed, warm + timed)
-    for c in w.cameras[:warm]:
-        inst.update(c)
-    snap = inst.snapshot()
-    live = inst.live_count()
-    cams = w.cameras[warm:warm + timed]
+LIVE_FRACS = (1 / 256, 1 / 32, 1 / 8)
+
+
+def _tune_snapshot(inst, snap, cams) -> dict:
+    """Every candidate schedule timed over cams from snap; the fastest."""
     results = []
     best = None
     for g in GROUPS:
@@ -75,29 +80,63 @@ def tune_depth(D: int, seed: int = 17, warm: int = 40, timed: int = 8, verbose: 
         results.append({"rank_groups": best[0], "reduce_levels": lv, "frame_ms": t})
         if t < best[2]:
             best = (best[0], lv, t)
+    return {"rank_groups": best[0], "reduce_levels": best[1], "frame_ms": best[2], "candidates": results}
+
+
+def tune_depth(D: int, seed: int = 17, warm: int = 40, timed: int = 8, verbose: bool = True) -> list:
+    inst, w = _busy_instance(D, seed, warm + timed)
+    cap = inst.cap
+    marks = [int(f * cap) for f in LIVE_FRACS]
+    snaps = []
+    for f, c in enumerate(w.cameras[:warm]):
+        inst.update(c)
+        live = inst.live_count()
+        while marks and live >= marks[0]:
+            marks.pop(0)
+            snaps.append((f + 1, live, inst.snapshot()))
+    if not snaps or snaps[-1][0] != warm:
+        snaps.append((warm, inst.live_count(), inst.snapshot()))
+    out = []
+    for f, live, snap in snaps:
+        cams = w.cameras[f:f + timed]
+        if len(cams) < timed:
+            continue
+        e = {"D": D, "live": live}
+        e.update(_tune_snapshot(inst, snap, cams))
+        out.append(e)
+        if verbose:
+            print(json.dumps({k: v for k, v in e.items() if k != "candidates"}), flush=True)
     inst.close()
-    out = {"D": D, "live": live, "rank_groups": best[0], "reduce_levels": best[1], "frame_ms": best[2],
-           "candidates": results}
-    if verbose:
-        print(json.dumps({k: v for k, v in out.items() if k != "candidates"}), flush=True)
     return out
 
 
 def load_table(path: str = TABLE) -> dict:
-    """depth -> (rank_groups, reduce_levels), empty when no table exists."""
+    """depth -> [(live, rank_groups, reduce_levels), ...] by live count,
+    empty when no table exists."""
     if not os.path.exists(path):
         return {}
     with open(path) as f:
         t = json.load(f)
-    return {int(e["D"]): (int(e["rank_groups"]), int(e["reduce_levels"])) for e in t["entries"]}
+    out = {}
+    for e in t["entries"]:
+        out.setdefault(int(e["D"]), []).append((int(e["live"]), int(e["rank_groups"]), int(e["reduce_levels"])))
+    return {d: sorted(v) for d, v in out.items()}
 
 
-def lookup(D: int, table: dict) -> tuple | None:
-    """The entry of the nearest tuned depth (None when the table is empty)."""
+def lookup(D: int, table: dict, live: int | None = None) -> tuple | None:
+    """(rank_groups, reduce_levels) of the nearest tuned depth, and within it
+    of the live count nearest to live (ratio-wise; the busiest entry when
+    live is None).  None when the table is empty."""
     if not table:
         return None
     d = min(table, key=lambda x: (abs(x - D), -x))
-    return table[d]
+    entries = table[d]
+    if live is None:
+        e = entries[-1]
+    else:
+        x = math.log(max(1, int(live)))
+        e = min(entries, key=lambda t: abs(math.log(max(1, t[0])) - x))
+    return e[1], e[2]
 
 
 def main():
@@ -109,7 +148,7 @@ def main():
     entries = []
     t0 = time.time()
     for D in [int(x) for x in args.depths.split(",")]:
-        entries.append(tune_depth(D))
+        entries += tune_depth(D)
     table = {"device": torch.cuda.get_device_name(0), "seconds": time.time() - t0, "entries": entries}
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)

@@ -122,3 +122,25 @@ def test_input_generators_are_seeded():
     assert np.array_equal(d1, I.random_decisions(1000, 5, 0.3, 0.2))
     assert not np.array_equal(d1, I.random_decisions(1000, 6, 0.3, 0.2))
     assert set(np.unique(d1).tolist()) <= {0, 1, 2}
+
+
+def test_tuned_schedule_lookup_by_depth_and_live_count(tmp_path):
+    """The tuned table holds several live counts per depth; the lookup takes
+    the nearest depth (the deeper one on a tie), then the live count nearest
+    by ratio, or the busiest entry when no live count is given."""
+    import json
+    from paper_2407_02215_amd import tune
+    entries = [{"D": 16, "live": 1000, "rank_groups": 32, "reduce_levels": 10},
+               {"D": 16, "live": 100000, "rank_groups": 256, "reduce_levels": 7},
+               {"D": 20, "live": 30000, "rank_groups": 64, "reduce_levels": 10},
+               {"D": 20, "live": 700000, "rank_groups": 512, "reduce_levels": 5}]
+    p = tmp_path / "schedule.json"
+    p.write_text(json.dumps({"device": "test", "seconds": 0.0, "entries": entries}))
+    t = tune.load_table(str(p))
+    assert t[16] == [(1000, 32, 10), (100000, 256, 7)]
+    assert tune.lookup(16, t) == (256, 7)
+    assert tune.lookup(16, t, 2000) == (32, 10)
+    assert tune.lookup(16, t, 50000) == (256, 7)      # log-nearer to 1e5 than to 1e3
+    assert tune.lookup(18, t, 800000) == (512, 5)     # tie between 16 and 20: the deeper table
+    assert tune.lookup(24, t, 40000) == (64, 10)
+    assert tune.lookup(16, {}, 5) is None
