@@ -576,7 +576,7 @@ def run_serve(args) -> dict:
 
     def serve(max_batch, slots):
         srv = cbt.Server(arena_bytes=arena, memory_budget=arena, max_batch=max_batch, slots=slots,
-                         map_capacity=1 << 22)
+                         map_capacity=1 << 22, tuned=True)
         ids = {}
         for k in range(args.instances):
             w, D, _ = specs[k]

@@ -447,6 +447,17 @@ cbt_status cbt_server_open(cbt_server s, const cbt_mesh* mesh, int32_t D, const 
                            int64_t* instance_id);
 cbt_status cbt_server_set_schedule(cbt_server s, int64_t instance_id, int32_t rank_groups,
                                    int32_t reduce_levels);
+/* Launch schedules by (depth, live count) for the instances that have none
+ * of their own (cbt_server_set_schedule): before each of an instance's
+ * frames the server takes, among the n entries, those of the depth nearest
+ * to the instance's (the deeper on a tie) and of them the one whose live
+ * count is nearest by ratio to the instance's live count after its last
+ * frame (its root count before the first).  Entries are checked as for
+ * cbt_set_schedule (CBT_E_ARG); an entry whose grids exceed the block-map
+ * capacity is skipped.  n = 0 clears the table.  Results do not depend on
+ * schedules. */
+cbt_status cbt_server_set_schedule_table(cbt_server s, int32_t n, const int32_t* depth, const int64_t* live,
+                                         const int32_t* rank_groups, const int32_t* reduce_levels);
 cbt_status cbt_server_submit(cbt_server s, int64_t instance_id, const cbt_camera* camera, uint64_t tag);
 /* Collects finished batches, launches new ones, and returns up to capacity
  * completions (with wait != 0 it blocks until at least one batch ends when

@@ -520,7 +520,7 @@ class ServerStats(C.Structure):
 
 
 SERVER_EXPORTS = ["cbt_server_overhead_bytes", "cbt_server_create", "cbt_server_open", "cbt_server_set_schedule",
-                  "cbt_server_submit", "cbt_server_poll", "cbt_server_drain", "cbt_server_query",
+                  "cbt_server_set_schedule_table", "cbt_server_submit", "cbt_server_poll", "cbt_server_drain", "cbt_server_query",
                   "cbt_server_close", "cbt_server_get_stats", "cbt_server_destroy"]
 EXPORTED += SERVER_EXPORTS
 
@@ -532,6 +532,7 @@ def _server_signatures(lib):
     lib.cbt_server_create.argtypes = [C.POINTER(ServerConfig), vp, C.c_size_t, C.POINTER(vp)]
     lib.cbt_server_open.argtypes = [vp, C.POINTER(Mesh), C.c_int32, C.POINTER(LodParams), C.POINTER(C.c_int64)]
     lib.cbt_server_set_schedule.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32]
+    lib.cbt_server_set_schedule_table.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     lib.cbt_server_submit.argtypes = [vp, C.c_int64, C.POINTER(Camera), C.c_uint64]
     lib.cbt_server_poll.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_int32)]
     lib.cbt_server_drain.argtypes = [vp]
@@ -548,7 +549,7 @@ class Server:
     submitted as they arrive and batched continuously on the device."""
 
     def __init__(self, arena_bytes: int, memory_budget: int = 0, max_batch: int = 128, slots: int = 2,
-                 map_capacity: int = 1 << 22, device: str = "cuda"):
+                 map_capacity: int = 1 << 22, device: str = "cuda", tuned: bool = False):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -568,6 +569,18 @@ class Server:
         self._tables = {}
         self._meta = {}
         self._buf = (Completion * 4096)()
+        if tuned:
+            from . import tune
+            self.set_schedule_table([(d, live, g, lv) for d, rows in tune.load_table().items()
+                                     for live, g, lv in rows])
+
+    def set_schedule_table(self, entries):
+        """(depth, live count, rank_groups, reduce_levels) entries the server
+        picks from for instances without a schedule of their own."""
+        n = len(entries)
+        arr = [np.ascontiguousarray([e[i] for e in entries], dt) for i, dt in
+               enumerate((np.int32, np.int64, np.int32, np.int32))]
+        self._check(self.lib.cbt_server_set_schedule_table(self.h, n, *(_ptr(a) for a in arr)))
 
     def _check(self, st):
         if st != CBT_OK:

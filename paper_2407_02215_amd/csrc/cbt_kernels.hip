@@ -59,10 +59,10 @@ namespace cbtk {
 // (all rows' loads in flight at once: these passes are bound by the latency
 // of the rank -> block -> command chain, not by bandwidth).
 constexpr int kClassRows = 4;   // LOD test: 48 bytes of vertices per rank
-// The LOD pass runs on the list passes' grid (half the rank workgroups),
-// each of its workgroups taking two consecutive rank chunks: fewer, longer
-// streams of vertex records measured faster.
-constexpr uint32_t kClassChunks = 2;
+// Rank chunks per workgroup of the LOD pass, which runs on the rank grid:
+// one chunk per workgroup (G workgroups) measured 71.6 us per terrain
+// frame against 76.6 us for two chunks on half as many workgroups.
+constexpr uint32_t kClassChunks = 1;
 // The rank-order scans (budget, owners) give each thread kSeg consecutive
 // ranks: one workgroup scan per kBlock * kSeg ranks, and the segment of
 // rank-list entries is one pair of 16-byte loads.  Rank chunks are whole
@@ -810,8 +810,8 @@ __device__ __forceinline__ void run_classify(const Pool& P, const LodK& K, const
 {
     auto& sh = S_.sh;
     auto& wcnt = S_.wcnt;
-    // each workgroup classifies kClassChunks consecutive rank chunks (the
-    // grid of the list passes), each chunk with its own partial and list
+    // each workgroup classifies kClassChunks consecutive rank chunks, each
+    // chunk with its own partial and list
     const int maxd = 63 - P.k;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t nsplit = 0, nmerge = 0, ncand = 0, tile = 0;
@@ -926,7 +926,7 @@ __global__ void __launch_bounds__(kBlock) k_classify(Batch B, Inst one)
     Pool P;
     LodK K;
     const uint8_t* inj;
-    const uint32_t blk = pick_k<kB>(B, one, B.map_list, P, K, inj);
+    const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
     run_classify<R>(P, K, inj, blk, S_);
 }
 
@@ -1965,9 +1965,9 @@ __device__ __forceinline__ uint32_t phase_groups(const Pool& P, int ph)
     switch (ph) {
     case kPhEnum:
     case kPhFree: return (P.W + kWordsPerBlock - 1) / kWordsPerBlock;
-    case kPhClass:
     case kPhVote:
     case kPhFill: return list_groups(P);
+    case kPhClass:
     case kPhBudget:
     case kPhWalk:
     case kPhOwners:
@@ -2432,9 +2432,9 @@ uint32_t phase_groups_host(const Pool& P, int ph)
     switch (ph) {
     case kPhEnum:
     case kPhFree: return word_groups(P);
-    case kPhClass:
     case kPhVote:
     case kPhFill: return list_groups(P);
+    case kPhClass:
     case kPhBudget:
     case kPhWalk:
     case kPhOwners:
@@ -2539,7 +2539,7 @@ static hipError_t frame_seq(const Launch& X, hipStream_t s, const StageEvents* e
     hipLaunchKernelGGL(k_enumerate<kB>, gw, b, 0, s, X.B, X.one);
     mark(kEnum, false);
     mark(kClass, true);
-    hipLaunchKernelGGL((k_classify<kB, R>), gl, b, 0, s, X.B, X.one);
+    hipLaunchKernelGGL((k_classify<kB, R>), g, b, 0, s, X.B, X.one);
     mark(kClass, false);
     mark(kVote, true);
     hipLaunchKernelGGL(k_vote<kB>, gl, b, 0, s, X.B, X.one);

@@ -11,6 +11,8 @@
 
 #include "cbt_host.h"
 
+#include <cmath>
+
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -96,6 +98,14 @@ struct cbt_server_s {
     // their oldest request; resident idle instances (nothing queued or in
     // flight) by last use -- the eviction order
     std::set<std::pair<double, int64_t>> ready, idle;
+    // tuned launch schedules by (depth, live count), for instances without a
+    // schedule of their own (cbt_server_set_schedule_table)
+    struct Sched {
+        int32_t D;
+        int64_t live;
+        int32_t groups, levels;
+    };
+    std::vector<Sched> sched;
     std::vector<Slot> slots;
     std::unordered_map<int64_t, SInst> inst;
     int64_t next_id = 1;
@@ -442,6 +452,35 @@ void harvest(cbt_server s, Slot& S)
     s->st.in_flight--;
 }
 
+uint64_t grid_need(int32_t D, int32_t groups, int32_t levels);
+
+// The table's schedule for a resident instance: the nearest tuned depth
+// (the deeper one on a tie), within it the entry whose live count is
+// nearest by ratio to the instance's count after its last frame (its root
+// count before the first); taken only when its grids fit the block maps.
+void apply_sched(cbt_server s, SInst& I)
+{
+    int32_t bestD = -1;
+    for (const auto& e : s->sched) {
+        const int32_t dd = std::abs(e.D - I.D), db = std::abs(bestD - I.D);
+        if (bestD < 0 || dd < db || (dd == db && e.D > bestD)) bestD = e.D;
+    }
+    const double x = std::log((double)std::max<int64_t>(1, I.live > 0 ? I.live : I.H));
+    const cbt_server_s::Sched* pick = nullptr;
+    double best = 0.0;
+    for (const auto& e : s->sched) {
+        if (e.D != bestD) continue;
+        const double dist = std::fabs(std::log((double)std::max<int64_t>(1, e.live)) - x);
+        if (!pick || dist < best) {
+            pick = &e;
+            best = dist;
+        }
+    }
+    if (!pick || grid_need(I.D, pick->groups, pick->levels) > (uint64_t)s->cfg.map_capacity) return;
+    I.h->P.G = (uint32_t)pick->groups;
+    I.h->P.sub = pick->levels;
+}
+
 cbt_status launch_slot(cbt_server s, Slot& S)
 {
     if (s->ready.empty()) return CBT_OK;
@@ -470,6 +509,7 @@ cbt_status launch_slot(cbt_server s, Slot& S)
             fail_queued(s, I, st);
             continue;
         }
+        if (!s->sched.empty() && I.groups == 0) apply_sched(s, I);
         const cbtk::Pool& P = I.h->P;
         const uint64_t r = P.G, w = cbtk::word_groups(P), d = cbtk::reduce_groups(P), l = cbtk::list_groups(P);
         if ((nr + r) + (nw + w) + (nd + d) + (nl + l) > (uint64_t)s->cfg.map_capacity) break;
@@ -709,6 +749,24 @@ cbt_status cbt_server_open(cbt_server s, const cbt_mesh* mesh, int32_t D, const 
         return cbth::fail(nullptr, CBT_E_BUDGET, "instance does not fit the memory budget");
     }
     *instance_id = id;
+    return CBT_OK;
+}
+
+cbt_status cbt_server_set_schedule_table(cbt_server s, int32_t n, const int32_t* depth, const int64_t* live,
+                                        const int32_t* rank_groups, const int32_t* reduce_levels)
+{
+    if (!s) return cbth::fail(nullptr, CBT_E_ARG, "NULL server");
+    if (n < 0 || (n > 0 && (!depth || !live || !rank_groups || !reduce_levels)))
+        return cbth::fail(nullptr, CBT_E_ARG, "invalid schedule table");
+    std::vector<cbt_server_s::Sched> t;
+    for (int32_t i = 0; i < n; ++i) {
+        if (depth[i] < 0 || depth[i] > 30 || live[i] < 0 || rank_groups[i] < cbtk::kMinRankGroups ||
+            rank_groups[i] > cbtk::kMaxRankGroups || reduce_levels[i] < cbtk::kMinReduceSub ||
+            reduce_levels[i] > cbtk::kMaxReduceSub)
+            return cbth::fail(nullptr, CBT_E_ARG, "schedule table entry %d out of range", i);
+        t.push_back({depth[i], live[i], rank_groups[i], reduce_levels[i]});
+    }
+    s->sched = std::move(t);
     return CBT_OK;
 }
 

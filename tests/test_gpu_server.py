@@ -45,7 +45,9 @@ def test_served_results_equal_alone(room):
     sizes = [cbt.workspace_bytes(w.mesh.H, w.depth) for w in ws]
     budget = sum(sorted(sizes)[-3:]) + (1 << 20) if room == "three" else max(sizes) + (1 << 12)
     log(f"[server] H={[w.mesh.H for w in ws]} D={[w.depth for w in ws]} budget={budget}")
-    srv = cbt.Server(arena_bytes=budget, memory_budget=budget, max_batch=4, slots=2, map_capacity=1 << 16)
+    # the tuned schedule table (per depth and live count) in one of the two runs
+    srv = cbt.Server(arena_bytes=budget, memory_budget=budget, max_batch=4, slots=2, map_capacity=1 << 16,
+                     tuned=(room == "three"))
     ids = [srv.open(w.mesh, w.depth, w.lod) for w in ws]
     rng = np.random.default_rng(5)
     nxt = [0] * len(ws)
