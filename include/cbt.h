@@ -383,6 +383,13 @@ cbt_status cbt_batch_update(cbt_batch b, const cbt_camera* cameras, const cbt_lo
 cbt_status cbt_batch_update_with_decisions(cbt_batch b, const uint8_t* const* device_decisions,
                                            cbt_frame_stats* stats);
 /* Releases the batch (not its workspace, not the members); synchronises. */
+/* Test hook for the failure path of a persistent batch: every wait of the
+ * given stage (1 .. 10: classify .. tree top, in pipeline order) gives up at
+ * once, as a wait that ran out of its bound does; the instances' later
+ * stages are skipped and the next update that reads statistics reports
+ * CBT_E_DEVICE (the members are then failed).  -1 restores normal waits.
+ * CBT_E_ARG for a batch that is not persistent.  Synchronises. */
+cbt_status cbt_batch_fail_stage(cbt_batch b, int32_t stage);
 cbt_status cbt_batch_destroy(cbt_batch b);
 
 /* ---- Serving loop ----------------------------------------------------------

@@ -26,7 +26,7 @@ EXPORTED = ["cbt_workspace_bytes", "cbt_init", "cbt_update", "cbt_update_with_de
             "cbt_set_schedule", "cbt_get_schedule", "cbt_stage_times", "cbt_batch_workspace_bytes", "cbt_batch_create",
             "cbt_batch_update", "cbt_batch_update_with_decisions", "cbt_batch_destroy", "cbt_update_converge",
             "cbt_export_triangles", "cbt_workspace_bytes_ex", "cbt_init_ex", "cbt_export_live", "cbt_import_live",
-            "cbt_update_noalloc", "cbt_noalloc_scratch_bytes"]
+            "cbt_update_noalloc", "cbt_noalloc_scratch_bytes", "cbt_batch_fail_stage"]
 
 INIT_FP64 = 1
 
@@ -115,6 +115,8 @@ def load_library():
     lib.cbt_batch_update.argtypes = [vp, vp, vp, vp]
     lib.cbt_batch_update_with_decisions.argtypes = [vp, vp, vp]
     lib.cbt_batch_destroy.argtypes = [vp]
+    lib.cbt_batch_fail_stage.argtypes = [vp, C.c_int32]
+    lib.cbt_batch_fail_stage.restype = C.c_int32
     lib.cbt_status_string.argtypes = [C.c_int32]
     lib.cbt_status_string.restype = C.c_char_p
     lib.cbt_last_error.argtypes = [vp]
@@ -474,6 +476,11 @@ class Batch:
         st = (FrameStats * self.n)() if stats else None
         self._check(self.lib.cbt_batch_update(self.h, cams, lods, st))
         return [s.as_dict() for s in st] if stats else None
+
+    def fail_stage(self, stage: int):
+        """Test hook (persistent batches): the given stage's waits give up
+        at once; -1 restores them."""
+        self._check(self.lib.cbt_batch_fail_stage(self.h, int(stage)))
 
     def update_with_decisions(self, decisions, stats: bool = False):
         torch = self._torch

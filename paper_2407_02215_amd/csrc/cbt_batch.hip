@@ -312,6 +312,7 @@ cbt_status cbt_batch_create(const cbt_handle* members, int32_t n, void* device_w
             return st2;
         }
         X.W.map = d_pmap;
+        X.W.fail_phase = cbtk::kPhCount;
         X.W.ticket = reinterpret_cast<uint32_t*>(ws + L.ticket);
         X.W.done = reinterpret_cast<uint32_t*>(ws + L.done);
         const uint32_t resident = cbtk::persist_resident_groups(X.f64);
@@ -364,6 +365,23 @@ cbt_status cbt_batch_update_with_decisions(cbt_batch b, const uint8_t* const* de
     st = run_frame(b);
     if (st) return st;
     return finish(b, stats);
+}
+
+cbt_status cbt_batch_fail_stage(cbt_batch b, int32_t stage)
+{
+    if (!b) return cbth::fail(nullptr, CBT_E_ARG, "NULL batch");
+    if (!b->X.persistent) return cbth::fail(nullptr, CBT_E_ARG, "not a persistent batch");
+    if (stage != -1 && (stage < 1 || stage >= cbtk::kPhCount))
+        return cbth::fail(nullptr, CBT_E_ARG, "stage %d outside [1, %d)", stage, (int)cbtk::kPhCount);
+    BATCH_TRY(b, hipStreamSynchronize(b->stream), "synchronise");
+    b->X.W.fail_phase = stage < 0 ? (uint32_t)cbtk::kPhCount : (uint32_t)stage;
+    // the launch arguments live in the captured graph: capture again
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->captured = false;
+    return CBT_OK;
 }
 
 cbt_status cbt_batch_destroy(cbt_batch b)

@@ -178,6 +178,7 @@ struct Persist {
     uint32_t* done;
     const uint32_t* map;   // per item: instance << kMapShift | span index
     uint32_t first[kPhCount + 1];
+    uint32_t fail_phase;   // test hook: this stage's waits give up at once (kPhCount: none)
 };
 
 // Everything a launch sequence needs: either one instance passed by value

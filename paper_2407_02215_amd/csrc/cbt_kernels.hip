@@ -65,9 +65,10 @@ constexpr int kClassRows = 4;   // LOD test: 48 bytes of vertices per rank
 constexpr uint32_t kClassChunks = 1;
 // The rank-order scans (budget, owners) give each thread kSeg consecutive
 // ranks: one workgroup scan per kBlock * kSeg ranks, and the segment of
-// rank-list entries is one pair of 16-byte loads.  Rank chunks are whole
-// segments.
-constexpr int kSeg = 8;
+// rank-list entries is one 16-byte load (4 ranks measured 22 + 28 us per
+// terrain frame for the two scans against 24 + 35 us with 8).  Rank chunks
+// are whole segments.
+constexpr int kSeg = 4;
 
 // ---------------------------------------------------------------------------
 // wave64 / workgroup scan primitives
@@ -372,7 +373,7 @@ __device__ __forceinline__ uint32_t share_start(const uint32_t* base, uint32_t G
 }
 
 // block numbers of ranks [t0, t0 + kSeg); t0 is a multiple of kSeg below
-// the pool size, so the two 16-byte loads stay inside the rank list; ranks
+// the pool size, so the 16-byte loads stay inside the rank list; ranks
 // from r1 on read as block 0 (in bounds, unused)
 __device__ __forceinline__ void load_seg(const Pool& P, uint32_t t0, uint32_t r1, uint32_t (&s)[kSeg])
 {
@@ -2073,18 +2074,26 @@ k_persist(Batch B, Persist W)
                     const Pool& Pq = Z.B.inst[in].P;
                     const uint32_t want = persist_items(phase_groups(Pq, ph - 1));
                     const uint32_t* dp = Z.W.done + (size_t)in * kPhCount + (ph - 1);
+                    const uint32_t* ep = &Pq.ctr->err;
                     uint32_t n = 0;
-                    while (__hip_atomic_load(dp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                    // a stage the host marked (test hook) gives up at once,
+                    // as if its wait had run out
+                    if ((uint32_t)ph == Z.W.fail_phase) n = kSpinLimit;
+                    while (n >= kSpinLimit ||
+                           __hip_atomic_load(dp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
                         // give up after kSpinLimit polls, or at once when an
                         // earlier wait of this instance gave up
                         if (++n >= kSpinLimit ||
-                            (__hip_atomic_load(&Pq.ctr->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrSpin)) {
+                            (__hip_atomic_load(ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrSpin)) {
                             raise_err(Pq, kErrSpin);
                             go = 0;
                             break;
                         }
                         __builtin_amdgcn_s_sleep(2);
                     }
+                    // once a wait of this instance has given up, none of its
+                    // later stages runs (their inputs would be incomplete)
+                    if (__hip_atomic_load(ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrSpin) go = 0;
                     // one acquire for the whole wait: the die's caches
                     // are invalidated once the earlier phase is complete
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

@@ -122,3 +122,33 @@ def test_persistent_spans_match_single_instances():
     batch.close()
     for x in alone + members:
         x.close()
+
+
+def test_persistent_wait_failure_is_reported():
+    """The failure path of the persistent frame, forced from the host: the
+    budget stage's waits give up at once (as a wait that ran out of its
+    bound would), the later stages are skipped, the update reports a device
+    error and the members refuse further work; the device itself stays
+    usable (a new instance then matches the CPU reference)."""
+    ws = I.batched_workloads(3, frames=6, seed=7, h_range=(24, 800), d_range=(12, 14), table_res=64)
+    members = [cbt.Instance(w.mesh, w.depth, w.lod) for w in ws]
+    log("[batch failure path] persistent, budget stage forced to give up")
+    batch = cbt.Batch(members, graph=True, persistent=True)
+    batch.update([w.cameras[0] for w in ws], stats=True)
+    batch.fail_stage(3)
+    with pytest.raises(cbt.CbtError) as e:
+        batch.update([w.cameras[1] for w in ws], stats=True)
+    assert e.value.status == -5 and "0x20" in str(e.value)
+    with pytest.raises(cbt.CbtError):
+        members[0].update(ws[0].cameras[2])
+    batch.close()
+    for m in members:
+        m.close()
+    w = ws[1]
+    inst = cbt.Instance(w.mesh, w.depth, w.lod)
+    orc = Oracle(w.mesh, w.depth, w.lod)
+    for cam in w.cameras[:4]:
+        inst.update(cam)
+        orc.frame(camera=cam)
+    assert_same_state(inst, orc, "after the failure")
+    inst.close()
