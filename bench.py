@@ -301,8 +301,8 @@ def run_single(args) -> dict:
     inst.time_stage(None)
     again = inst.pool()
     assert all(np.array_equal(a, b) for a, b in zip(check, again)), "non-deterministic frame"
-    print("# stage survey", file=sys.stderr, flush=True)
-    survey = {}
+    print("# per-stage timing pass", file=sys.stderr, flush=True)
+    stage_mean = {}
     for stage in STAGES:
         inst.restore(*snap)
         inst.time_stage(stage)
@@ -310,7 +310,7 @@ def run_single(args) -> dict:
             inst.update(cam)
         n_st, ms_st = inst.stage_time()
         inst.time_stage(None)
-        survey[stage] = ms_st / max(1, n_st)
+        stage_mean[stage] = ms_st / max(1, n_st)
     # triangle export of the final state: live list (4), vertex record, 36
     # bytes written per triangle
     L = inst.live_count()
@@ -336,8 +336,8 @@ def run_single(args) -> dict:
     from paper_2407_02215_amd import traffic as T
     rec = T.lookup(args.workload, args.criterion, args.precision, P, W, K, schedule)
     # dominant kernel: the longest stage the paper-minimal model gives bytes
-    dominant = max((k for k in STAGES if mean(lambda s, k=k: paper_bytes(k, s, D)) > 0), key=survey.get)
-    mean_ms = survey[dominant]
+    dominant = max((k for k in STAGES if mean(lambda s, k=k: paper_bytes(k, s, D)) > 0), key=stage_mean.get)
+    mean_ms = stage_mean[dominant]
     pb = mean(lambda s: paper_bytes(dominant, s, D))
     lb = mean(lambda s: layout_bytes(dominant, s, D, vb))
     counted = rec["kernels"].get(dominant, {}).get("bytes") if rec else None
@@ -381,7 +381,7 @@ def run_single(args) -> dict:
                        "what": "GPU time of one whole update, HIP events"},
         "export": {"triangles": L, "ms": exp_mean, "alg_bytes": exp_bytes,
                    "achieved_gbs": exp_bytes / (exp_mean * 1e-3) / 1e9},
-        "stage_ms": survey,
+        "stage_ms": stage_mean,
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": gbs(pb, mean_ms * 1e-3), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs(pb, mean_ms * 1e-3) / HBM_PEAK_GBS, "traffic": counted,
                      "traffic_unit": "HBM bytes per launch", "mean_launch_ms": mean_ms,
