@@ -133,15 +133,15 @@ def layout_bytes(stage: str, st: dict, D: int, vb: int = 48) -> float:
         # bitfield read + write, a free-list entry per new block
         return cap / 4 + 4.0 * c["N"]
     if stage == "fill":
-        # owner entries (8 + 4); a split bisector's ID (8) and vertex record
-        # (vb) read, its fate + forwarding written (20); per split output a
-        # free-list entry (4), a vertex record (vb) and the heap ID (8); a
-        # merge reads its smallest member's forwarding (16), per parent a
-        # member's ID (8), three of the children's six world positions (vb),
-        # a free-list entry (4) and writes the parent's record (vb) and heap
-        # ID (8); every merged member's fate + forwarding (20).  Flat
-        # vertices are decoded from the IDs.
-        return (12.0 * (S + C) + (28.0 + vb) * S + (12.0 + vb) * O + 16.0 * C + (20.0 + 2.0 * vb) * P
+        # owner entries (8 + 4); a split bisector's vertex record (vb, its
+        # heap ID included) read, its fate + forwarding written (20); per
+        # split output a free-list entry (4) and a vertex record (vb); a
+        # merge reads its smallest member's forwarding (16), per parent
+        # three of the children's six world positions and a member's ID
+        # (vb), a free-list entry (4) and writes the parent's record (vb);
+        # every merged member's fate + forwarding (20).  Flat vertices are
+        # decoded from the IDs.
+        return (12.0 * (S + C) + (20.0 + vb) * S + (4.0 + vb) * O + 16.0 * C + (4.0 + 2.0 * vb) * P
                 + 20.0 * M)
     if stage == "resolve":
         # owner entries (8); a split bisector's pointers (16) and its

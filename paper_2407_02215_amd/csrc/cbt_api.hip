@@ -399,7 +399,7 @@ static cbt_status init_impl(const cbt_mesh* mesh, int32_t D, uint32_t flags, voi
         INIT_TRY(cbtk::launch_import_records(P, 0, (uint32_t)H, staging, s), "root records");
         INIT_TRY(cbtk::launch_bits_from_ids(P, s), "bitfield");
         INIT_TRY(cbtk::launch_reduce(cbtk::single_launch(P, h->wk, nullptr), s), "sum reduction");
-        INIT_TRY(cbtk::launch_refresh(cbtk::single_launch(P, h->wk, nullptr), s), "vertex cache");
+        INIT_TRY(cbtk::launch_refresh(cbtk::single_launch(P, h->wk, nullptr), s, true), "vertex cache");
         INIT_TRY(hipStreamSynchronize(s), "init synchronise");
     } else if (!roots_cached) {
         INIT_TRY(hipStreamSynchronize(s), "init synchronise");   // the local root array goes out of scope
@@ -474,7 +474,7 @@ cbt_status cbt_update(cbt_handle h, const cbt_camera* camera, const cbt_lod_para
     if (cbth::world_changed(K, h->wk)) {
         // new world-position parameters: recompute the cached world positions
         h->wk = K;
-        HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), h->stream), "vertex cache");
+        HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), h->stream, false), "vertex cache");
     }
     HIP_TRY(h, cbtk::launch_frame(cbtk::single_launch(h->P, K, nullptr), h->stream, next_events(h)), "frame launch");
     return finish_frame(h, stats);
@@ -558,7 +558,7 @@ cbt_status cbt_update_noalloc(cbt_handle h, const cbt_camera* camera, const cbt_
     HIP_TRY(h, cbtk::launch_clear_frame_scratch(Q, h->stream), "clear scratch");
     if (cbth::world_changed(K, h->wk)) {
         h->wk = K;
-        HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(Q, K, nullptr), h->stream), "vertex cache");
+        HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(Q, K, nullptr), h->stream, false), "vertex cache");
     }
     HIP_TRY(h, cbtk::launch_frame(cbtk::single_launch(Q, K, nullptr), h->stream, nullptr), "frame launch");
     // the frame's rank list lives in the shared scratch, not in the handle
@@ -843,7 +843,7 @@ cbt_status cbt_restore(cbt_handle h, const uint64_t* heap_id, const int32_t* twi
     const cbtk::Launch X = cbtk::single_launch(P, h->wk, nullptr);
     HIP_TRY(h, cbtk::launch_bits_from_ids(P, h->stream), "bitfield");
     HIP_TRY(h, cbtk::launch_reduce(X, h->stream), "sum reduction");
-    HIP_TRY(h, cbtk::launch_refresh(X, h->stream), "vertex cache");
+    HIP_TRY(h, cbtk::launch_refresh(X, h->stream, true), "vertex cache");
     HIP_TRY(h, hipStreamSynchronize(h->stream), "synchronise");
     h->last_frame_valid = 0;
     return CBT_OK;
@@ -890,7 +890,7 @@ cbt_status cbt_import_live(cbt_handle h, const uint32_t* records, int64_t count,
     const cbtk::Launch X = cbtk::single_launch(P, h->wk, nullptr);
     HIP_TRY(h, cbtk::launch_bits_from_ids(P, s), "bitfield");
     HIP_TRY(h, cbtk::launch_reduce(X, s), "sum reduction");
-    HIP_TRY(h, cbtk::launch_refresh(X, s), "vertex cache");
+    HIP_TRY(h, cbtk::launch_refresh(X, s, true), "vertex cache");
     h->last_frame_valid = 0;
     return read_counters(h);
 }

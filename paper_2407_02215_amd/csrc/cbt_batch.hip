@@ -339,7 +339,7 @@ cbt_status cbt_batch_update(cbt_batch b, const cbt_camera* cameras, const cbt_lo
         cbt_handle h = b->m[i];
         if (cbth::world_changed(K[i], h->wk)) {
             h->wk = K[i];
-            BATCH_TRY(b, cbtk::launch_refresh(cbtk::single_launch(b->pools[i], K[i], nullptr), b->stream),
+            BATCH_TRY(b, cbtk::launch_refresh(cbtk::single_launch(b->pools[i], K[i], nullptr), b->stream, false),
                       "vertex cache");
         }
     }

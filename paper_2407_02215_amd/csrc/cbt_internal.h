@@ -110,7 +110,9 @@ struct LinkFwd {
 
 // Device state of one instance, carved from its workspace.
 struct Pool {
-    uint64_t* id;      // [cap] heap ID per block (stale when free)
+    uint64_t* id;      // [cap] heap IDs as the last initialisation or import
+                       //       wrote them; a frame keeps a block's ID in its
+                       //       vertex record only
     LinkFwd* lf;       // [cap] pointer and forwarding records, side by side
     float4* vworld;    // [3 cap] world positions of the three vertices; the w
                        //         components hold raw bits: the subdivision depth
@@ -236,7 +238,9 @@ hipError_t launch_reduce(const Launch& X, hipStream_t s);
 hipError_t launch_enumerate(const Launch& X, hipStream_t s);
 // rebuild the vertex cache of every live block: world positions (with the
 // instance's K) of the vertices decoded from its heap ID
-hipError_t launch_refresh(const Launch& X, hipStream_t s);
+// from_ids: the heap IDs come from the ID array (after an initialisation or
+// an import), else from the live blocks' own vertex records
+hipError_t launch_refresh(const Launch& X, hipStream_t s, bool from_ids);
 
 // cached world positions of the L live bisectors in rank order (after an
 // enumeration) -> out9[9 L]

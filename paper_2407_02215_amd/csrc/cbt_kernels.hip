@@ -584,6 +584,18 @@ __device__ __forceinline__ T4<R>* world_rec(const Pool& P, uint32_t s)
     return reinterpret_cast<T4<R>*>(P.vworld) + 3 * (size_t)s;
 }
 
+// Heap ID of a live block, from its vertex record (the frame keeps it there
+// only; the ID array holds the IDs of the last initialisation or import).
+__device__ __forceinline__ uint64_t block_id(const Pool& P, uint32_t s)
+{
+    if (P.f64) {
+        const double4* r = world_rec<double>(P, s);
+        return RecId<double>::get(r[1], r[2]);
+    }
+    const float4* r = world_rec<float>(P, s);
+    return RecId<float>::get(r[1], r[2]);
+}
+
 // Splitting matrices applied from the root downwards, one path bit per
 // level, most significant first: M0 -> (v0, v2, m), M1 -> (v2, v1, m).
 // Scalar registers only (struct selects would be lowered through scratch).
@@ -781,14 +793,13 @@ __device__ __forceinline__ void store_world(const Pool& P, uint32_t s, Vec3<R> p
     store_rec(world_rec<R>(P, s), pa, pb, pc, depth, id);
 }
 
-// a new bisector's vertex record and heap ID (the pointer pass writes its
-// pointers)
+// a new bisector's vertex record, which carries its heap ID (the pointer
+// pass writes its pointers)
 template <typename R>
 __device__ __forceinline__ void store_output(const Pool& P, uint32_t q, Vec3<R> pa, Vec3<R> pb, Vec3<R> pc, int depth,
                                              uint64_t id)
 {
     store_world<R>(P, q, pa, pb, pc, depth, id);
-    P.id[q] = id;
 }
 
 // ---------------------------------------------------------------------------
@@ -971,7 +982,7 @@ __device__ __forceinline__ int merge_vote_even(const Pool& P, uint32_t s, int d,
     if (!slot_ok(P, j4)) { raise_err(P, kErrPointer); return 0; }
     const uint32_t cm4 = P.cmd[j4];
     if (!merges(cm4)) return 0;
-    if (P.id[j4] < P.id[s]) return 0;   // found from the cycle's smallest member
+    if (block_id(P, (uint32_t)j4) < block_id(P, s)) return 0;   // found from the cycle's smallest member
     *j3o = j3;
     *j4o = j4;
     return 4;
@@ -2160,15 +2171,18 @@ __global__ void k_persist_clear(Persist W, uint32_t n)
 // ---------------------------------------------------------------------------
 
 // Rebuild the cache of every live block: world positions of the Alg. 2
-// decode of its heap ID.
+// decode of its heap ID, taken from the ID array (after an initialisation
+// or an import, which write it) or from the block's own record (new world
+// parameters between frames).
 template <typename R>
-__device__ __forceinline__ void run_refresh(const Pool& P, const LodK& K, const uint8_t* inj, uint32_t blk)
+__device__ __forceinline__ void run_refresh(const Pool& P, const LodK& K, const uint8_t* inj, uint32_t blk,
+                                            bool from_ids)
 {
     (void)inj;
     const uint32_t L = P.ctr->L;
     for (uint32_t r = blk * kBlock + threadIdx.x; r < L; r += P.G * kBlock) {
         const uint32_t s = P.live[r];
-        const uint64_t id = P.id[s];
+        const uint64_t id = from_ids ? P.id[s] : block_id(P, s);
         Vec3<R> a = {0, 0, 0}, b = a, c = a;
         int d = 0;
         if (valid_id(P, id)) {
@@ -2182,13 +2196,13 @@ __device__ __forceinline__ void run_refresh(const Pool& P, const LodK& K, const 
 }
 
 template <bool kB, typename R>
-__global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one)
+__global__ void __launch_bounds__(kBlock) k_refresh(Batch B, Inst one, bool from_ids)
 {
     Pool P;
     LodK K;
     const uint8_t* inj;
     const uint32_t blk = pick_k<kB>(B, one, B.map_rank, P, K, inj);
-    run_refresh<R>(P, K, inj, blk);
+    run_refresh<R>(P, K, inj, blk, from_ids);
 }
 
 // Clears a pool before it is filled: heap IDs, pointer and forwarding
@@ -2242,7 +2256,7 @@ __global__ void k_gather_ids(Pool P, uint32_t r0, uint32_t n, uint64_t* out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    out[i] = P.id[P.live[r0 + i]];
+    out[i] = block_id(P, P.live[r0 + i]);
 }
 
 // The bisector of rank r0 + i in the paper's notation b_j^d: its root
@@ -2251,7 +2265,7 @@ __global__ void k_gather_canonical(Pool P, uint32_t r0, uint32_t n, int32_t* roo
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint64_t id = P.id[P.live[r0 + i]];
+    const uint64_t id = block_id(P, P.live[r0 + i]);
     int32_t h = -1;
     uint64_t c = 0;
     if (valid_id(P, id)) {
@@ -2283,7 +2297,7 @@ __global__ void k_gather_vertices(Pool P, uint32_t r0, uint32_t n, O* out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint64_t id = P.id[P.live[r0 + i]];
+    const uint64_t id = block_id(P, P.live[r0 + i]);
     Vec3<R> v[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     if (valid_id(P, id)) decode<R>(P, id, ilog2_64(id) - P.k, v[0], v[1], v[2]);
     else raise_err(P, kErrPointer);
@@ -2334,7 +2348,7 @@ __global__ void k_export_records(Pool P, uint32_t b0, uint32_t n, uint32_t* out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint64_t id = P.id[b0 + i];
+    const uint64_t id = block_id(P, b0 + i);   // meaningful for live blocks only
     const int4 l = P.lf[b0 + i].l;
     uint32_t* o = out + 5 * (size_t)i;
     o[0] = (uint32_t)id;
@@ -2360,7 +2374,7 @@ __global__ void k_export_live(Pool P, uint32_t L, uint32_t* out)
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= L) return;
     const uint32_t s = P.live[r];
-    const uint64_t id = P.id[s];
+    const uint64_t id = block_id(P, s);
     const int4 l = P.lf[s].l;
     uint32_t* o = out + 6 * (size_t)r;
     o[0] = s;
@@ -2615,17 +2629,17 @@ hipError_t launch_enumerate(const Launch& X, hipStream_t s)
     return X.batched ? enumerate_seq<true>(X, s) : enumerate_seq<false>(X, s);
 }
 
-hipError_t launch_refresh(const Launch& X, hipStream_t s)
+hipError_t launch_refresh(const Launch& X, hipStream_t s, bool from_ids)
 {
     hipError_t e = launch_enumerate(X, s);
     if (e != hipSuccess) return e;
     const dim3 g(X.grid_rank), b(kBlock);
     if (X.f64) {
-        if (X.batched) hipLaunchKernelGGL((k_refresh<true, double>), g, b, 0, s, X.B, X.one);
-        else hipLaunchKernelGGL((k_refresh<false, double>), g, b, 0, s, X.B, X.one);
+        if (X.batched) hipLaunchKernelGGL((k_refresh<true, double>), g, b, 0, s, X.B, X.one, from_ids);
+        else hipLaunchKernelGGL((k_refresh<false, double>), g, b, 0, s, X.B, X.one, from_ids);
     } else {
-        if (X.batched) hipLaunchKernelGGL((k_refresh<true, float>), g, b, 0, s, X.B, X.one);
-        else hipLaunchKernelGGL((k_refresh<false, float>), g, b, 0, s, X.B, X.one);
+        if (X.batched) hipLaunchKernelGGL((k_refresh<true, float>), g, b, 0, s, X.B, X.one, from_ids);
+        else hipLaunchKernelGGL((k_refresh<false, float>), g, b, 0, s, X.B, X.one, from_ids);
     }
     return hipGetLastError();
 }

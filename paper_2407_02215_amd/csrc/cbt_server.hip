@@ -300,7 +300,7 @@ cbt_status import_async(cbt_handle h, const uint32_t* records, uint32_t n)
     HIP_TRY(h, cbtk::launch_import_live(P, n, records, st), "import live records");
     HIP_TRY(h, cbtk::launch_bits_from_ids(P, st), "bitfield");
     HIP_TRY(h, cbtk::launch_reduce(X, st), "sum reduction");
-    HIP_TRY(h, cbtk::launch_refresh(X, st), "vertex cache");
+    HIP_TRY(h, cbtk::launch_refresh(X, st, true), "vertex cache");
     h->last_frame_valid = 0;
     return CBT_OK;
 }
@@ -538,7 +538,7 @@ cbt_status launch_slot(cbt_server s, Slot& S)
         cbt_handle h = I.h;
         if (cbth::world_changed(K, h->wk)) {
             h->wk = K;
-            HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), s->aux), "vertex cache");
+            HIP_TRY(h, cbtk::launch_refresh(cbtk::single_launch(h->P, K, nullptr), s->aux, false), "vertex cache");
             s->aux_pending = true;
         }
         S.h_inst[i].P = h->P;

@@ -333,3 +333,34 @@ def test_canonical_pairs_match_reference():
     assert inst.canonical() == orc.canonical()
     assert len(set(inst.canonical())) == live.size
     inst.close()
+
+
+def test_new_world_parameters_between_frames():
+    """A displacement amplitude that changes between frames: the cached world
+    positions are rebuilt from the heap IDs the vertex records carry (the
+    frames write no other copy), and the frames after it follow the
+    reference, for a single instance and for a batch member."""
+    import dataclasses
+    w = I.workload("planet", frames=40, table_res=64)
+    inst = cbt.Instance(w.mesh, w.depth, w.lod)
+    member = cbt.Instance(w.mesh, w.depth, w.lod)
+    batch = cbt.Batch([member], graph=False)
+    orc = Oracle(w.mesh, w.depth, w.lod)
+    steeper = dataclasses.replace(w.lod, amplitude=w.lod.amplitude * 4.0)
+    for f, cam in enumerate(w.cameras[:24]):
+        if f == 12:
+            for x in (inst, member, orc):
+                x.set_lod(steeper)
+        log(f"[new world] frame {f} L={orc.live_count}")
+        inst.update(cam)
+        batch.update([cam])
+        orc.frame(camera=cam)
+        assert_same_state(inst, orc, f"frame {f}")
+        if f in (12, 13, 23):
+            _vertices_match(inst, orc, f"frame {f}")
+            _vertices_match(member, orc, f"member, frame {f}")
+            assert_same_state(member, orc, f"member, frame {f}")
+    assert orc.live_count > 10000
+    batch.close()
+    inst.close()
+    member.close()
