@@ -861,7 +861,7 @@ cbt_status cbt_export_live(cbt_handle h, uint32_t* records, int64_t capacity, in
     *count = L;
     if (capacity < (int64_t)L) return fail(h, CBT_E_CAPACITY, "capacity %lld < %u live bisectors", (long long)capacity, L);
     if (!records) return fail(h, CBT_E_ARG, "NULL records");
-    HIP_TRY(h, cbtk::launch_export_live(P, L, records, h->stream), "export live records");
+    HIP_TRY(h, cbtk::launch_export_live(P, L, records, h->stream, false), "export live records");
     return CBT_OK;
 }
 

@@ -270,7 +270,9 @@ hipError_t launch_export_heap(const Pool& P, uint32_t* out, hipStream_t s);
 // live bisectors in rank order (after an enumeration) <-> packed records
 // (block, id low, id high, twin, next, prev); the import scatters into a
 // cleared pool and flags blocks or pointers out of range
-hipError_t launch_export_live(const Pool& P, uint32_t L, uint32_t* out6, hipStream_t s);
+// into_cache: out6 lies in the pool's own vertex cache (the IDs are first
+// copied to the ID array, so no record is overwritten before it is read)
+hipError_t launch_export_live(const Pool& P, uint32_t L, uint32_t* out6, hipStream_t s, bool into_cache);
 hipError_t launch_import_live(const Pool& P, uint32_t n, const uint32_t* in6, hipStream_t s);
 // blocks [b0, b0+n) <-> packed records (id low, id high, twin, next, prev)
 hipError_t launch_export_records(const Pool& P, uint32_t b0, uint32_t n, uint32_t* out5, hipStream_t s);

@@ -220,6 +220,21 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* sh)
     return t;
 }
 
+// saturating sum over the workgroup, returned to every thread; sh holds >= 4
+__device__ __forceinline__ uint32_t block_sum_sat(uint32_t v, uint32_t* sh)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = sat_add(v, __shfl_xor(v, o, 64));
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) t = sat_add(t, sh[i]);
+    __syncthreads();
+    return t;
+}
+
 // ---------------------------------------------------------------------------
 // instance selection
 // ---------------------------------------------------------------------------
@@ -915,7 +930,9 @@ __device__ __forceinline__ void run_classify(const Pool& P, const LodK& K, const
             }
             nlist = at - r0;
         }
-        const uint32_t c = block_sum(scost, sh);
+        // a chunk's split reservations can pass 2^32 in the deepest pools
+        // (2^30 blocks over 16 workgroups); a saturated sum is over any F
+        const uint32_t c = block_sum_sat(scost, sh);
         if (threadIdx.x == 0) {
             P.part[rb] = make_uint2(0, c);
             P.lcnt[rb] = nlist;
@@ -2368,13 +2385,25 @@ __global__ void k_import_records(Pool P, uint32_t b0, uint32_t n, const uint32_t
     P.lf[b0 + i].f = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
 }
 
-// Live records, rank order: (block, id low, id high, twin, next, prev).
-__global__ void k_export_live(Pool P, uint32_t L, uint32_t* out)
+// Heap IDs of the live blocks copied from their vertex records into the ID
+// array, for an export whose output overwrites the vertex cache.
+__global__ void k_ids_from_records(Pool P, uint32_t L)
 {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= L) return;
     const uint32_t s = P.live[r];
-    const uint64_t id = block_id(P, s);
+    P.id[s] = block_id(P, s);
+}
+
+// Live records, rank order: (block, id low, id high, twin, next, prev); the
+// IDs from the vertex records, or from the ID array (from_ids: after
+// k_ids_from_records, when the output lies in the vertex cache).
+__global__ void k_export_live(Pool P, uint32_t L, uint32_t* out, bool from_ids)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= L) return;
+    const uint32_t s = P.live[r];
+    const uint64_t id = from_ids ? P.id[s] : block_id(P, s);
     const int4 l = P.lf[s].l;
     uint32_t* o = out + 6 * (size_t)r;
     o[0] = s;
@@ -2652,9 +2681,10 @@ hipError_t launch_export_triangles(const Pool& P, uint32_t L, float* out9, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_export_live(const Pool& P, uint32_t L, uint32_t* out6, hipStream_t s)
+hipError_t launch_export_live(const Pool& P, uint32_t L, uint32_t* out6, hipStream_t s, bool into_cache)
 {
-    if (L) hipLaunchKernelGGL(k_export_live, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out6);
+    if (L && into_cache) hipLaunchKernelGGL(k_ids_from_records, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L);
+    if (L) hipLaunchKernelGGL(k_export_live, dim3(cdiv(L, kBlock)), dim3(kBlock), 0, s, P, L, out6, into_cache);
     return hipGetLastError();
 }
 

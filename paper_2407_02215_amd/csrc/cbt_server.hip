@@ -235,7 +235,7 @@ cbt_status evict(cbt_server s, SInst& I)
     uint32_t* rec = reinterpret_cast<uint32_t*>(P.vworld);
     const uint32_t n = (uint32_t)I.live;
     HIP_TRY(nullptr, cbtk::launch_enumerate(cbtk::single_launch(P, h->wk, nullptr), s->aux), "enumerate");
-    HIP_TRY(nullptr, cbtk::launch_export_live(P, n, rec, s->aux), "export live records");
+    HIP_TRY(nullptr, cbtk::launch_export_live(P, n, rec, s->aux, true), "export live records");
     const size_t bytes = sizeof(uint32_t) * 6 * (size_t)n;
     size_t off = 0;
     if (arena_alloc_top(s, bytes, &off)) {

@@ -364,3 +364,43 @@ def test_new_world_parameters_between_frames():
     batch.close()
     inst.close()
     member.close()
+
+
+def test_maximum_depth_pool_matches_reference():
+    """The deepest pool the library accepts (D = 30: 2^30 blocks, a 120 GB
+    workspace) against the reference at D = 20.  While the budget cuts
+    nothing (checked on the reference every frame), a frame does not depend
+    on the pool's size: the same decisions give the same owners, the same
+    first free blocks (all below 2^20) and the same records, so the live
+    records must agree exactly."""
+    import torch
+    mesh = I.mesh_grid(64)
+    small, big = 20, 30
+    orc = Oracle(mesh, small)
+    inst = cbt.Instance(mesh, big)
+    log(f"[max depth] D={big} workspace {inst.cap} blocks")
+    dev = torch.zeros(1 << big, dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(30)
+    for f in range(8):
+        ps, pm = (0.3, 0.1) if f < 5 else (0.05, 0.85)
+        dec = I.random_decisions(1 << small, int(rng.integers(1 << 30)), ps, pm)
+        dev[: 1 << small].copy_(torch.from_numpy(dec))
+        gst = inst.update_with_decisions(dev, stats=True)
+        ost = orc.frame(decisions=dec)
+        log(f"[max depth] frame {f} L={ost.live_before} -> {ost.live_after}")
+        assert ost.split_accepted == ost.split_requests and ost.merge_accepted == ost.merge_configs
+        for k in ("live_before", "split_requests", "split_accepted", "merge_configs", "merges_executed",
+                  "allocations", "live_after"):
+            assert gst[k] == getattr(ost, k), (f, k, gst[k], getattr(ost, k))
+    assert orc.live_count > 200000
+    assert inst.live_count() == orc.live_count
+    r = inst.export_live().cpu().numpy().view(np.uint32)
+    ids, tw, nx, pv = orc.pool()
+    live = np.nonzero(ids)[0]
+    assert np.array_equal(r[:, 0], live)
+    assert np.array_equal(r[:, 1].astype(np.uint64) | (r[:, 2].astype(np.uint64) << np.uint64(32)), ids[live])
+    for col, ref in ((3, tw), (4, nx), (5, pv)):
+        assert np.array_equal(r[:, col].view(np.int32), ref[live])
+    inst.close()
+    del dev, inst
+    torch.cuda.empty_cache()
