@@ -404,3 +404,44 @@ def test_maximum_depth_pool_matches_reference():
     inst.close()
     del dev, inst
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["cube", "qsphere", "open2"])
+def test_degenerate_frames_match_reference(name):
+    """Frames that change nothing and the round trip: every block KEEP
+    (no allocation, no free, the same pool), every block MERGE on the base
+    mesh (roots never merge: the same pool), four frames of SPLIT everywhere,
+    then MERGE everywhere until no merge executes, which returns the roots
+    (Section 2.3).  The GPU matches the reference slot by slot after every
+    frame."""
+    mesh = {"cube": I.mesh_cube(), "qsphere": I.mesh_quad_sphere(2, 0.5, 9),
+            "open2": I.mesh_two_triangles(False)}[name]
+    D = 12
+    inst = cbt.Instance(mesh, D)
+    orc = Oracle(mesh, D)
+    base = [a.copy() for a in inst.pool()]
+    roots = sorted(int(x) for x in base[0] if x)
+    for label, code in (("keep", 0), ("merge at the roots", 2)):
+        gst = inst.update_with_decisions(np.full(inst.cap, code, np.uint8), stats=True)
+        ost = orc.frame(decisions=np.full(orc.cap, code, np.uint8))
+        assert gst["allocations"] == ost.allocations == 0 and gst["frees"] == 0, label
+        for a, b in zip(inst.pool(), base):
+            assert np.array_equal(a, b), label
+        assert_same_state(inst, orc, label)
+    for f in range(4):
+        inst.update_with_decisions(np.ones(inst.cap, np.uint8))
+        orc.frame(decisions=np.ones(orc.cap, np.uint8))
+        assert_same_state(inst, orc, f"split {f}")
+        assert_same_tree(inst, orc, f"split {f}")
+    assert orc.live_count > 8 * mesh.H
+    for f in range(40):
+        gst = inst.update_with_decisions(np.full(inst.cap, 2, np.uint8), stats=True)
+        ost = orc.frame(decisions=np.full(orc.cap, 2, np.uint8))
+        assert gst["merges_executed"] == ost.merges_executed, f"merge {f}"
+        assert_same_state(inst, orc, f"merge {f}")
+        if ost.merges_executed == 0:
+            break
+    assert_same_tree(inst, orc, "after the round trip")
+    assert sorted(int(x) for x in inst.pool()[0] if x) == roots
+    assert inst.live_count() == mesh.H
+    inst.close()
