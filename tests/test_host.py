@@ -144,3 +144,41 @@ def test_tuned_schedule_lookup_by_depth_and_live_count(tmp_path):
     assert tune.lookup(18, t, 800000) == (512, 5)     # tie between 16 and 20: the deeper table
     assert tune.lookup(24, t, 40000) == (64, 10)
     assert tune.lookup(16, {}, 5) is None
+
+
+def test_trace_window_means_between_markers(tmp_path):
+    """Kernel-trace durations: only the launches strictly between the two
+    marker kernels count; per stage the mean launch duration and the
+    launches per timed frame (two reduction launches per frame)."""
+    from paper_2407_02215_amd import traffic as T
+    rows = []
+    d = 0
+
+    def add(name, ns):
+        nonlocal d
+        d += 1
+        rows.append({"Dispatch_Id": d, "Kernel_Name": name, "Start_Timestamp": 1000 * d,
+                     "End_Timestamp": 1000 * d + ns})
+
+    fill = "void cbtk::k_fill<false, float>(cbtk::Batch, cbtk::Inst)"
+    sub = "void cbtk::k_reduce_sub<false>(cbtk::Batch, cbtk::Inst)"
+    top = "void cbtk::k_reduce_top<false>(cbtk::Batch, cbtk::Inst)"
+    add(fill, 999_000)                   # before the timed pass
+    add("spin_kernel(long)", 5)
+    for k in range(4):
+        add(fill, 100_000 + 1000 * k)
+        add(sub, 4000)
+        add(top, 2000)
+    add("spin_kernel(long)", 5)
+    add(fill, 999_000)                   # after it
+    p = tmp_path / "trace_kernel_trace.csv"
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    tw = T.trace_window(str(p), 4)
+    assert tw["fill"]["launches_per_frame"] == 1.0
+    assert abs(tw["fill"]["mean_us"] - 101.5) < 1e-9
+    assert tw["reduce"]["launches_per_frame"] == 2.0
+    assert abs(tw["reduce"]["mean_us"] - 3.0) < 1e-9
+    assert abs(tw["reduce"]["us_per_frame"] - 6.0) < 1e-9
