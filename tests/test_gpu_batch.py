@@ -152,3 +152,40 @@ def test_persistent_wait_failure_is_reported():
         orc.frame(camera=cam)
     assert_same_state(inst, orc, "after the failure")
     inst.close()
+
+
+def test_batched_configuration_sampled_against_reference():
+    """The batched configuration at its full size and seed (128 closed sphere
+    meshes of 24 to 50,000 halfedges, depths 14-22, tuned schedules, a HIP
+    graph), 20 frames from the base meshes with one launch per stage and
+    with one persistent launch per frame; sampled members (the smallest and
+    deepest, the largest mesh, and three more) replayed on the CPU
+    reference with the same cameras and compared slot by slot."""
+    frames = 20
+    log("[batched configuration] building 128 workloads")
+    ws = I.batched_workloads(128, frames=64, seed=4, workers=1)
+    H = [w.mesh.H for w in ws]
+    sample = sorted({int(np.argmin(H)), int(np.argmax(H)), 0, 64, 127})
+    refs = {}
+    for i in sample:
+        w = ws[i]
+        o = Oracle(w.mesh, w.depth, w.lod)
+        for f in range(frames):
+            o.frame(camera=w.cameras[f])
+        refs[i] = o
+        log(f"[batched configuration] reference member {i}: H={w.mesh.H} D={w.depth} live {o.live_count}")
+    for persistent in (False, True):
+        members = [cbt.Instance(w.mesh, w.depth, w.lod, tuned=True) for w in ws]
+        batch = cbt.Batch(members, graph=True, persistent=persistent)
+        for f in range(frames):
+            batch.update([w.cameras[f] for w in ws])
+        batch.synchronize()
+        log(f"[batched configuration] persistent={persistent}: {frames} frames done")
+        for i in sample:
+            assert_same_state(members[i], refs[i], f"member {i} persistent={persistent}")
+            assert_same_tree(members[i], refs[i], f"member {i} persistent={persistent}")
+        batch.close()
+        for m in members:
+            m.close()
+        del members
+        torch.cuda.empty_cache()
