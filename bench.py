@@ -699,8 +699,10 @@ def main():
         print(json.dumps({"error": "the update runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
     if args.mode == "single":
+        # without arguments: the steady window past the pre-roll (terrain
+        # frames 40..239)
         args.steps = 200 if args.steps is None else args.steps
-        args.warmup = 5 if args.warmup is None else args.warmup
+        args.warmup = 0 if args.warmup is None else args.warmup
         out = run_single(args)
     elif args.mode == "converge":
         out = run_converge(args)
